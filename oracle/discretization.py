@@ -1,0 +1,220 @@
+"""All-at-once discretisation (paper Section 1), FP64, scipy.sparse.
+
+Notation follows the paper: M interior points per dimension, m = M**dims
+spatial unknowns, h = 1/(M+1), n time steps, tau = T/n, alpha = tau/sqrt(gamma)
+(eqn:matrix_A), theta in [1/2, 1] (theta = 1 backward Euler, 1/2 Crank-Nicolson).
+Finite differences: mass matrix M_m = I, stiffness K_m = -L_m where L_m is the
+(variable-coefficient) five-point Laplacian with homogeneous Dirichlet data.
+
+Vectors are time major: a block vector [v^(1); ...; v^(n)] is an (n, m) array,
+spatial index x1 fastest.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.linalg as sla
+
+
+@dataclass
+class Problem:
+    dims: int
+    M: int
+    n: int
+    T: float = 1.0
+    theta: float = 1.0
+    gamma: float = 1e-4
+    zeta: float = np.pi
+    a_face: Optional[np.ndarray] = None  # None => a == 1
+    s2_remedy: float = 1.0
+
+    def __post_init__(self):
+        if self.dims not in (1, 2):
+            raise ValueError("dims must be 1 or 2")
+        if not (0.5 <= self.theta <= 1.0):
+            raise ValueError("theta must lie in [1/2, 1] (Section 1)")
+        if self.gamma <= 0:
+            raise ValueError("gamma must be positive")
+
+    @property
+    def h(self):
+        return 1.0 / (self.M + 1)
+
+    @property
+    def m(self):
+        return self.M ** self.dims
+
+    @property
+    def tau(self):
+        return self.T / self.n
+
+    @property
+    def alpha(self):
+        return self.tau / np.sqrt(self.gamma)
+
+
+def stiffness(dims: int, M: int, a_face: Optional[np.ndarray] = None) -> sp.csr_matrix:
+    """K = -L_h: conservative five-point (three-point in 1D) finite differences.
+
+    (K u)_P = sum over the faces f of P of a_f (u_P - u_nb(f)) / h^2, with
+    u = 0 at boundary neighbours (homogeneous Dirichlet, eqn:heat).  a_f is the
+    coefficient at the face midpoint (a = 1 when a_face is None).  Face layout
+    as in datagen: 1D (M+1,); 2D ax (M, M+1) then ay (M+1, M).
+    """
+    h2 = (1.0 / (M + 1)) ** 2
+    rows, cols, vals = [], [], []
+    if dims == 1:
+        a = np.ones(M + 1) if a_face is None else np.asarray(a_face, dtype=np.float64)
+        assert a.shape == (M + 1,)
+        for i in range(M):  # node x_{i+1}; left face a[i], right face a[i+1]
+            diag = (a[i] + a[i + 1]) / h2
+            rows.append(i); cols.append(i); vals.append(diag)
+            if i > 0:
+                rows.append(i); cols.append(i - 1); vals.append(-a[i] / h2)
+            if i < M - 1:
+                rows.append(i); cols.append(i + 1); vals.append(-a[i + 1] / h2)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(M, M))
+    if a_face is None:
+        ax = np.ones((M, M + 1))
+        ay = np.ones((M + 1, M))
+    else:
+        a_face = np.asarray(a_face, dtype=np.float64)
+        assert a_face.shape == (2 * M * (M + 1),)
+        ax = a_face[: M * (M + 1)].reshape(M, M + 1)
+        ay = a_face[M * (M + 1):].reshape(M + 1, M)
+    idx = lambda i, j: j * M + i  # i = x1 index 0..M-1, j = x2 index 0..M-1
+    for j in range(M):
+        for i in range(M):
+            P = idx(i, j)
+            aw, ae = ax[j, i], ax[j, i + 1]      # west/east faces
+            as_, an = ay[j, i], ay[j + 1, i]     # south/north faces
+            rows.append(P); cols.append(P); vals.append((aw + ae + as_ + an) / h2)
+            if i > 0:
+                rows.append(P); cols.append(idx(i - 1, j)); vals.append(-aw / h2)
+            if i < M - 1:
+                rows.append(P); cols.append(idx(i + 1, j)); vals.append(-ae / h2)
+            if j > 0:
+                rows.append(P); cols.append(idx(i, j - 1)); vals.append(-as_ / h2)
+            if j < M - 1:
+                rows.append(P); cols.append(idx(i, j + 1)); vals.append(-an / h2)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(M * M, M * M))
+
+
+def B1(n: int) -> sp.csr_matrix:
+    """B_n^(1): unit lower bidiagonal, 1 on the diagonal, -1 below (Section 1)."""
+    return sp.diags([np.ones(n), -np.ones(n - 1)], [0, -1], format="csr")
+
+
+def B2(n: int, theta: float) -> sp.csr_matrix:
+    """B_n^(2): theta on the diagonal, 1 - theta below (Section 1)."""
+    return sp.diags([theta * np.ones(n), (1 - theta) * np.ones(n - 1)], [0, -1], format="csr")
+
+
+def Bn_closed_form(n: int, theta: float) -> np.ndarray:
+    """B_n = B^(1) (B^(2))^{-1} from its printed entries (Section 1, after eqn:matrix_T).
+
+    Lower triangular Toeplitz: 1/theta on the diagonal, -1/theta^2 on the first
+    subdiagonal and -(theta-1)^{k-1}/theta^{k+1} on the k-th subdiagonal, k >= 2.
+    """
+    col = np.zeros(n)
+    col[0] = 1.0 / theta
+    for k in range(1, n):
+        col[k] = -((theta - 1.0) ** (k - 1)) / theta ** (k + 1)
+    return sla.toeplitz(col, np.zeros(n))
+
+
+def assemble_Atilde(prob: Problem) -> sp.csr_matrix:
+    """The 2nm x 2nm matrix of eqn:matrix_A_before with M_m = I, K_m = K."""
+    n, m, tau, th, gam = prob.n, prob.m, prob.tau, prob.theta, prob.gamma
+    K = stiffness(prob.dims, prob.M, prob.a_face)
+    I = sp.identity(m, format="csr")
+    b1, b2 = B1(n), B2(n, th)
+    A11 = tau * sp.kron(b2, I)
+    A12 = sp.kron(b1.T, I) + tau * sp.kron(b2.T, K)
+    A21 = sp.kron(b1, I) + tau * sp.kron(b2, K)
+    A22 = -(tau / gam) * sp.kron(b2.T, I)
+    return sp.bmat([[A11, A12], [A21, A22]], format="csr")
+
+
+class AllAtOnce:
+    """Matrix-free applies of A_tilde, A (symmetric) and A_hat (nonsymmetric).
+
+    A_tilde [y; p] uses the Kronecker identity (B kron C) vec(X) = vec(B X C^T)
+    for time-major (n, m) arrays X; tests pin it against assemble_Atilde.
+    A and A_hat are reached from A_tilde by the change of variables of
+    eqn:main_system: x1 = sqrt(gamma) B^(2) y, x2 = (B^(2))^T p, second block
+    row scaled by sqrt(gamma); A_hat is A with its block rows swapped
+    (eqn:matrix_A_hat).
+    """
+
+    def __init__(self, prob: Problem):
+        self.prob = prob
+        self.K = stiffness(prob.dims, prob.M, prob.a_face)
+        n = prob.n
+        self.b1 = B1(n).toarray()
+        self.b2 = B2(n, prob.theta).toarray()
+
+    def Atilde(self, y: np.ndarray, p: np.ndarray):
+        """Return the two block rows of A_tilde [y; p] for (n, m) arrays y, p."""
+        pr, K = self.prob, self.K
+        tau, gam = pr.tau, pr.gamma
+        b1, b2 = self.b1, self.b2
+        KY = (K @ y.T).T  # I_n kron K applied to y
+        KP = (K @ p.T).T
+        r1 = tau * (b2 @ y) + b1.T @ p + tau * (b2.T @ KP)
+        r2 = b1 @ y + tau * (b2 @ KY) - (tau / gam) * (b2.T @ p)
+        return r1, r2
+
+    def to_yp(self, x1: np.ndarray, x2: np.ndarray):
+        """[x1; x2] = [sqrt(gamma) y_tilde; p_tilde] -> (y, p)."""
+        g = np.sqrt(self.prob.gamma)
+        y = sla.solve_triangular(self.b2, x1 / g, lower=True)
+        p = sla.solve_triangular(self.b2.T, x2, lower=False)
+        return y, p
+
+    def A(self, x: np.ndarray) -> np.ndarray:
+        """Symmetric operator of eqn:matrix_A applied to a flat 2nm vector."""
+        n, m = self.prob.n, self.prob.m
+        x1 = x[: n * m].reshape(n, m)
+        x2 = x[n * m:].reshape(n, m)
+        y, p = self.to_yp(x1, x2)
+        r1, r2 = self.Atilde(y, p)
+        return np.concatenate([r1.ravel(), np.sqrt(self.prob.gamma) * r2.ravel()])
+
+    def Ahat(self, x: np.ndarray) -> np.ndarray:
+        """Nonsymmetric operator of eqn:matrix_A_hat (block rows of A swapped)."""
+        nm = self.prob.n * self.prob.m
+        r = self.A(x)
+        return np.concatenate([r[nm:], r[:nm]])
+
+
+def rhs_tilde(prob: Problem, f: np.ndarray, g: np.ndarray, y0: np.ndarray):
+    """f_tilde and g_tilde of Section 1 (M_m = I) from samples at t_0..t_n.
+
+    f, g: (n+1, m) arrays at time levels 0..n; y0: (m,).  Returns (g_t, f_t),
+    each (n, m).
+    """
+    n, tau, th = prob.n, prob.tau, prob.theta
+    K = stiffness(prob.dims, prob.M, prob.a_face)
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    y0 = np.asarray(y0, dtype=np.float64)
+    ft = np.empty((n, prob.m))
+    gt = np.empty((n, prob.m))
+    for k in range(1, n + 1):  # block row k uses levels k-1 and k
+        ft[k - 1] = th * tau * f[k] + (1 - th) * tau * f[k - 1]
+        gt[k - 1] = tau * (th * g[k - 1] + (1 - th) * g[k])
+    ft[0] += y0 - (1 - th) * tau * (K @ y0)
+    gt[0] -= tau * (1 - th) * y0
+    return gt, ft
+
+
+def transformed_rhs(prob: Problem, gt: np.ndarray, ft: np.ndarray, symmetric: bool) -> np.ndarray:
+    """[g; sqrt(gamma) f] (eqn:main_system) or [sqrt(gamma) f; g] (eqn:main_system_nonsym)."""
+    sg = np.sqrt(prob.gamma)
+    if symmetric:
+        return np.concatenate([gt.ravel(), sg * ft.ravel()])
+    return np.concatenate([sg * ft.ravel(), gt.ravel()])

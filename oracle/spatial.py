@@ -1,0 +1,46 @@
+"""Spatial eigenbasis of -L_h for a = 1 (Section 3.4, fast sine transform).
+
+Textbook facts for the three-point / five-point Dirichlet Laplacian on a
+uniform grid with h = 1/(M+1): the orthonormal sine matrix
+U[i, j] = sqrt(2/(M+1)) sin(i j pi/(M+1)), i, j = 1..M, is symmetric and its
+own inverse, and U (-L_h) U = diag(mu) with mu_j = 4 h^-2 sin^2(j pi h / 2)
+(1D); in 2D the basis is U kron U with eigenvalues mu_j1 + mu_j2.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def sine_matrix(M: int) -> np.ndarray:
+    i = np.arange(1, M + 1)
+    return np.sqrt(2.0 / (M + 1)) * np.sin(np.outer(i, i) * np.pi / (M + 1))
+
+
+def laplacian_eigenvalues(M: int) -> np.ndarray:
+    """mu_j, j = 1..M (1D)."""
+    h = 1.0 / (M + 1)
+    j = np.arange(1, M + 1)
+    return 4.0 / h ** 2 * np.sin(j * np.pi * h / 2) ** 2
+
+
+def eigenvalues(dims: int, M: int) -> np.ndarray:
+    """Eigenvalues of -L_h in the order of the (x2, x1) row-major grid index."""
+    mu = laplacian_eigenvalues(M)
+    if dims == 1:
+        return mu
+    return (mu[:, None] + mu[None, :]).ravel()  # [j2][j1]
+
+
+def sine_transform(dims: int, M: int, X: np.ndarray) -> np.ndarray:
+    """Apply U (1D) or U kron U (2D) to every row of X (rows = spatial vectors).
+
+    X has shape (..., M**dims); the transform is its own inverse.
+    """
+    U = sine_matrix(M)
+    if dims == 1:
+        return X @ U.T
+    shp = X.shape
+    Y = X.reshape(-1, M, M)            # [., x2, x1]
+    Y = Y @ U.T                        # along x1
+    Y = np.matmul(U, Y)                # along x2
+    return Y.reshape(shp)

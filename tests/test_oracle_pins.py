@@ -1,0 +1,399 @@
+"""Pins for the CPU oracle: each check ties an oracle function to something
+other than itself (a closed form printed in the paper, a theorem's spectral
+statement, a dense definition at tiny size, a textbook identity, the printed
+tables, or a sparse direct solve)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import datagen
+from oracle import circulant, spatial, krylov, solver
+from oracle.discretization import (Problem, AllAtOnce, stiffness, B1, B2, Bn_closed_form,
+                                   assemble_Atilde, rhs_tilde)
+from oracle.precond import (FastPreconditioner, dense_PS, dense_absPS, dense_PMS, dense_A,
+                            dense_Ahat, dense_absA)
+from conftest import load_golden
+
+ZETAS = [np.pi, 1.0, 0.1, 2.5]
+THETAS = [1.0, 0.5, 0.75]
+
+
+# --------------------------------------------------------------------------
+# P1 / P3: omega-circulant factors, transform, eigenvalue tables
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 5, 8, 16])
+@pytest.mark.parametrize("zeta", ZETAS + [0.0])
+@pytest.mark.parametrize("theta", THETAS)
+def test_transform_diagonalises_omega_circulants(n, zeta, theta):
+    for S in (circulant.S1(n, zeta), circulant.S2(n, theta, zeta)):
+        d, off = circulant.similarity_diagonal(S, zeta)
+        assert off < 1e-12 * max(1.0, np.abs(d).max())
+
+
+@pytest.mark.parametrize("n", [4, 7, 16])
+@pytest.mark.parametrize("zeta", ZETAS)
+def test_circulants_differ_from_toeplitz_factors_by_rank_one(n, zeta):
+    # Proof of the GMRES proposition: rank(S^(j) - B^(j)) <= 1
+    for S, B in ((circulant.S1(n, zeta), B1(n).toarray()),
+                 (circulant.S2(n, 0.5, zeta), B2(n, 0.5).toarray())):
+        sv = np.linalg.svd(S - B, compute_uv=False)
+        assert np.sum(sv > 1e-12) == 1
+
+
+@pytest.mark.parametrize("n", [4, 6, 16, 64])
+@pytest.mark.parametrize("zeta", ZETAS)
+@pytest.mark.parametrize("theta", THETAS)
+def test_eigenvalues_match_lemma_closed_form(n, zeta, theta):
+    l1, l2, lam = circulant.eigen_tables(n, theta, zeta)
+    closed = circulant.lemma_eigenvalues(n, theta, zeta)
+    # same multiset (the paper's index order differs from the transform order)
+    a = np.sort_complex(np.round(lam, 10))
+    b = np.sort_complex(np.round(closed, 10))
+    np.testing.assert_allclose(a, b, atol=1e-9)
+    # eigenvalues of the dense S_n agree too
+    ev = np.linalg.eigvals(circulant.Sn(n, theta, zeta))
+    for x in lam:
+        assert np.min(np.abs(ev - x)) < 1e-8 * max(1, abs(x))
+    # Hermitian part: lemma on S_n^* + S_n (PSD, closed form)
+    S = circulant.Sn(n, theta, zeta)
+    h = np.linalg.eigvalsh(S + S.conj().T)
+    assert h.min() > -1e-10
+    np.testing.assert_allclose(np.sort(h), np.sort(circulant.lemma_hermitian_part(n, theta, zeta)),
+                               atol=1e-9)
+
+
+def test_singular_S2_remedy_is_rank_one():
+    # theta = 1/2, zeta = pi, n odd: S^(2) has a zero eigenvalue (remark)
+    n, theta, zeta = 7, 0.5, np.pi
+    l1, l2, lam = circulant.eigen_tables(n, theta, zeta, s2_remedy=1.0)
+    s2 = circulant.S2(n, theta, zeta)
+    assert np.min(np.abs(np.linalg.eigvals(s2))) < 1e-12
+    s2r = circulant.inverse_transform(n, zeta) @ np.diag(l2) @ circulant.transform(n, zeta)
+    sv = np.linalg.svd(s2r - s2, compute_uv=False)
+    assert np.sum(sv > 1e-12) == 1
+    with pytest.raises(ZeroDivisionError):
+        circulant.eigen_tables(n, theta, zeta, s2_remedy=0.0)
+
+
+# --------------------------------------------------------------------------
+# P2: time operators and the all-at-once matrices
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("theta", THETAS)
+def test_Bn_closed_form(theta):
+    n = 9
+    b1, b2 = B1(n).toarray(), B2(n, theta).toarray()
+    Bn = Bn_closed_form(n, theta)
+    np.testing.assert_allclose(b1 @ np.linalg.inv(b2), Bn, atol=1e-12)
+    np.testing.assert_allclose(np.linalg.inv(b2) @ b1, Bn, atol=1e-12)
+
+
+@pytest.mark.parametrize("dims,M,n", [(1, 5, 6), (2, 3, 4)])
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("coeff", ["const", "sin"])
+def test_symmetric_form_matches_block_formula(dims, M, n, theta, coeff):
+    a_face = None if coeff == "const" else datagen.sinusoidal_a(dims, M)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-3, a_face=a_face)
+    K = stiffness(dims, M, a_face).toarray()
+    Bn = Bn_closed_form(n, theta)
+    Im, In = np.eye(pr.m), np.eye(n)
+    T = np.kron(Bn, Im) + pr.tau * np.kron(In, K)                 # eqn:matrix_T
+    A = np.block([[pr.alpha * np.eye(n * pr.m), T.T], [T, -pr.alpha * np.eye(n * pr.m)]])
+    Ahat = np.block([[T, -pr.alpha * np.eye(n * pr.m)], [pr.alpha * np.eye(n * pr.m), T.T]])
+    np.testing.assert_allclose(dense_A(pr), A, atol=1e-10 * np.abs(A).max())
+    np.testing.assert_allclose(dense_Ahat(pr), Ahat, atol=1e-10 * np.abs(A).max())
+    assert np.allclose(A, A.T)
+
+
+def test_matrix_free_Atilde_matches_assembled():
+    pr = Problem(dims=2, M=4, n=5, theta=0.5, gamma=1e-2, a_face=datagen.sinusoidal_a(2, 4))
+    op = AllAtOnce(pr)
+    At = assemble_Atilde(pr)
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal((pr.n, pr.m))
+    p = rng.standard_normal((pr.n, pr.m))
+    r1, r2 = op.Atilde(y, p)
+    ref = At @ np.concatenate([y.ravel(), p.ravel()])
+    np.testing.assert_allclose(np.concatenate([r1.ravel(), r2.ravel()]), ref, rtol=1e-13, atol=1e-10)
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5, 0.6])
+@pytest.mark.parametrize("dims", [1, 2])
+def test_direct_solve_reproduces_theta_scheme(theta, dims):
+    """Manufacture a discrete solution of the two-level scheme (Section 1,
+    equations preceding eqn:main_system_before), derive f and g from it, and
+    check that rhs_tilde + A_tilde return it."""
+    M, n, gamma = (6, 7, 1e-2)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma,
+                 a_face=datagen.sinusoidal_a(dims, M))
+    K = stiffness(dims, M, pr.a_face).toarray()
+    tau, th, m = pr.tau, theta, pr.m
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((n + 1, m))
+    p = rng.standard_normal((n + 1, m))
+    p[n] = 0.0
+    f = np.zeros((n + 1, m)); g = np.zeros((n + 1, m))
+    f[0] = rng.standard_normal(m)
+    for k in range(n):  # state equation, solved for f^(k+1)
+        lhs = (y[k + 1] - y[k]) / tau + K @ (th * y[k + 1] + (1 - th) * y[k])
+        rest = (1 - th) * f[k] + (th * p[k] + (1 - th) * p[k + 1]) / gamma
+        f[k + 1] = (lhs - rest) / th
+    g[n] = rng.standard_normal(m)
+    for k in range(n - 1, -1, -1):  # adjoint equation, solved for g^(k)
+        lhs = -(p[k + 1] - p[k]) / tau + K @ (th * p[k] + (1 - th) * p[k + 1])
+        rest = (1 - th) * g[k + 1] - th * y[k + 1] - (1 - th) * y[k]
+        g[k] = (lhs - rest) / th
+    ys, ps = solver.direct_solve(pr, f, g, y[0])
+    np.testing.assert_allclose(ys, y[1:], atol=1e-9)
+    np.testing.assert_allclose(ps, p[:-1], atol=1e-9)
+
+
+def test_variable_stiffness_is_second_order():
+    # K u ~ -(a u')' for smooth u, a: error must fall like h^2 (face placement pin)
+    def err(M):
+        h = 1.0 / (M + 1)
+        x = datagen.nodes(M)
+        a = lambda s: 1 + 0.5 * np.sin(2 * np.pi * s)
+        da = lambda s: 0.5 * 2 * np.pi * np.cos(2 * np.pi * s)
+        u = np.sin(np.pi * x) * x
+        du = np.pi * np.cos(np.pi * x) * x + np.sin(np.pi * x)
+        d2u = -np.pi ** 2 * np.sin(np.pi * x) * x + 2 * np.pi * np.cos(np.pi * x)
+        exact = -(da(x) * du + a(x) * d2u)
+        K = stiffness(1, M, datagen.face_coefficients(a, 1, M))
+        return np.max(np.abs(K @ u - exact))
+    e1, e2 = err(31), err(63)
+    assert 3.5 < e1 / e2 < 4.5
+
+    def err2(M):
+        x = datagen.nodes(M)
+        X2, X1 = np.meshgrid(x, x, indexing="ij")
+        a = lambda s1, s2: 1 + 0.5 * np.sin(2 * np.pi * s1) * np.sin(2 * np.pi * s2)
+        u = np.sin(np.pi * X1) * np.sin(2 * np.pi * X2)
+        # -(div a grad u) analytically
+        ux = np.pi * np.cos(np.pi * X1) * np.sin(2 * np.pi * X2)
+        uy = 2 * np.pi * np.sin(np.pi * X1) * np.cos(2 * np.pi * X2)
+        uxx = -np.pi ** 2 * u
+        uyy = -4 * np.pi ** 2 * u
+        ax = np.pi * np.cos(2 * np.pi * X1) * np.sin(2 * np.pi * X2)
+        ay = np.pi * np.sin(2 * np.pi * X1) * np.cos(2 * np.pi * X2)
+        exact = -(ax * ux + ay * uy + a(X1, X2) * (uxx + uyy))
+        K = stiffness(2, M, datagen.face_coefficients(a, 2, M))
+        return np.max(np.abs(K @ u.ravel() - exact.ravel()))
+    f1, f2 = err2(15), err2(31)
+    assert 3.5 < f1 / f2 < 4.5
+
+
+# --------------------------------------------------------------------------
+# P4: sine basis
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M", [1, 4, 7, 15])
+def test_sine_basis(M):
+    U = spatial.sine_matrix(M)
+    np.testing.assert_allclose(U, U.T, atol=1e-14)
+    np.testing.assert_allclose(U @ U, np.eye(M), atol=1e-13)
+    K1 = stiffness(1, M).toarray()
+    np.testing.assert_allclose(U @ K1 @ U, np.diag(spatial.eigenvalues(1, M)), atol=1e-10 * (M + 1) ** 2)
+    if M <= 7:
+        U2 = np.kron(U, U)
+        K2 = stiffness(2, M).toarray()
+        np.testing.assert_allclose(U2 @ K2 @ U2, np.diag(spatial.eigenvalues(2, M)),
+                                   atol=1e-10 * (M + 1) ** 2)
+        X = np.random.default_rng(1).standard_normal((3, M * M))
+        np.testing.assert_allclose(spatial.sine_transform(2, M, X), X @ U2.T, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# P5: three-step applies vs dense inverses of the definitions
+# --------------------------------------------------------------------------
+
+SMALL = [(1, 5, 6), (2, 3, 4), (1, 3, 8)]
+
+
+@pytest.mark.parametrize("dims,M,n", SMALL)
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("zeta", [np.pi, 1.0])
+@pytest.mark.parametrize("kind,coeff", [("ps", "const"), ("abs_ps", "const"), ("pms", "const"),
+                                        ("ps", "sin"), ("pms", "sin")])
+def test_fast_apply_matches_dense_inverse(dims, M, n, theta, zeta, kind, coeff):
+    a_face = None if coeff == "const" else datagen.sinusoidal_a(dims, M)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-3, zeta=zeta, a_face=a_face)
+    dense = {"ps": dense_PS, "abs_ps": dense_absPS, "pms": dense_PMS}[kind](pr)
+    v = np.random.default_rng(3).standard_normal(2 * n * pr.m)
+    ref = np.linalg.solve(dense, v.astype(complex))
+    got = FastPreconditioner(pr, kind).apply(v, return_complex=True)
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    if zeta == np.pi:  # real preconditioners for zeta = pi
+        assert np.abs(got.imag).max() < 1e-11 * np.abs(got).max()
+
+
+def test_fast_apply_with_remedied_S2():
+    pr = Problem(dims=1, M=4, n=5, theta=0.5, gamma=1e-2, zeta=np.pi, s2_remedy=1.0)
+    v = np.random.default_rng(4).standard_normal(2 * pr.n * pr.m)
+    for kind, dense in (("ps", dense_PS), ("abs_ps", dense_absPS), ("pms", dense_PMS)):
+        ref = np.linalg.solve(dense(pr), v.astype(complex))
+        got = FastPreconditioner(pr, kind).apply(v, return_complex=True)
+        np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------
+# P6-P9: the paper's spectral statements
+# --------------------------------------------------------------------------
+
+SPEC = [(1, 4, 8, 1.0), (1, 4, 8, 0.5), (2, 2, 6, 0.5), (2, 2, 6, 1.0)]
+
+
+@pytest.mark.parametrize("dims,M,n,theta", SPEC)
+@pytest.mark.parametrize("zeta", [np.pi, 1.0])
+def test_PS_minus_Ahat_low_rank(dims, M, n, theta, zeta):
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-2, zeta=zeta)
+    D = dense_PS(pr) - dense_Ahat(pr)
+    sv = np.linalg.svd(D, compute_uv=False)
+    assert np.sum(sv > 1e-9 * sv.max()) <= 4 * pr.m
+    # singular values of P_S^{-1} A_hat cluster at 1: at most 4m away from 1
+    s = np.linalg.svd(np.linalg.solve(dense_PS(pr), dense_Ahat(pr)), compute_uv=False)
+    assert np.sum(np.abs(s - 1) > 1e-8) <= 4 * pr.m
+
+
+@pytest.mark.parametrize("dims,M,n,theta", SPEC)
+def test_ideal_preconditioner_symmetric_orthogonal(dims, M, n, theta):
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-2)
+    A = dense_A(pr)
+    Q = np.linalg.solve(dense_absA(pr), A)
+    np.testing.assert_allclose(Q, Q.T, atol=1e-10)
+    np.testing.assert_allclose(Q @ Q.T, np.eye(A.shape[0]), atol=1e-10)
+    ev = np.linalg.eigvalsh(A)
+    assert np.sum(ev > 0) == n * pr.m and np.sum(ev < 0) == n * pr.m
+
+
+@pytest.mark.parametrize("dims,M,n,theta", SPEC)
+def test_absPS_clusters_at_plus_minus_one(dims, M, n, theta):
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-2)
+    ev = np.linalg.eigvals(np.linalg.solve(dense_absPS(pr), dense_A(pr)))
+    assert np.abs(ev.imag).max() < 1e-8
+    outliers = np.sum(np.minimum(np.abs(ev - 1), np.abs(ev + 1)) > 1e-8)
+    assert outliers <= 8 * pr.m
+
+
+@pytest.mark.parametrize("dims,M,n,theta", SPEC + [(1, 15, 16, 0.5)])
+@pytest.mark.parametrize("gamma", [1e-10, 1e-6, 1e-2])
+def test_PMS_spectrally_equivalent_to_absPS(dims, M, n, theta, gamma):
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma)
+    ev = np.linalg.eigvals(np.linalg.solve(dense_PMS(pr), dense_absPS(pr)))
+    assert np.abs(ev.imag).max() < 1e-8
+    lo, hi = ev.real.min(), ev.real.max()
+    assert lo >= 1 / np.sqrt(2) - 1e-10
+    assert hi <= (1.0 if theta == 0.5 else np.sqrt(2)) + 1e-10
+
+
+# --------------------------------------------------------------------------
+# Krylov solvers: textbook special cases
+# --------------------------------------------------------------------------
+
+def test_minres_distinct_eigenvalues():
+    rng = np.random.default_rng(2)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.repeat([-3.0, -1.0, 2.0, 5.0], 10)
+    A = (Q * lam) @ Q.T
+    b = rng.standard_normal(40)
+    d = 1.0 + rng.random(40)  # SPD diagonal preconditioner
+    x, it, _ = krylov.minres(lambda v: A @ v, b, lambda v: v / d, tol=1e-12, maxit=200)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-9)
+    x, it, _ = krylov.minres(lambda v: A @ v, b, lambda v: v, tol=1e-12)
+    assert it <= 5  # four distinct eigenvalues (+1 for rounding)
+
+
+def test_gmres_random_nonsymmetric():
+    rng = np.random.default_rng(3)
+    A = np.eye(30) * 12 + rng.standard_normal((30, 30))
+    b = rng.standard_normal(30)
+    x, it, _ = krylov.gmres(lambda v: A @ v, b, lambda v: v / 12, tol=1e-12, restart=10, maxit=300)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-9)
+    x, it, _ = krylov.gmres(lambda v: A @ v, b, lambda v: v, tol=1e-13, restart=40, maxit=40)
+    assert it <= 30
+
+
+# --------------------------------------------------------------------------
+# P11 / P12: end to end
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["gmres_ps", "minres_abs_ps", "minres_pms"])
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("dims,M,n", [(1, 15, 16), (2, 7, 8)])
+def test_krylov_solution_matches_direct_solve(method, theta, dims, M, n):
+    d = datagen.config_problem(dims, M, n, seed=7, noise_sigma=1e-3)
+    d["y0"] = datagen.smooth_modes(11, dims, M, 1, 1.0)[0]
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=1e-4)
+    out = solver.solve(pr, d["f"], d["g"], d["y0"], method, tol=1e-12, maxit=400)
+    y, p = solver.direct_solve(pr, d["f"], d["g"], d["y0"])
+    assert out["relres"] <= 1e-12
+    sc = max(np.abs(y).max(), np.abs(p).max())
+    np.testing.assert_allclose(out["y"], y, atol=1e-9 * sc)
+    np.testing.assert_allclose(out["p"], p, atol=1e-9 * sc)
+
+
+def test_variable_coefficient_solve_matches_direct():
+    d = datagen.config_problem(2, 7, 8, seed=3, noise_sigma=1e-3, coeff="sin")
+    pr = Problem(dims=2, M=7, n=8, theta=0.5, gamma=1e-4, a_face=d["a_face"])
+    y, p = solver.direct_solve(pr, d["f"], d["g"], d["y0"])
+    for method in ("gmres_ps", "minres_pms"):
+        out = solver.solve(pr, d["f"], d["g"], d["y0"], method, tol=1e-12, maxit=400)
+        sc = max(np.abs(y).max(), np.abs(p).max())
+        np.testing.assert_allclose(out["y"], y, atol=1e-9 * sc)
+        np.testing.assert_allclose(out["p"], p, atol=1e-9 * sc)
+
+
+def _table(name, hexp):
+    return [r for r in load_golden(name) if int(r[1]) == hexp]
+
+
+@pytest.mark.parametrize("row", _table("table1_example1_cn.txt", 5), ids=lambda r: f"gamma={r[0]}")
+def test_table1_h5(row):
+    gamma, e = float(row[0]), int(row[1])
+    M = 2 ** e - 1
+    n = 2 ** e
+    d = datagen.example1(M, n)
+    pr = Problem(dims=2, M=M, n=n, theta=0.5, gamma=gamma, zeta=np.pi)
+    assert 2 * n * pr.m == int(row[2])
+    g = solver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps")
+    assert g["iters"] == int(row[3])
+    eh = solver.e_h(pr, g["y"], g["p"], d["y_exact"], d["p_exact"])
+    assert float(f"{eh:.3g}") == pytest.approx(float(row[4]), rel=1e-9)
+    mr = solver.solve(pr, d["f"], d["g"], d["y0"], "minres_abs_ps")
+    assert abs(mr["iters"] - int(row[5])) <= 1
+    ehm = solver.e_h(pr, mr["y"], mr["p"], d["y_exact"], d["p_exact"])
+    assert ehm <= float(row[6]) * 1.005
+
+
+@pytest.mark.parametrize("row", _table("table3_example2_cn.txt", 5), ids=lambda r: f"gamma={r[0]}")
+def test_table3_h5_gmres(row):
+    gamma, e = float(row[0]), int(row[1])
+    M, n = 2 ** e - 1, 2 ** e
+    d = datagen.example2(M, n, gamma)
+    pr = Problem(dims=2, M=M, n=n, theta=0.5, gamma=gamma, zeta=np.pi, a_face=d["a_face"])
+    g = solver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps")
+    assert g["iters"] == int(row[3])
+    eh = solver.e_h(pr, g["y"], g["p"], d["y_exact"], d["p_exact"])
+    assert float(f"{eh:.3g}") == pytest.approx(float(row[4]), rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Lemma 2.3 decoupling of the per-frequency 2x2 block (variable a, P_S):
+# the closed-form factors used by the fast solver are checked here against
+# a dense 2x2 eigen-solve (a check of the reading, not of the oracle).
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("zeta", [np.pi, 1.0])
+def test_lemma_decoupling(theta, zeta):
+    n, alpha = 8, 0.37
+    _, _, lam = circulant.eigen_tables(n, theta, zeta)
+    for l in lam:
+        G = np.array([[l, -alpha], [alpha, np.conj(l)]])
+        s = np.sqrt(l.imag ** 2 + alpha ** 2)
+        d1 = l.real + 1j * s
+        mu = -(1j / alpha) * (s - l.imag)
+        W = np.array([[1, mu], [mu, 1]])
+        D = np.diag([d1, np.conj(d1)])
+        np.testing.assert_allclose(W @ D @ np.linalg.inv(W), G, atol=1e-12)
