@@ -1,0 +1,187 @@
+/*
+ * wc.h -- C ABI of the MI355X (gfx950) block omega-circulant solver library.
+ *
+ * The library solves the all-at-once theta-method optimality system of the
+ * parabolic tracking problem of Fung & Hon, "Block omega-circulant
+ * preconditioners for parabolic optimal control problems":
+ *
+ *   min 1/2 ||y - g||^2 + gamma/2 ||u||^2  s.t.  y_t - div(a grad y) = f + u,
+ *   y = 0 on the boundary, y(0) = y0                     (Section 1, eqn:heat)
+ *
+ * discretised with the theta-method in time (theta = 1 backward Euler,
+ * theta = 1/2 Crank-Nicolson) and conservative finite differences in space
+ * (M = I, K = -L_h), on the unit interval or square with h = 1/(M+1),
+ * tau = T/n (Section 1, eqn:main_system_before).  The unknown of the
+ * transformed systems is x = [sqrt(gamma) y_tilde; p_tilde] (eqn:main_system).
+ *
+ * Methods (Section 4 naming):
+ *   WC_MINRES_ABS_PS : MINRES on A (eqn:matrix_A) with |P_S| (eqn:matrix_P)
+ *   WC_MINRES_PMS    : MINRES on A with P_MS (eqn:matrix_P_MS)
+ *   WC_GMRES_PS      : right-preconditioned GMRES(restart) on A_hat
+ *                      (eqn:matrix_A_hat) with P_S (eqn:matrix_P_GMRES)
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers to FP64 data owned by the caller
+ *    (the library never frees them).  Host pointers are named *_host.
+ *  - Space-time arrays are time major: element (k, s) at k*m + s, with the
+ *    spatial index s = x2*M + x1 (x1 fastest), m = M^dims.
+ *  - A "system vector" has 2*n*m doubles: block row 1 then block row 2, each
+ *    an (n, m) time-major array (time slices 1..n).
+ *  - Work is enqueued on the plan's HIP stream (hipStream_t passed as void*;
+ *    NULL = the default stream).  wc_rhs, wc_matvec, wc_pc_apply and
+ *    wc_recover are asynchronous; wc_krylov and wc_solve return after the
+ *    solve has finished (they synchronise the plan's stream).
+ *  - Every call returns a wc_status and never aborts.  Arguments are checked
+ *    before any launch.  A plan is not thread safe: calls on one plan must
+ *    be serialised by the caller.
+ */
+#ifndef WC_H_
+#define WC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WC_OK = 0,
+  WC_E_ARG = 1,          /* invalid argument (sizes, theta, gamma, NULL pointer, ...) */
+  WC_E_SINGULAR_S2 = 2,  /* S_n^(2) singular and s2_remedy == 0 (remark in Section 1) */
+  WC_E_NOMEM = 3,        /* device allocation failed */
+  WC_E_MAXIT = 4,        /* maxit reached; the last iterate is still written */
+  WC_E_BREAKDOWN = 5,    /* Krylov breakdown (non-positive preconditioned norm) */
+  WC_E_NONFINITE = 6,    /* NaN/Inf met in a Krylov scalar */
+  WC_E_CANCELLED = 7,    /* request cancelled (server) */
+  WC_E_ADMISSION = 8,    /* request larger than the server's memory budget */
+  WC_E_UNSUPPORTED = 9,  /* valid problem outside what the GPU path implements */
+  WC_E_HIP = 10,         /* a HIP runtime call failed */
+  WC_E_INTERNAL = 11
+} wc_status;
+
+typedef enum { WC_MINRES_ABS_PS = 0, WC_MINRES_PMS = 1, WC_GMRES_PS = 2 } wc_method;
+
+/* Arithmetic of the preconditioner apply.  The Krylov recurrence, inner
+ * products, the all-at-once matvec and all tables are FP64 in both modes. */
+typedef enum { WC_FP64 = 0, WC_MIXED = 1 } wc_precision;
+
+/* The discrete problem (Section 1 and the Section 4 protocol). */
+typedef struct {
+  int dims;           /* 1 or 2 */
+  int M;              /* interior points per dimension; h = 1/(M+1); m = M^dims */
+  int n;              /* time steps; tau = T/n */
+  double T;           /* final time, > 0 */
+  double theta;       /* 1/2 <= theta <= 1 (Section 1) */
+  double gamma;       /* regularisation, > 0 */
+  double zeta;        /* omega = exp(i zeta); the paper's experiments use pi */
+  double s2_remedy;   /* value replacing a zero eigenvalue of S_n^(2); 0 => error */
+  const double *a_face_host;  /* HOST pointer or NULL (a == 1).  Diffusion
+                         coefficient at cell-face midpoints: 1D M+1 values at
+                         (i+1/2)h; 2D faces normal to x1 as an (M, M+1) array
+                         [x2 node][x1 face] followed by faces normal to x2 as
+                         an (M+1, M) array [x2 face][x1 node].  Copied at plan
+                         creation. */
+} wc_problem;
+
+typedef struct {
+  int method;         /* wc_method */
+  int precision;      /* wc_precision */
+  double tol;         /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual) */
+  int maxit;          /* total Krylov iteration cap */
+  int restart;        /* GMRES restart length (1..64) */
+  int flexible;       /* GMRES: store preconditioned basis (forced on for WC_MIXED) */
+  int mg_max_cycles;  /* multigrid V-cycles per spatial solve (variable a) */
+  double mg_tol;      /* multigrid relative residual target (variable a) */
+} wc_opts;
+
+typedef struct {
+  int status;         /* wc_status of the solve */
+  int iters;          /* Krylov iterations */
+  int restarts;       /* GMRES cycles / MINRES true-residual restarts */
+  double relres;      /* explicit ||b - A x||_2 / ||b||_2 at exit (FP64) */
+  double relres_est;  /* recurrence estimate at exit */
+  double ms;          /* wall time of the Krylov solve */
+  int mg_cycles_max;  /* largest V-cycle count of any spatial solve (variable a) */
+} wc_info;
+
+typedef struct wc_plan wc_plan;
+
+/* Human-readable name of a status code (static string). */
+const char *wc_status_str(int status);
+
+/* Defaults: GMRES_PS, FP64, tol 1e-8, maxit 500, restart 30, flexible 0,
+ * mg_max_cycles 30, mg_tol 1e-10. */
+void wc_opts_default(wc_opts *opts);
+
+/* Device bytes a plan for (problem, opts) allocates (tables, spectral
+ * workspaces, Krylov vectors).  Returns 0 if the arguments are invalid. */
+size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts);
+
+/* Validate, build the FP64 eigenvalue / twiddle tables (Section 1 remark on
+ * S_n^(2) and Section 3.4), upload them, allocate workspaces.  *out is set to
+ * NULL on failure.  stream: hipStream_t or NULL. */
+wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stream,
+                         wc_plan **out);
+wc_status wc_plan_destroy(wc_plan *plan);
+wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
+
+/* Right-hand side of the transformed system (Section 1: f_tilde, g_tilde
+ * with M = I; eqn:main_system / eqn:main_system_nonsym).
+ * f, g: (n+1)*m samples at time levels 0..n; y0: m values; b: 2*n*m out.
+ * MINRES methods get b = [g_tilde; sqrt(gamma) f_tilde], GMRES gets
+ * [sqrt(gamma) f_tilde; g_tilde]. */
+wc_status wc_rhs(wc_plan *plan, const double *f, const double *g, const double *y0,
+                 double *b);
+
+/* y = A x (MINRES methods) or y = A_hat x (GMRES), x and y of 2*n*m doubles,
+ * distinct buffers (eqn:matrix_A, eqn:matrix_A_hat; time factor
+ * B_n = (B^(2))^{-1} B^(1) applied by its two-term recurrences). */
+wc_status wc_matvec(wc_plan *plan, const double *x, double *y);
+
+/* w = P^{-1} v for the plan's preconditioner (|P_S|, P_MS or P_S) by the
+ * three-step procedure of Section 3.4: omega-scaled time FFT, independent
+ * spatial problems per frequency, inverse transform.  v, w: 2*n*m doubles,
+ * may alias.  Arithmetic in FP64 or FP32 per opts.precision. */
+wc_status wc_pc_apply(wc_plan *plan, const double *v, double *w);
+
+/* Recover y (levels 1..n), p (levels 0..n-1), each n*m doubles, from
+ * x = [sqrt(gamma) B^(2) y; (B^(2))^T p] (eqn:main_system).  u (optional,
+ * may be NULL) receives p/gamma, the control (u = p/gamma, eqn:heat_2). */
+wc_status wc_recover(wc_plan *plan, const double *x, double *y, double *p, double *u);
+
+/* Solve the transformed system for right-hand side b (2*n*m) into x (2*n*m,
+ * overwritten; zero initial guess).  Synchronous.  info may be NULL. */
+wc_status wc_krylov(wc_plan *plan, const double *b, double *x, wc_info *info);
+
+/* Whole path: wc_rhs, wc_krylov, wc_recover.  y, p: n*m each; u optional.
+ * Synchronous.  Returns the solve status (WC_E_MAXIT still writes y, p). */
+wc_status wc_solve(wc_plan *plan, const double *f, const double *g, const double *y0,
+                   double *y, double *p, double *u, wc_info *info);
+
+/* ---- per-kernel timing (tracing) --------------------------------------------
+ * wc_profile(plan, 1) clears and starts recording a hipEvent pair around every
+ * kernel the plan launches on its stream; wc_profile(plan, 0) stops.
+ * wc_profile_read synchronises the stream, folds the recorded pairs into one
+ * entry per kernel family (launch count, summed duration) and writes at most
+ * `max` entries to `out` (host memory); returns the number of entries, or -1
+ * on error.  Recording adds no synchronisation to the solve.  `bytes` is the
+ * summed algorithmic HBM traffic of the family's launches: the bytes each
+ * launch must read and write at minimum (operands once, results once). */
+typedef struct {
+  char name[32];
+  int launches;
+  double total_ms;
+  double bytes;
+} wc_kernel_stat;
+
+wc_status wc_profile(wc_plan *plan, int enable);
+int wc_profile_read(wc_plan *plan, wc_kernel_stat *out, int max);
+
+/* Library build identification (static string). */
+const char *wc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WC_H_ */

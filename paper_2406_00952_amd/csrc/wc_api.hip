@@ -1,0 +1,620 @@
+// C ABI of libwcirc: plan construction (FP64 tables, workspaces), the asynchronous
+// building blocks (rhs, matvec, pc apply, recovery) and the Krylov drivers.
+//
+// Krylov drivers keep every vector on the device.  MINRES advances its scalar
+// recurrences in one-block device kernels between the vector passes; the host reads
+// back a status word once per iteration.  GMRES(k) computes Hessenberg entries on the
+// device (classical Gram-Schmidt applied twice), copies the new column to the host once
+// per iteration and does the Givens QR of the small (k+1) x k matrix there.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+
+#include "wc_internal.h"
+
+using namespace wc;
+
+namespace wc {
+
+const char *kernel_name(int id) {
+  static const char *names[K_COUNT] = {
+      "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
+      "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
+      "multiaxpy", "scale", "fill"};
+  return (id >= 0 && id < K_COUNT) ? names[id] : "?";
+}
+
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace wc
+
+namespace {
+
+#define WC_TRY(expr)                                          \
+  do {                                                        \
+    hipError_t _e = (expr);                                   \
+    if (_e != hipSuccess) return WC_E_HIP;                    \
+  } while (0)
+
+bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
+
+wc_status validate(const wc_problem *pr, const wc_opts *op) {
+  if (!pr || !op) return WC_E_ARG;
+  if (pr->dims != 1 && pr->dims != 2) return WC_E_ARG;
+  if (pr->M < 1 || pr->n < 2) return WC_E_ARG;
+  if (!(pr->T > 0) || !std::isfinite(pr->T)) return WC_E_ARG;
+  if (!(pr->theta >= 0.5 && pr->theta <= 1.0)) return WC_E_ARG;
+  if (!(pr->gamma > 0) || !std::isfinite(pr->gamma)) return WC_E_ARG;
+  if (!std::isfinite(pr->zeta) || !std::isfinite(pr->s2_remedy)) return WC_E_ARG;
+  if (op->method < WC_MINRES_ABS_PS || op->method > WC_GMRES_PS) return WC_E_ARG;
+  if (op->precision != WC_FP64 && op->precision != WC_MIXED) return WC_E_ARG;
+  if (!(op->tol > 0) || op->maxit < 1) return WC_E_ARG;
+  if (op->method == WC_GMRES_PS && (op->restart < 1 || op->restart > kMaxRestart)) return WC_E_ARG;
+  if (op->method == WC_MINRES_ABS_PS && pr->a_face_host) return WC_E_ARG;  // |P_S| needs a == 1
+  const double m = std::pow((double)pr->M, pr->dims);
+  if (m * pr->n * 2.0 > 4.0e9) return WC_E_ARG;  // 32-bit spatial indexing inside kernels
+  if (pr->a_face_host) {
+    const size_t nf = pr->dims == 1 ? (size_t)pr->M + 1 : 2 * (size_t)pr->M * (pr->M + 1);
+    for (size_t i = 0; i < nf; ++i)
+      if (!(pr->a_face_host[i] > 0) || !std::isfinite(pr->a_face_host[i])) return WC_E_ARG;
+  }
+  return WC_OK;
+}
+
+// Whether the GPU preconditioner covers this problem: a == 1, zeta == pi (real arithmetic,
+// half spectrum), n and M+1 powers of two in [4, 1024].
+bool pc_path_ok(const wc_problem *pr) {
+  if (pr->a_face_host) return false;
+  if (std::fabs(pr->zeta - M_PI) > 1e-12) return false;
+  return pow2_in(pr->n, 4, 1024) && pow2_in(pr->M + 1, 4, 1024);
+}
+
+int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
+  (void)pr;
+  if (op->method == WC_GMRES_PS) {
+    const bool flex = op->flexible || op->precision == WC_MIXED;
+    return (op->restart + 1) + (flex ? op->restart : 1) + 1 + 2;  // V, Z, Wt, B, X
+  }
+  return 8 + 2;  // R V0 V1 Z ZN W0 W1 AZ, B, X
+}
+
+struct Sizes {
+  size_t nvec, spec_bytes, partials, tables, vecs, total;
+};
+
+Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
+  Sizes s{};
+  const size_t m = (size_t)std::llround(std::pow((double)pr->M, pr->dims));
+  s.nvec = 2 * (size_t)pr->n * m;
+  const size_t es = op->precision == WC_MIXED ? 8 : 16;
+  s.spec_bytes = (size_t)pr->n * m * es;  // n/2 frequencies x 2 halves x m complex
+  size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads), (size_t)32 * kRedBlocks);
+  parts = std::max<size_t>(parts, (size_t)pc_partials_needed(pr->n, (int)m, op->precision));
+  s.partials = parts + 64;
+  s.tables = 1 << 20;
+  s.vecs = (size_t)krylov_vectors(pr, op) * s.nvec * sizeof(double);
+  s.total = s.spec_bytes * (pr->dims == 2 ? 2 : 1) + s.partials * sizeof(double) + s.tables +
+            s.vecs + S_COUNT * sizeof(double);
+  if (pr->a_face_host) s.total += 2 * (size_t)(pr->M + 1) * pr->M * sizeof(double);
+  return s;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void free_plan(wc_plan *p) {
+  if (!p) return;
+  for (auto &r : p->prof.recs) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
+  for (auto e : p->prof.pool) (void)hipEventDestroy(e);
+  dfree(p->d_aface);
+  dfree(p->d_lam64); dfree(p->d_lam32); dfree(p->d_dtw);
+  dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
+  dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
+  dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
+  dfree(p->d_vecs);
+  if (p->h_scal) (void)hipHostFree(p->h_scal);
+  p->h_scal = nullptr;
+  delete p;
+}
+
+std::vector<float> to_f32(const std::vector<double> &v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+hipError_t sync_read(wc_plan *p, int slot, int count) {
+  hipError_t e = hipMemcpyAsync(p->h_scal + slot, p->d_scal + slot, count * sizeof(double),
+                                hipMemcpyDeviceToHost, p->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(p->stream);
+}
+
+hipError_t write_scalar(wc_plan *p, int slot, const double *vals, int count) {
+  std::memcpy(p->h_scal + slot, vals, count * sizeof(double));
+  return hipMemcpyAsync(p->d_scal + slot, p->h_scal + slot, count * sizeof(double),
+                        hipMemcpyHostToDevice, p->stream);
+}
+
+// ---------------------------------------------------------------------------------
+// MINRES (preconditioned, Lanczos in the P^{-1} inner product).  The residual
+// r_j = b - A x_j is carried by the recurrence r_j = s^2 r_{j-1} + c eta_j v~_{j+1}
+// that follows from the Givens QR of the Lanczos tridiagonal, and is confirmed by an
+// explicit FP64 matvec when the recurrence reports convergence; a mismatch restarts
+// MINRES from the current iterate.
+// ---------------------------------------------------------------------------------
+wc_status run_minres(wc_plan *p, const double *b, double *x, wc_info *info) {
+  double *R = p->vec(0), *V0 = p->vec(1), *V1 = p->vec(2), *Z = p->vec(3), *ZN = p->vec(4);
+  double *W0 = p->vec(5), *W1 = p->vec(6), *AZ = p->vec(7);
+  const double tol = p->opts.tol;
+  WC_TRY(launch_dot(*p, b, b, S_DOT));
+  WC_TRY(sync_read(p, S_DOT, 1));
+  const double bnorm = std::sqrt(p->h_scal[S_DOT]);
+  WC_TRY(launch_fill(*p, x, 0.0, p->nvec));
+  if (!std::isfinite(bnorm)) return WC_E_NONFINITE;
+  if (bnorm == 0.0) {
+    if (info) { info->status = WC_OK; info->relres = 0; info->relres_est = 0; }
+    return WC_OK;
+  }
+  {
+    const double v[1] = {bnorm};
+    WC_TRY(write_scalar(p, S_BNORM, v, 1));
+  }
+  WC_TRY(launch_lincomb3(*p, R, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
+  int iters = 0, restarts = 0;
+  wc_status st = WC_E_MAXIT;
+  double relres = 1.0, relres_est = 1.0;
+  for (;;) {
+    {
+      const double zero[2] = {0.0, 0.0};
+      WC_TRY(write_scalar(p, S_STATUS, zero, 2));  // status, iteration count
+    }
+    WC_TRY(launch_lincomb3(*p, V1, R, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
+    WC_TRY(launch_fill(*p, V0, 0.0, p->nvec));
+    WC_TRY(launch_fill(*p, W0, 0.0, p->nvec));
+    WC_TRY(launch_fill(*p, W1, 0.0, p->nvec));
+    int np = 0;
+    WC_TRY(launch_pc_apply(*p, V1, Z, true, &np));
+    WC_TRY(launch_minres_scalar(*p, 0, np, tol));
+    WC_TRY(sync_read(p, 0, 16));
+    int code = (int)p->h_scal[S_STATUS];
+    if (code == ST_NONFINITE) return WC_E_NONFINITE;
+    if (code == ST_BREAKDOWN) { st = WC_E_BREAKDOWN; break; }
+    while (code == ST_RUNNING && iters < p->opts.maxit) {
+      WC_TRY(launch_matvec(*p, Z, AZ, p->d_partials, &np));
+      WC_TRY(launch_minres_scalar(*p, 1, np, tol));
+      WC_TRY(launch_lincomb3(*p, V0, AZ, V1, V0, S_CV0, 0, 0, 0));
+      WC_TRY(launch_pc_apply(*p, V0, ZN, true, &np));
+      WC_TRY(launch_minres_scalar(*p, 2, np, tol));
+      WC_TRY(launch_minres_update(*p, W0, W1, Z, x, R, V0));
+      WC_TRY(launch_minres_scalar(*p, 3, red_blocks(p->nvec), tol));
+      WC_TRY(sync_read(p, 0, 16));
+      ++iters;
+      std::swap(V0, V1);
+      std::swap(W0, W1);
+      std::swap(Z, ZN);
+      code = (int)p->h_scal[S_STATUS];
+      relres_est = std::sqrt(p->h_scal[S_RNORM2]) / bnorm;
+    }
+    if (code == ST_NONFINITE) { st = WC_E_NONFINITE; break; }
+    // explicit FP64 true residual
+    WC_TRY(launch_matvec(*p, x, AZ, p->d_partials, nullptr));
+    WC_TRY(launch_lincomb3(*p, R, b, AZ, nullptr, -1, 1.0, -1.0, 0.0));
+    WC_TRY(launch_dot(*p, R, R, S_DOT));
+    WC_TRY(sync_read(p, S_DOT, 1));
+    relres = std::sqrt(p->h_scal[S_DOT]) / bnorm;
+    if (relres <= tol) { st = WC_OK; break; }
+    if (code == ST_BREAKDOWN && restarts > 0) { st = WC_E_BREAKDOWN; break; }
+    if (iters >= p->opts.maxit) { st = WC_E_MAXIT; break; }
+    if (++restarts > 20) { st = WC_E_MAXIT; break; }
+  }
+  if (info) {
+    info->iters = iters;
+    info->restarts = restarts;
+    info->relres = relres;
+    info->relres_est = relres_est;
+    info->status = st;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------------
+// GMRES(k), right preconditioned: solve A P^{-1} u = b, x = P^{-1} u.  Flexible form
+// (stores z_j = P^{-1} v_j) when requested or when the preconditioner runs in FP32.
+// ---------------------------------------------------------------------------------
+wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
+  const int k = p->opts.restart;
+  const bool flex = p->opts.flexible || p->opts.precision == WC_MIXED;
+  const size_t nv = p->nvec;
+  double *V = p->vec(0);
+  double *Zb = p->vec(k + 1);
+  double *Wt = p->vec(k + 1 + (flex ? k : 1));
+  const double tol = p->opts.tol;
+  WC_TRY(launch_dot(*p, b, b, S_DOT));
+  WC_TRY(sync_read(p, S_DOT, 1));
+  const double bnorm = std::sqrt(p->h_scal[S_DOT]);
+  WC_TRY(launch_fill(*p, x, 0.0, nv));
+  if (!std::isfinite(bnorm)) return WC_E_NONFINITE;
+  if (bnorm == 0.0) {
+    if (info) { info->status = WC_OK; info->relres = 0; info->relres_est = 0; }
+    return WC_OK;
+  }
+  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k);
+  int total = 0, cycles = 0;
+  bool first = true;
+  wc_status st = WC_E_MAXIT;
+  double relres = 1.0, relres_est = 1.0;
+  for (;;) {
+    if (first) {
+      WC_TRY(launch_lincomb3(*p, V, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
+    } else {
+      WC_TRY(launch_matvec(*p, x, Wt, p->d_partials, nullptr));
+      WC_TRY(launch_lincomb3(*p, V, b, Wt, nullptr, -1, 1.0, -1.0, 0.0));
+    }
+    WC_TRY(launch_dot(*p, V, V, S_BETA));
+    WC_TRY(sync_read(p, S_BETA, 1));
+    const double beta = std::sqrt(p->h_scal[S_BETA]);
+    relres = beta / bnorm;
+    if (!std::isfinite(relres)) { st = WC_E_NONFINITE; break; }
+    if (relres <= tol) { st = WC_OK; break; }
+    if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
+    WC_TRY(launch_scale(*p, V, V, S_BETA));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jd = 0;
+    bool stop = false;
+    for (int j = 0; j < k && !stop; ++j) {
+      double *Vj = V + (size_t)j * nv;
+      double *Zj = flex ? Zb + (size_t)j * nv : Zb;
+      WC_TRY(launch_pc_apply(*p, Vj, Zj, false, nullptr));
+      WC_TRY(launch_matvec(*p, Zj, Wt, p->d_partials, nullptr));
+      WC_TRY(launch_multidot(*p, V, j + 1, Wt, S_H1));
+      WC_TRY(launch_multiaxpy(*p, Wt, V, j + 1, S_H1, -1.0, false, 0));
+      WC_TRY(launch_multidot(*p, V, j + 1, Wt, S_H2));
+      WC_TRY(launch_multiaxpy(*p, Wt, V, j + 1, S_H2, -1.0, true, S_HNORM));
+      WC_TRY(launch_scale(*p, V + (size_t)(j + 1) * nv, Wt, S_HNORM));
+      // S_H1..S_H2+j and S_HNORM: one copy of the span [S_HNORM, S_H2 + j]
+      WC_TRY(sync_read(p, S_HNORM, S_H2 + j + 1 - S_HNORM));
+      double *h = &H[(size_t)j * (k + 1)];  // column j
+      for (int i = 0; i <= j; ++i) h[i] = p->h_scal[S_H1 + i] + p->h_scal[S_H2 + i];
+      const double hn = std::sqrt(std::max(p->h_scal[S_HNORM], 0.0));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double r = std::hypot(h[j], hn);
+      cs[j] = r > 0 ? h[j] / r : 1.0;
+      sn[j] = r > 0 ? hn / r : 0.0;
+      h[j] = r;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      jd = j + 1;
+      relres_est = std::fabs(g[j + 1]) / bnorm;
+      if (!std::isfinite(relres_est) || r == 0.0) { stop = true; break; }
+      if (relres_est <= tol || hn == 0.0 || total >= p->opts.maxit) stop = true;
+    }
+    // back substitution R y = g
+    for (int i = jd - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < jd; ++l) s -= H[(size_t)l * (k + 1) + i] * y[l];
+      const double d = H[(size_t)i * (k + 1) + i];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
+    WC_TRY(write_scalar(p, S_Y, y.data(), jd));
+    if (flex) {
+      WC_TRY(launch_multiaxpy(*p, x, Zb, jd, S_Y, 1.0, false, 0));
+    } else {
+      WC_TRY(launch_fill(*p, Wt, 0.0, nv));
+      WC_TRY(launch_multiaxpy(*p, Wt, V, jd, S_Y, 1.0, false, 0));
+      WC_TRY(launch_pc_apply(*p, Wt, Zb, false, nullptr));
+      WC_TRY(launch_lincomb3(*p, x, x, Zb, nullptr, -1, 1.0, 1.0, 0.0));
+    }
+    first = false;
+    ++cycles;
+  }
+  if (info) {
+    info->iters = total;
+    info->restarts = cycles;
+    info->relres = relres;
+    info->relres_est = relres_est;
+    info->status = st;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wc_version(void) { return "libwcirc 0.1 gfx950"; }
+
+wc_status wc_profile(wc_plan *plan, int enable) {
+  if (!plan) return WC_E_ARG;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return WC_E_HIP;
+  if (enable) {  // recycle the previous recording's events, start a new one
+    for (auto &r : plan->prof.recs) {
+      if (r.a) plan->prof.pool.push_back(r.a);
+      if (r.b) plan->prof.pool.push_back(r.b);
+    }
+    plan->prof.recs.clear();
+  }
+  plan->prof.on = enable != 0;
+  return WC_OK;
+}
+
+int wc_profile_read(wc_plan *plan, wc_kernel_stat *out, int max) {
+  if (!plan || (!out && max > 0)) return -1;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return -1;
+  int launches[K_COUNT] = {0};
+  double ms[K_COUNT] = {0};
+  double bytes[K_COUNT] = {0};
+  for (const auto &r : plan->prof.recs) {
+    float t = 0.f;
+    if (r.a && r.b && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.kid >= 0 &&
+        r.kid < K_COUNT) {
+      launches[r.kid] += 1;
+      ms[r.kid] += t;
+      bytes[r.kid] += r.bytes;
+    }
+  }
+  int cnt = 0;
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (!launches[k]) continue;
+    if (cnt < max) {
+      std::memset(&out[cnt], 0, sizeof(wc_kernel_stat));
+      std::strncpy(out[cnt].name, kernel_name(k), sizeof(out[cnt].name) - 1);
+      out[cnt].launches = launches[k];
+      out[cnt].total_ms = ms[k];
+      out[cnt].bytes = bytes[k];
+    }
+    ++cnt;
+  }
+  return cnt < max ? cnt : max;
+}
+
+const char *wc_status_str(int s) {
+  switch (s) {
+    case WC_OK: return "ok";
+    case WC_E_ARG: return "invalid argument";
+    case WC_E_SINGULAR_S2: return "S_n^(2) singular and no remedy value";
+    case WC_E_NOMEM: return "device allocation failed";
+    case WC_E_MAXIT: return "maximum iterations reached";
+    case WC_E_BREAKDOWN: return "Krylov breakdown";
+    case WC_E_NONFINITE: return "non-finite value";
+    case WC_E_CANCELLED: return "cancelled";
+    case WC_E_ADMISSION: return "admission refused";
+    case WC_E_UNSUPPORTED: return "unsupported by the GPU path";
+    case WC_E_HIP: return "HIP runtime error";
+    default: return "internal error";
+  }
+}
+
+void wc_opts_default(wc_opts *o) {
+  if (!o) return;
+  o->method = WC_GMRES_PS;
+  o->precision = WC_FP64;
+  o->tol = 1e-8;
+  o->maxit = 500;
+  o->restart = 30;
+  o->flexible = 0;
+  o->mg_max_cycles = 30;
+  o->mg_tol = 1e-10;
+}
+
+size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts) {
+  if (validate(prob, opts) != WC_OK) return 0;
+  return sizes_of(prob, opts).total;
+}
+
+wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stream,
+                         wc_plan **out) {
+  if (!out) return WC_E_ARG;
+  *out = nullptr;
+  wc_status vs = validate(prob, opts);
+  if (vs != WC_OK) return vs;
+  wc_plan *p = new (std::nothrow) wc_plan();
+  if (!p) return WC_E_NOMEM;
+  p->dims = prob->dims;
+  p->M = prob->M;
+  p->n = prob->n;
+  p->m = prob->dims == 1 ? prob->M : prob->M * prob->M;
+  p->N1 = prob->M + 1;
+  p->T = prob->T;
+  p->theta = prob->theta;
+  p->gamma = prob->gamma;
+  p->zeta = prob->zeta;
+  p->s2_remedy = prob->s2_remedy;
+  p->tau = prob->T / prob->n;
+  p->alpha = p->tau / std::sqrt(prob->gamma);
+  p->h = 1.0 / (prob->M + 1);
+  p->inv_h2 = 1.0 / (p->h * p->h);
+  p->var_coeff = prob->a_face_host != nullptr;
+  p->pc_ok = pc_path_ok(prob);
+  p->opts = *opts;
+  p->stream = (hipStream_t)stream;
+  p->nvec = 2 * (size_t)p->n * p->m;
+  const Sizes sz = sizes_of(prob, opts);
+
+  // ---- FP64 tables ----
+  const int n = p->n, N1 = p->N1, M = p->M;
+  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M);
+  for (int l = 0; l < n; ++l) {  // check every frequency of S^(2) for a zero eigenvalue
+    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
+    const std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
+    if (std::abs(l2) < 1e-13 && p->s2_remedy == 0.0) {
+      free_plan(p);
+      return WC_E_SINGULAR_S2;
+    }
+  }
+  for (int q = 0; q < n / 2; ++q) {  // kept frequencies l = q + 1
+    const int l = q + 1;
+    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
+    const std::complex<double> l1 = 1.0 - e;
+    std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
+    if (std::abs(l2) < 1e-13) l2 = p->s2_remedy;
+    const std::complex<double> lv = l1 / l2;
+    lam[2 * q] = lv.real();
+    lam[2 * q + 1] = lv.imag();
+  }
+  for (int k = 0; k < n; ++k) {
+    dtw[2 * k] = std::cos(p->zeta * k / n);
+    dtw[2 * k + 1] = std::sin(p->zeta * k / n);
+    twt[2 * k] = std::cos(2.0 * M_PI * k / n);
+    twt[2 * k + 1] = -std::sin(2.0 * M_PI * k / n);
+  }
+  for (int k = 0; k < N1; ++k) {
+    tws[2 * k] = std::cos(2.0 * M_PI * k / N1);
+    tws[2 * k + 1] = -std::sin(2.0 * M_PI * k / N1);
+    sn[k] = std::sin(M_PI * k / N1);
+  }
+  for (int j = 0; j < M; ++j) {
+    const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
+    mu[j] = 4.0 * p->inv_h2 * sv * sv;
+  }
+  hipError_t e = hipSuccess;
+#define WC_UP(dst, src)                 \
+  if (e == hipSuccess) e = upload(&p->dst, src);
+  WC_UP(d_lam64, lam) WC_UP(d_dtw, dtw) WC_UP(d_twt64, twt) WC_UP(d_tws64, tws)
+  WC_UP(d_sin64, sn) WC_UP(d_mu64, mu)
+  WC_UP(d_lam32, to_f32(lam)) WC_UP(d_twt32, to_f32(twt)) WC_UP(d_tws32, to_f32(tws))
+  WC_UP(d_sin32, to_f32(sn)) WC_UP(d_mu32, to_f32(mu))
+#undef WC_UP
+  if (e == hipSuccess && prob->a_face_host) {
+    const size_t nf = p->dims == 1 ? (size_t)M + 1 : 2 * (size_t)M * (M + 1);
+    std::vector<double> af(prob->a_face_host, prob->a_face_host + nf);
+    e = upload(&p->d_aface, af);
+  }
+  if (e != hipSuccess) {
+    free_plan(p);
+    return WC_E_HIP;
+  }
+  // ---- workspaces ----
+  bool oom = false;
+  auto alloc = [&](void **ptr, size_t bytes) {
+    if (oom) return;
+    if (hipMalloc(ptr, bytes) != hipSuccess) oom = true;
+  };
+  alloc(&p->d_specA, sz.spec_bytes);
+  if (p->dims == 2) alloc(&p->d_specB, sz.spec_bytes);
+  alloc((void **)&p->d_partials, sz.partials * sizeof(double));
+  alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
+  p->nkvec = krylov_vectors(prob, opts);
+  alloc((void **)&p->d_vecs, sz.vecs);
+  if (!oom && hipHostMalloc((void **)&p->h_scal, S_COUNT * sizeof(double), 0) != hipSuccess)
+    oom = true;
+  if (oom) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return WC_E_NOMEM;
+  }
+  std::memset(p->h_scal, 0, S_COUNT * sizeof(double));
+  if (hipMemcpy(p->d_scal, p->h_scal, S_COUNT * sizeof(double), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    free_plan(p);
+    return WC_E_HIP;
+  }
+  p->footprint = sz.total;
+  *out = p;
+  return WC_OK;
+}
+
+wc_status wc_plan_destroy(wc_plan *plan) {
+  if (!plan) return WC_E_ARG;
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) {
+    free_plan(plan);
+    return WC_E_HIP;
+  }
+  free_plan(plan);
+  return WC_OK;
+}
+
+wc_status wc_plan_set_stream(wc_plan *plan, void *stream) {
+  if (!plan) return WC_E_ARG;
+  plan->stream = (hipStream_t)stream;
+  return WC_OK;
+}
+
+wc_status wc_rhs(wc_plan *plan, const double *f, const double *g, const double *y0, double *b) {
+  if (!plan || !f || !g || !y0 || !b) return WC_E_ARG;
+  WC_TRY(launch_rhs(*plan, f, g, y0, b));
+  return WC_OK;
+}
+
+wc_status wc_matvec(wc_plan *plan, const double *x, double *y) {
+  if (!plan || !x || !y || x == y) return WC_E_ARG;
+  WC_TRY(launch_matvec(*plan, x, y, plan->d_partials, nullptr));
+  return WC_OK;
+}
+
+wc_status wc_pc_apply(wc_plan *plan, const double *v, double *w) {
+  if (!plan || !v || !w) return WC_E_ARG;
+  if (!plan->pc_ok) return WC_E_UNSUPPORTED;
+  WC_TRY(launch_pc_apply(*plan, v, w, false, nullptr));
+  return WC_OK;
+}
+
+wc_status wc_recover(wc_plan *plan, const double *x, double *y, double *p, double *u) {
+  if (!plan || !x || !y || !p) return WC_E_ARG;
+  WC_TRY(launch_recover(*plan, x, y, p, u));
+  return WC_OK;
+}
+
+wc_status wc_krylov(wc_plan *plan, const double *b, double *x, wc_info *info) {
+  if (!plan || !b || !x || b == x) return WC_E_ARG;
+  if (!plan->pc_ok) return WC_E_UNSUPPORTED;
+  wc_info local{};
+  wc_info *inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  const auto t0 = std::chrono::steady_clock::now();
+  wc_status st = plan->opts.method == WC_GMRES_PS ? run_gmres(plan, b, x, inf)
+                                                  : run_minres(plan, b, x, inf);
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) st = WC_E_HIP;
+  const auto t1 = std::chrono::steady_clock::now();
+  inf->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  inf->status = st;
+  return st;
+}
+
+wc_status wc_solve(wc_plan *plan, const double *f, const double *g, const double *y0, double *y,
+                   double *p, double *u, wc_info *info) {
+  if (!plan || !f || !g || !y0 || !y || !p) return WC_E_ARG;
+  if (!plan->pc_ok) return WC_E_UNSUPPORTED;
+  double *B = plan->vec(plan->nkvec - 2);
+  double *X = plan->vec(plan->nkvec - 1);
+  WC_TRY(launch_rhs(*plan, f, g, y0, B));
+  wc_status st = wc_krylov(plan, B, X, info);
+  if (st != WC_OK && st != WC_E_MAXIT) return st;
+  WC_TRY(launch_recover(*plan, X, y, p, u));
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return WC_E_HIP;
+  return st;
+}
+
+}  // extern "C"

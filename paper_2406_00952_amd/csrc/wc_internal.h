@@ -1,0 +1,166 @@
+// Internal declarations shared by the HIP translation units of libwcirc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/wc.h"
+
+namespace wc {
+
+constexpr int kThreads = 256;        // threads per workgroup for every kernel
+constexpr int kRedBlocks = 1024;     // max workgroups of the streaming reductions
+constexpr int kMaxRestart = 64;
+constexpr int kMaxPartials = 1 << 16;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+// ---- device-side scalar state of the Krylov solvers ------------------------
+// A small FP64 array in device memory; kernels read their coefficients from it
+// so no host round trip is needed between the steps of one iteration.
+enum ScalarSlot : int {
+  // MINRES state
+  S_GAMMA_PREV = 0, S_GAMMA, S_DELTA, S_ETA, S_C_PREV, S_C, S_S_PREV, S_S,
+  S_BNORM, S_RNORM2, S_STATUS, S_ITER,
+  // v update:  v_new = c0*Az + c1*v + c2*v_prev
+  S_CV0 = 16, S_CV1, S_CV2,
+  // w/x/r update
+  S_CWZ = 20, S_CW0, S_CW1, S_CX, S_CRR, S_CRV,
+  // GMRES
+  S_BETA = 32, S_HNORM, S_INVH,
+  S_H1 = 64,     // kMaxRestart+1 values
+  S_H2 = 160,    // kMaxRestart+1 values
+  S_Y = 256,     // kMaxRestart values (least-squares solution)
+  S_DOT = 340,   // scratch dot results
+  S_COUNT = 512
+};
+
+enum SolveStatusCode : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+
+// kernel families for the optional event timing
+enum KernelId : int {
+  K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
+  K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
+  K_MULTIAXPY, K_SCALE, K_FILL, K_COUNT
+};
+const char *kernel_name(int id);
+
+struct ProfRec {
+  int kid;
+  double bytes;  // algorithmic HBM bytes the launch must move
+  hipEvent_t a, b;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+};
+
+}  // namespace wc
+
+struct wc_plan {
+  // problem
+  int dims = 1, M = 0, n = 0, m = 0, N1 = 0;
+  double T = 1, theta = 1, gamma = 1, zeta = 0, s2_remedy = 1;
+  double tau = 0, alpha = 0, h = 0, inv_h2 = 0;
+  bool var_coeff = false;
+  bool pc_ok = false;            // the GPU preconditioner covers this problem
+  wc_opts opts{};
+  hipStream_t stream = nullptr;
+  size_t nvec = 0;          // 2*n*m
+  // device tables
+  double *d_aface = nullptr;     // face coefficients (variable a) or null
+  double *d_lam64 = nullptr;     // n/2 complex: eigenvalues of S_n at kept frequencies
+  float *d_lam32 = nullptr;
+  double *d_dtw = nullptr;       // n complex: omega^{k/n} = e^{i zeta k/n}
+  double *d_twt64 = nullptr;     // n complex: e^{-2 pi i p/n}
+  float *d_twt32 = nullptr;
+  double *d_tws64 = nullptr;     // N1 complex: e^{-2 pi i p/N1}
+  float *d_tws32 = nullptr;
+  double *d_sin64 = nullptr;     // N1 reals: sin(pi i/N1)
+  float *d_sin32 = nullptr;
+  double *d_mu64 = nullptr;      // M reals: eigenvalues of the 1D -L_h (a == 1)
+  float *d_mu32 = nullptr;
+  // workspaces
+  void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
+  void *d_specB = nullptr;       // n*m complex (P): x2-line-contiguous copy (2D)
+  double *d_partials = nullptr;  // reduction partials
+  double *d_scal = nullptr;      // Krylov scalars (wc::S_COUNT)
+  double *h_scal = nullptr;      // pinned host mirror
+  // Krylov vectors: one allocation of nvecs * nvec doubles
+  double *d_vecs = nullptr;
+  int nkvec = 0;
+  size_t footprint = 0;
+
+  mutable wc::Profiler prof;
+
+  double *vec(int i) const { return d_vecs + (size_t)i * nvec; }
+};
+
+namespace wc {
+// Records an event pair around the launches in its scope when profiling is on.
+struct ProfScope {
+  const wc_plan &p;
+  int kid;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(const wc_plan &pl, int k, double nbytes) : p(pl), kid(k), bytes(nbytes) {
+    if (p.prof.on) {
+      a = p.prof.get();
+      (void)hipEventRecord(a, p.stream);
+    }
+  }
+  ~ProfScope() {
+    if (p.prof.on && a) {
+      hipEvent_t b = p.prof.get();
+      (void)hipEventRecord(b, p.stream);
+      p.prof.recs.push_back({kid, bytes, a, b});
+    }
+  }
+};
+}  // namespace wc
+
+namespace wc {
+
+// ---- launchers (wc_ops.hip) -------------------------------------------------
+hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
+                         int *nblocks_out);
+hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
+                      double *b);
+hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u);
+
+int red_blocks(size_t n);
+// dst[i] = c0*a + c1*b + c2*c, coefficient k read from d_scal[slot + k] (slot < 0: host c*)
+hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,
+                           const double *c, int slot, double h0, double h1, double h2);
+// partials of <a, b> (one per block) -> finalize into d_scal[slot]
+hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot);
+hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, int nsum,
+                           int slot);
+hipError_t launch_minres_update(const wc_plan &p, double *w0, const double *w1,
+                                const double *z, double *x, double *r, const double *vnew);
+hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double tol);
+hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
+                           int slot);
+hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb,
+                            int slot, double sign, bool norm, int norm_slot);
+hipError_t launch_scale(const wc_plan &p, double *dst, const double *src, int slot_inv);
+hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count);
+hipError_t launch_gmres_scalar(const wc_plan &p, int stage, int j);
+
+// ---- preconditioner (wc_pc.hip) --------------------------------------------
+// w = P^{-1} v.  With dot = true the last pass also writes per-block partial sums of
+// <w, v> to p.d_partials[0..*nparts) (v must then not alias w).
+hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool dot, int *nparts);
+bool pc_supported(int n, int N1);
+int pc_partials_needed(int n, int m, int precision);
+
+}  // namespace wc

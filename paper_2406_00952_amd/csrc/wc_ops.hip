@@ -1,0 +1,576 @@
+// FP64 kernels of the solve around the preconditioner: the all-at-once operator,
+// right-hand side assembly, recovery of y and p, deterministic reductions and the
+// device-side scalar steps of MINRES.
+//
+// Operator (eqn:matrix_A, eqn:matrix_T): T = B_n kron I + tau I kron K with
+// B_n = (B^(2))^{-1} B^(1) (Section 1).  B_n x is the forward recurrence
+//   z_k = (x_k - x_{k-1} - (1-theta) z_{k-1}) / theta,
+// B_n^T x the backward recurrence
+//   u_k = (x_k - (1-theta) u_{k+1}) / theta,  z_k = u_k - u_{k+1},
+// so one thread per spatial point marches through time, O(nm) for every theta.
+// K = -L_h is the conservative five-point (three-point) stencil with face
+// coefficients; Dirichlet neighbours are zero.
+
+#include "wc_internal.h"
+
+namespace wc {
+namespace {
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+struct Stencil {
+  double cc, cw, ce, cs, cn;   // K x = cc x_P - cw x_W - ce x_E - cs x_S - cn x_N
+  int ow, oe, os, on;          // neighbour offsets (0 when absent: coefficient is 0)
+};
+
+__device__ __forceinline__ Stencil make_stencil(int s, int M, int dims, double inv_h2,
+                                                const double *__restrict__ aface) {
+  Stencil st;
+  if (dims == 1) {
+    const double aw = aface ? aface[s] : 1.0;
+    const double ae = aface ? aface[s + 1] : 1.0;
+    st.cc = inv_h2 * (aw + ae);
+    st.cw = s > 0 ? inv_h2 * aw : 0.0;
+    st.ce = s < M - 1 ? inv_h2 * ae : 0.0;
+    st.ow = s > 0 ? -1 : 0;
+    st.oe = s < M - 1 ? 1 : 0;
+    st.cs = st.cn = 0.0;
+    st.os = st.on = 0;
+    return st;
+  }
+  const int i = s % M, j = s / M;
+  double aw = 1.0, ae = 1.0, as = 1.0, an = 1.0;
+  if (aface) {
+    const double *ax = aface;                      // (M, M+1)
+    const double *ay = aface + (size_t)M * (M + 1);  // (M+1, M)
+    aw = ax[(size_t)j * (M + 1) + i];
+    ae = ax[(size_t)j * (M + 1) + i + 1];
+    as = ay[(size_t)j * M + i];
+    an = ay[(size_t)(j + 1) * M + i];
+  }
+  st.cc = inv_h2 * (aw + ae + as + an);
+  st.cw = i > 0 ? inv_h2 * aw : 0.0;
+  st.ce = i < M - 1 ? inv_h2 * ae : 0.0;
+  st.cs = j > 0 ? inv_h2 * as : 0.0;
+  st.cn = j < M - 1 ? inv_h2 * an : 0.0;
+  st.ow = i > 0 ? -1 : 0;
+  st.oe = i < M - 1 ? 1 : 0;
+  st.os = j > 0 ? -M : 0;
+  st.on = j < M - 1 ? M : 0;
+  return st;
+}
+
+__device__ __forceinline__ double apply_stencil(const Stencil &st, const double *__restrict__ xk,
+                                                int s) {
+  return st.cc * xk[s] - st.cw * xk[s + st.ow] - st.ce * xk[s + st.oe] - st.cs * xk[s + st.os] -
+         st.cn * xk[s + st.on];
+}
+
+struct MvArgs {
+  int n, M, dims, m, sym;
+  double theta, tau, alpha, inv_h2;
+  const double *aface;
+};
+
+// blockIdx.y == 0: T x1 - alpha x2 (forward in time); 1: T^T x2 + alpha x1 (backward).
+// Output block rows: A (sym) = [alpha x1 + T^T x2; T x1 - alpha x2],
+//                    A_hat   = [T x1 - alpha x2; alpha x1 + T^T x2].
+// partials[dir*gridDim.x + block] = this block's share of <y, x>.
+__global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ x,
+                                                     double *__restrict__ y, MvArgs a,
+                                                     double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const int dir = blockIdx.y;
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  const size_t nm = (size_t)a.n * a.m;
+  double acc = 0.0;
+  if (s < a.m) {
+    const double *xs = dir == 0 ? x : x + nm;
+    const double *xo = dir == 0 ? x + nm : x;
+    double *yo = a.sym ? (dir == 0 ? y + nm : y) : (dir == 0 ? y : y + nm);
+    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
+    const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
+    double zprev = 0.0, xprev = 0.0;
+#pragma unroll 4
+    for (int kk = 0; kk < a.n; ++kk) {
+      const int k = dir == 0 ? kk : a.n - 1 - kk;
+      const double *xk = xs + (size_t)k * a.m;
+      const double xc = xk[s];
+      const double kx = apply_stencil(st, xk, s);
+      const double xok = xo[(size_t)k * a.m + s];
+      double out;
+      if (dir == 0) {
+        const double z = (xc - xprev - omt * zprev) * ith;
+        out = z + a.tau * kx - a.alpha * xok;
+        zprev = z;
+        xprev = xc;
+      } else {
+        const double u = (xc - omt * zprev) * ith;
+        out = (u - zprev) + a.tau * kx + a.alpha * xok;
+        zprev = u;
+      }
+      yo[(size_t)k * a.m + s] = out;
+      acc += out * (a.sym ? xok : xc);
+    }
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[dir * gridDim.x + blockIdx.x] = r;
+}
+
+struct RhsArgs {
+  int n, M, dims, m, sym;
+  double theta, tau, sqrt_gamma, inv_h2;
+  const double *aface;
+};
+
+// f_tilde, g_tilde of Section 1 with M = I, then b = [g; sqrt(gamma) f] (sym) or
+// [sqrt(gamma) f; g].  One thread per (time slice k+1, point s).
+__global__ __launch_bounds__(kThreads) void k_rhs(const double *__restrict__ f,
+                                                  const double *__restrict__ g,
+                                                  const double *__restrict__ y0,
+                                                  double *__restrict__ b, RhsArgs a) {
+  const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t nm = (size_t)a.n * a.m;
+  if (idx >= nm) return;
+  const int k = (int)(idx / a.m), s = (int)(idx % a.m);
+  const double th = a.theta, omt = 1.0 - th;
+  double ft = a.tau * (th * f[(size_t)(k + 1) * a.m + s] + omt * f[(size_t)k * a.m + s]);
+  double gt = a.tau * (th * g[(size_t)k * a.m + s] + omt * g[(size_t)(k + 1) * a.m + s]);
+  if (k == 0) {
+    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
+    ft += y0[s] - omt * a.tau * apply_stencil(st, y0, s);
+    gt -= a.tau * omt * y0[s];
+  }
+  if (a.sym) {
+    b[idx] = gt;
+    b[nm + idx] = a.sqrt_gamma * ft;
+  } else {
+    b[idx] = a.sqrt_gamma * ft;
+    b[nm + idx] = gt;
+  }
+}
+
+// y from theta y_1 = yt_1, theta y_k + (1-theta) y_{k-1} = yt_k (yt = x1/sqrt(gamma));
+// p from theta p^{(n-1)} = pt_n, theta p^{(k-1)} + (1-theta) p^{(k)} = pt_k.
+__global__ __launch_bounds__(kThreads) void k_recover(const double *__restrict__ x,
+                                                      double *__restrict__ y,
+                                                      double *__restrict__ p,
+                                                      double *__restrict__ u, int n, int m,
+                                                      double theta, double inv_sqrt_gamma,
+                                                      double inv_gamma) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  const size_t nm = (size_t)n * m;
+  const double omt = 1.0 - theta, ith = 1.0 / theta;
+  if (blockIdx.y == 0) {
+    double prev = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double v = (x[(size_t)k * m + s] * inv_sqrt_gamma - omt * prev) * ith;
+      y[(size_t)k * m + s] = v;
+      prev = v;
+    }
+  } else {
+    double next = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      const double v = (x[nm + (size_t)k * m + s] - omt * next) * ith;
+      p[(size_t)k * m + s] = v;
+      if (u) u[(size_t)k * m + s] = v * inv_gamma;
+      next = v;
+    }
+  }
+}
+
+// ---- streaming BLAS-1 with deterministic reductions ---------------------------
+
+__global__ __launch_bounds__(kThreads) void k_lincomb3(double *__restrict__ dst,
+                                                       const double *__restrict__ a,
+                                                       const double *__restrict__ b,
+                                                       const double *__restrict__ c, size_t nv,
+                                                       const double *__restrict__ scal,
+                                                       int slot, double h0, double h1,
+                                                       double h2) {
+  const double c0 = slot >= 0 ? scal[slot] : h0;
+  const double c1 = slot >= 0 ? scal[slot + 1] : h1;
+  const double c2 = slot >= 0 ? scal[slot + 2] : h2;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    double v = c0 * a[i];
+    if (b) v += c1 * b[i];
+    if (c) v += c2 * c[i];
+    dst[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot(const double *__restrict__ a,
+                                                  const double *__restrict__ b, size_t nv,
+                                                  double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads)
+    acc += a[i] * b[i];
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// scal[slot + j] = sum_{i < count} partials[j*count + i], fixed order.
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials,
+                                                       int count, int nsum,
+                                                       double *__restrict__ scal, int slot) {
+  __shared__ double red[kThreads / 64];
+  for (int j = 0; j < nsum; ++j) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kThreads) acc += partials[(size_t)j * count + i];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) scal[slot + j] = r;
+  }
+}
+
+// MINRES direction / iterate / residual update (coefficients in scal):
+//   w0 <- CWZ z + CW0 w0 + CW1 w1   (the new direction overwrites w_{j-1})
+//   x  <- x + CX w0
+//   r  <- CRR r + CRV vnew,   partial sums of ||r||^2
+__global__ __launch_bounds__(kThreads) void k_minres_update(double *__restrict__ w0,
+                                                            const double *__restrict__ w1,
+                                                            const double *__restrict__ z,
+                                                            double *__restrict__ x,
+                                                            double *__restrict__ r,
+                                                            const double *__restrict__ vnew,
+                                                            size_t nv,
+                                                            const double *__restrict__ scal,
+                                                            double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const double cwz = scal[S_CWZ], cw0 = scal[S_CW0], cw1 = scal[S_CW1];
+  const double cxx = scal[S_CX], crr = scal[S_CRR], crv = scal[S_CRV];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    const double wn = cwz * z[i] + cw0 * w0[i] + cw1 * w1[i];
+    w0[i] = wn;
+    x[i] += cxx * wn;
+    const double rn = crr * r[i] + crv * vnew[i];
+    r[i] = rn;
+    acc += rn * rn;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// One block: reduce `nparts` partials and advance the MINRES scalar recurrences.
+// stage 0: init from <z1, v1>; 1: after A z (delta); 2: after P^{-1} v_new (gamma_new,
+// Givens rotation, update coefficients); 3: after the update (true residual norm).
+__global__ __launch_bounds__(kThreads) void k_minres_scalar(const double *__restrict__ partials,
+                                                            int nparts, double *__restrict__ S,
+                                                            int stage, double tol) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += partials[i];
+  const double dot = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  if (stage == 0) {
+    if (!(dot >= 0.0) || !isfinite(dot)) {
+      S[S_STATUS] = isfinite(dot) ? ST_BREAKDOWN : ST_NONFINITE;
+      return;
+    }
+    const double g = sqrt(dot);
+    S[S_GAMMA_PREV] = 1.0;
+    S[S_GAMMA] = g;
+    S[S_ETA] = g;
+    S[S_C_PREV] = 1.0;
+    S[S_C] = 1.0;
+    S[S_S_PREV] = 0.0;
+    S[S_S] = 0.0;
+    S[S_STATUS] = g == 0.0 ? ST_CONVERGED : ST_RUNNING;
+  } else if (stage == 1) {
+    const double g = S[S_GAMMA];
+    const double delta = dot / (g * g);
+    S[S_DELTA] = delta;
+    S[S_CV0] = 1.0 / g;
+    S[S_CV1] = -delta / g;
+    S[S_CV2] = -g / S[S_GAMMA_PREV];
+    if (!isfinite(delta)) S[S_STATUS] = ST_NONFINITE;
+  } else if (stage == 2) {
+    if (!isfinite(dot)) {
+      S[S_STATUS] = ST_NONFINITE;
+      return;
+    }
+    if (dot < 0.0) S[S_STATUS] = ST_BREAKDOWN;
+    const double gn = dot > 0.0 ? sqrt(dot) : 0.0;
+    const double g = S[S_GAMMA], delta = S[S_DELTA];
+    const double c = S[S_C], cp = S[S_C_PREV], s = S[S_S], sp = S[S_S_PREV], eta = S[S_ETA];
+    const double a0 = c * delta - cp * s * g;
+    const double a1 = hypot(a0, gn);
+    const double a2 = s * delta + cp * c * g;
+    const double a3 = sp * g;
+    const double cn = a0 / a1, sn = gn / a1;
+    const double eta_n = -sn * eta;
+    S[S_CWZ] = 1.0 / (g * a1);
+    S[S_CW0] = -a3 / a1;
+    S[S_CW1] = -a2 / a1;
+    S[S_CX] = cn * eta;
+    S[S_CRR] = sn * sn;
+    S[S_CRV] = gn > 0.0 ? cn * eta_n / gn : 0.0;
+    S[S_GAMMA_PREV] = g;
+    S[S_GAMMA] = gn;
+    S[S_C_PREV] = c;
+    S[S_C] = cn;
+    S[S_S_PREV] = s;
+    S[S_S] = sn;
+    S[S_ETA] = eta_n;
+    if (!isfinite(a1) || a1 == 0.0) S[S_STATUS] = ST_BREAKDOWN;
+  } else {
+    S[S_RNORM2] = dot;
+    S[S_ITER] += 1.0;
+    const double rel = sqrt(dot) / S[S_BNORM];
+    if (!isfinite(rel)) {
+      S[S_STATUS] = ST_NONFINITE;
+    } else if (S[S_STATUS] == ST_RUNNING && (rel <= tol || S[S_GAMMA] == 0.0)) {
+      S[S_STATUS] = ST_CONVERGED;
+    }
+  }
+}
+
+// <basis_i, w> for i < nb, basis vectors stored contiguously with stride nv.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict__ basis,
+                                                       const double *__restrict__ w, size_t nv,
+                                                       double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  double acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
+  }
+  for (int j = 0; j < NB; ++j) {
+    const double r = block_sum(acc[j], red);
+    if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// w += sign * sum_i scal[slot+i] basis_i  (optional partials of ||w||^2)
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
+                                                        const double *__restrict__ basis,
+                                                        size_t nv, const double *__restrict__ scal,
+                                                        int slot, double sign,
+                                                        double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  double c[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) c[j] = sign * scal[slot + j];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    double v = w[i];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v += c[j] * basis[(size_t)j * nv + i];
+    w[i] = v;
+    acc += v * v;
+  }
+  if (partials) {
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  }
+}
+
+// dst = src / sqrt(scal[slot])
+__global__ __launch_bounds__(kThreads) void k_scale_invnorm(double *__restrict__ dst,
+                                                            const double *__restrict__ src,
+                                                            size_t nv,
+                                                            const double *__restrict__ scal,
+                                                            int slot) {
+  const double c = 1.0 / sqrt(scal[slot]);
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads)
+    dst[i] = src[i] * c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(double *__restrict__ dst, double val,
+                                                   size_t count) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * kThreads)
+    dst[i] = val;
+}
+
+}  // namespace
+
+int red_blocks(size_t n) {
+  size_t b = (n + (size_t)kThreads * 4 - 1) / ((size_t)kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  return (int)b;
+}
+
+hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
+                         int *nblocks_out) {
+  MvArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
+           p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface};
+  dim3 grid((p.m + kThreads - 1) / kThreads, 2);
+  ProfScope ps(p, K_MATVEC, 16.0 * p.nvec);
+  hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, a, partials);
+  if (nblocks_out) *nblocks_out = 2 * grid.x;
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
+                      double *b) {
+  RhsArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
+            p.theta, p.tau, sqrt(p.gamma), p.inv_h2, p.d_aface};
+  const size_t nm = (size_t)p.n * p.m;
+  dim3 grid((unsigned)((nm + kThreads - 1) / kThreads));
+  ProfScope ps(p, K_RHS, 8.0 * (2.0 * (p.n + 1) * p.m + p.m + p.nvec));
+  hipLaunchKernelGGL(k_rhs, grid, dim3(kThreads), 0, p.stream, f, g, y0, b, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u) {
+  dim3 grid((p.m + kThreads - 1) / kThreads, 2);
+  ProfScope ps(p, K_RECOVER, 8.0 * (p.nvec + p.nvec + (u ? p.nvec / 2 : 0)));
+  hipLaunchKernelGGL(k_recover, grid, dim3(kThreads), 0, p.stream, x, y, pp, u, p.n, p.m,
+                     p.theta, 1.0 / sqrt(p.gamma), 1.0 / p.gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,
+                           const double *c, int slot, double h0, double h1, double h2) {
+  ProfScope ps(p, K_LINCOMB, 8.0 * p.nvec * (2 + (b ? 1 : 0) + (c ? 1 : 0)));
+  hipLaunchKernelGGL(k_lincomb3, dim3(red_blocks(p.nvec)), dim3(kThreads), 0, p.stream, dst, a,
+                     b, c, p.nvec, p.d_scal, slot, h0, h1, h2);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, int nsum,
+                           int slot) {
+  ProfScope ps(p, K_FINALIZE, 8.0 * count * nsum);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, p.stream, partials, count, nsum,
+                     p.d_scal, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot) {
+  const int nb = red_blocks(p.nvec);
+  hipError_t e;
+  {
+    ProfScope ps(p, K_DOT, 8.0 * p.nvec * (a == b ? 1 : 2));
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, p.stream, a, b, p.nvec, p.d_partials);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  return launch_finalize(p, p.d_partials, nb, 1, slot);
+}
+
+hipError_t launch_minres_update(const wc_plan &p, double *w0, const double *w1,
+                                const double *z, double *x, double *r, const double *vnew) {
+  const int nb = red_blocks(p.nvec);
+  ProfScope ps(p, K_MINRES_UPDATE, 9.0 * 8.0 * p.nvec);
+  hipLaunchKernelGGL(k_minres_update, dim3(nb), dim3(kThreads), 0, p.stream, w0, w1, z, x, r,
+                     vnew, p.nvec, p.d_scal, p.d_partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double tol) {
+  ProfScope ps(p, K_MINRES_SCALAR, 8.0 * nparts);
+  hipLaunchKernelGGL(k_minres_scalar, dim3(1), dim3(kThreads), 0, p.stream, p.d_partials,
+                     nparts, p.d_scal, stage, tol);
+  return hipGetLastError();
+}
+
+template <template <int> class K> struct NbDispatch;
+
+#define WC_NB_CASES(X)                                                                         \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)      \
+  X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)  \
+  X(32)
+
+hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
+                           int slot) {
+  const int g = red_blocks(p.nvec);
+  int done = 0;
+  while (done < nb) {
+    const int chunk = nb - done > 32 ? 32 : nb - done;
+    const double *bs = basis + (size_t)done * p.nvec;
+    hipError_t e;
+    {
+    ProfScope ps(p, K_MULTIDOT, 8.0 * p.nvec * (chunk + 1));
+    switch (chunk) {
+#define CASE_NB(K)                                                                            \
+  case K:                                                                                     \
+    hipLaunchKernelGGL(k_multidot<K>, dim3(g), dim3(kThreads), 0, p.stream, bs, w, p.nvec,    \
+                       p.d_partials);                                                          \
+    break;
+      WC_NB_CASES(CASE_NB)
+#undef CASE_NB
+      default: return hipErrorInvalidValue;
+    }
+    e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    e = launch_finalize(p, p.d_partials, g, chunk, slot + done);
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb, int slot,
+                            double sign, bool norm, int norm_slot) {
+  const int g = red_blocks(p.nvec);
+  int done = 0;
+  while (done < nb) {
+    const int chunk = nb - done > 32 ? 32 : nb - done;
+    const bool last = done + chunk == nb;
+    double *parts = (norm && last) ? p.d_partials : nullptr;
+    const double *bs = basis + (size_t)done * p.nvec;
+    ProfScope ps(p, K_MULTIAXPY, 8.0 * p.nvec * (chunk + 2));
+    switch (chunk) {
+#define CASE_NB(K)                                                                            \
+  case K:                                                                                     \
+    hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, bs, p.nvec,   \
+                       p.d_scal, slot + done, sign, parts);                                    \
+    break;
+      WC_NB_CASES(CASE_NB)
+#undef CASE_NB
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  if (norm) return launch_finalize(p, p.d_partials, g, 1, norm_slot);
+  return hipSuccess;
+}
+
+hipError_t launch_scale(const wc_plan &p, double *dst, const double *src, int slot_inv) {
+  ProfScope ps(p, K_SCALE, 16.0 * p.nvec);
+  hipLaunchKernelGGL(k_scale_invnorm, dim3(red_blocks(p.nvec)), dim3(kThreads), 0, p.stream,
+                     dst, src, p.nvec, p.d_scal, slot_inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count) {
+  size_t b = (count + kThreads * 4 - 1) / (kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  ProfScope ps(p, K_FILL, 8.0 * count);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)b), dim3(kThreads), 0, p.stream, dst, val, count);
+  return hipGetLastError();
+}
+
+}  // namespace wc

@@ -1,0 +1,71 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/wc.h declares, and rejects invalid arguments before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2406_00952_amd", "lib", "libwcirc.so")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "wc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wc_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def wc():
+    if not os.path.exists(LIB):
+        pytest.fail("libwcirc.so is not built (run python -m paper_2406_00952_amd.build)")
+    from paper_2406_00952_amd import wc as mod
+    return mod
+
+
+def test_library_exports_every_declared_symbol(wc):
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(wc.EXPORTED)
+
+
+def test_status_strings(wc):
+    assert wc.status_str(0) == "ok"
+    assert "argument" in wc.status_str(1)
+    assert wc.version().startswith("libwcirc")
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=3), dict(M=0), dict(n=1), dict(theta=0.3), dict(theta=1.2), dict(gamma=0.0),
+    dict(gamma=-1.0), dict(T=0.0), dict(tol=0.0), dict(restart=0), dict(restart=65),
+    dict(maxit=0), dict(gamma=float("nan")),
+])
+def test_invalid_arguments_rejected(wc, bad):
+    args = dict(dims=2, M=31, n=32, T=1.0, theta=0.5, gamma=1e-4)
+    args.update(bad)
+    assert wc.footprint_bytes(**args) == 0
+
+
+def test_abs_ps_requires_constant_coefficient(wc):
+    a = np.ones(2 * 7 * 8)
+    assert wc.footprint_bytes(2, 7, 8, a_face=a, method="minres_abs_ps") == 0
+    assert wc.footprint_bytes(2, 7, 8, a_face=a, method="minres_pms") > 0
+    assert wc.footprint_bytes(2, 7, 8, a_face=-a, method="minres_pms") == 0
+
+
+def test_footprint_grows_with_restart_and_precision(wc):
+    f30 = wc.footprint_bytes(2, 255, 256, restart=30)
+    f10 = wc.footprint_bytes(2, 255, 256, restart=10)
+    nvec = 2 * 256 * 255 * 255 * 8
+    assert f30 - f10 == 20 * nvec
+    fm = wc.footprint_bytes(2, 255, 256, restart=30, precision="mixed")
+    # mixed: FP32 spectral arrays but a flexible basis (30 more vectors)
+    assert fm > f30
+    # MINRES: ten system vectors
+    fmin = wc.footprint_bytes(2, 255, 256, method="minres_abs_ps")
+    assert 10 * nvec < fmin < 10 * nvec + 2 * 256 * 255 * 255 * 16 * 2 + (64 << 20)
