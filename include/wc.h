@@ -89,7 +89,7 @@ typedef struct {
   int precision;      /* wc_precision */
   double tol;         /* stop when ||b - A x||_2 / ||b||_2 <= tol (true residual) */
   int maxit;          /* total Krylov iteration cap */
-  int restart;        /* GMRES restart length (1..64) */
+  int restart;        /* GMRES restart length (1..32) */
   int flexible;       /* GMRES: store preconditioned basis (forced on for WC_MIXED) */
   int mg_max_cycles;  /* multigrid V-cycles per spatial solve (variable a) */
   double mg_tol;      /* multigrid relative residual target (variable a) */

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -86,7 +87,7 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
   (void)pr;
   if (op->method == WC_GMRES_PS) {
     const bool flex = op->flexible || op->precision == WC_MIXED;
-    return (op->restart + 1) + (flex ? op->restart : 1) + 1 + 2;  // V, Z, Wt, B, X
+    return (op->restart + 1) + (flex ? op->restart : 1) + 1 + 2;  // V, Z, T, B, X
   }
   return 8 + 2;  // R V0 V1 Z ZN W0 W1 AZ, B, X
 }
@@ -247,6 +248,12 @@ wc_status run_minres(wc_plan *p, const double *b, double *x, wc_info *info) {
 // ---------------------------------------------------------------------------------
 // GMRES(k), right preconditioned: solve A P^{-1} u = b, x = P^{-1} u.  Flexible form
 // (stores z_j = P^{-1} v_j) when requested or when the preconditioner runs in FP32.
+//
+// Arnoldi with classical Gram-Schmidt and a second projection only when the first one
+// removed more than half of the norm (decided on the device; the second pass launches
+// are no-ops otherwise).  Basis vectors are stored unnormalised (V_j = nu_j v_j, nu_j
+// kept as a device scalar): the matvec writes straight into the next basis slot and no
+// scaling pass is needed; all coefficients are rescaled on the host.
 // ---------------------------------------------------------------------------------
 wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   const int k = p->opts.restart;
@@ -254,8 +261,9 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   const size_t nv = p->nvec;
   double *V = p->vec(0);
   double *Zb = p->vec(k + 1);
-  double *Wt = p->vec(k + 1 + (flex ? k : 1));
+  double *T = p->vec(k + 1 + (flex ? k : 1));
   const double tol = p->opts.tol;
+  const double *gate = p->d_scal + S_REORTH;
   WC_TRY(launch_dot(*p, b, b, S_DOT));
   WC_TRY(sync_read(p, S_DOT, 1));
   const double bnorm = std::sqrt(p->h_scal[S_DOT]);
@@ -265,8 +273,8 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (info) { info->status = WC_OK; info->relres = 0; info->relres_est = 0; }
     return WC_OK;
   }
-  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k);
-  int total = 0, cycles = 0;
+  std::vector<double> H((size_t)(k + 1) * k), cs(k), sn(k), g(k + 1), y(k), nu(k + 1);
+  int total = 0, cycles = 0, reorth = 0;
   bool first = true;
   wc_status st = WC_E_MAXIT;
   double relres = 1.0, relres_est = 1.0;
@@ -274,36 +282,45 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (first) {
       WC_TRY(launch_lincomb3(*p, V, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
     } else {
-      WC_TRY(launch_matvec(*p, x, Wt, p->d_partials, nullptr));
-      WC_TRY(launch_lincomb3(*p, V, b, Wt, nullptr, -1, 1.0, -1.0, 0.0));
+      WC_TRY(launch_matvec(*p, x, T, p->d_partials, nullptr));
+      WC_TRY(launch_lincomb3(*p, V, b, T, nullptr, -1, 1.0, -1.0, 0.0));
     }
-    WC_TRY(launch_dot(*p, V, V, S_BETA));
-    WC_TRY(sync_read(p, S_BETA, 1));
-    const double beta = std::sqrt(p->h_scal[S_BETA]);
+    WC_TRY(launch_dot(*p, V, V, S_NU2));
+    WC_TRY(sync_read(p, S_NU2, 1));
+    const double beta = std::sqrt(p->h_scal[S_NU2]);
     relres = beta / bnorm;
     if (!std::isfinite(relres)) { st = WC_E_NONFINITE; break; }
     if (relres <= tol) { st = WC_OK; break; }
     if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
-    WC_TRY(launch_scale(*p, V, V, S_BETA));
+    nu[0] = beta;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jd = 0;
     bool stop = false;
     for (int j = 0; j < k && !stop; ++j) {
       double *Vj = V + (size_t)j * nv;
+      double *Vn = V + (size_t)(j + 1) * nv;
       double *Zj = flex ? Zb + (size_t)j * nv : Zb;
+      int np = 0;
       WC_TRY(launch_pc_apply(*p, Vj, Zj, false, nullptr));
-      WC_TRY(launch_matvec(*p, Zj, Wt, p->d_partials, nullptr));
-      WC_TRY(launch_multidot(*p, V, j + 1, Wt, S_H1));
-      WC_TRY(launch_multiaxpy(*p, Wt, V, j + 1, S_H1, -1.0, false, 0));
-      WC_TRY(launch_multidot(*p, V, j + 1, Wt, S_H2));
-      WC_TRY(launch_multiaxpy(*p, Wt, V, j + 1, S_H2, -1.0, true, S_HNORM));
-      WC_TRY(launch_scale(*p, V + (size_t)(j + 1) * nv, Wt, S_HNORM));
-      // S_H1..S_H2+j and S_HNORM: one copy of the span [S_HNORM, S_H2 + j]
-      WC_TRY(sync_read(p, S_HNORM, S_H2 + j + 1 - S_HNORM));
-      double *h = &H[(size_t)j * (k + 1)];  // column j
-      for (int i = 0; i <= j; ++i) h[i] = p->h_scal[S_H1 + i] + p->h_scal[S_H2 + i];
-      const double hn = std::sqrt(std::max(p->h_scal[S_HNORM], 0.0));
+      WC_TRY(launch_matvec(*p, Zj, Vn, p->d_partials, nullptr));
+      WC_TRY(launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np));
+      WC_TRY(launch_gs_finalize(*p, 1, j, np));
+      WC_TRY(launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np));
+      WC_TRY(launch_gs_finalize(*p, 2, j, np));
+      WC_TRY(launch_multidot(*p, V, j + 1, Vn, false, gate, &np));
+      WC_TRY(launch_gs_finalize(*p, 3, j, np));
+      WC_TRY(launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np));
+      WC_TRY(launch_gs_finalize(*p, 4, j, np));
+      WC_TRY(sync_read(p, S_WN2, S_D2 + j + 1 - S_WN2));
+      const bool two = p->h_scal[S_REORTH] != 0.0;
+      reorth += two ? 1 : 0;
+      const double nn = std::sqrt(std::max(p->h_scal[S_NU2 + j + 1], 0.0));
+      nu[j + 1] = nn;
+      double *h = &H[(size_t)j * (k + 1)];  // column j of the Hessenberg matrix
+      for (int i = 0; i <= j; ++i)
+        h[i] = (p->h_scal[S_D1 + i] + (two ? p->h_scal[S_D2 + i] : 0.0)) / (nu[i] * nu[j]);
+      const double hn = nn / nu[j];
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * h[i] + sn[i] * h[i + 1];
         h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
@@ -321,20 +338,21 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       if (!std::isfinite(relres_est) || r == 0.0) { stop = true; break; }
       if (relres_est <= tol || hn == 0.0 || total >= p->opts.maxit) stop = true;
     }
-    // back substitution R y = g
+    // back substitution R y = g; the update uses the unnormalised vectors, so y_i / nu_i
     for (int i = jd - 1; i >= 0; --i) {
       double s = g[i];
       for (int l = i + 1; l < jd; ++l) s -= H[(size_t)l * (k + 1) + i] * y[l];
       const double d = H[(size_t)i * (k + 1) + i];
       y[i] = d != 0.0 ? s / d : 0.0;
     }
+    for (int i = 0; i < jd; ++i) y[i] /= nu[i];
     WC_TRY(write_scalar(p, S_Y, y.data(), jd));
     if (flex) {
-      WC_TRY(launch_multiaxpy(*p, x, Zb, jd, S_Y, 1.0, false, 0));
+      WC_TRY(launch_multiaxpy(*p, x, Zb, jd, S_Y, 1.0, false, nullptr, nullptr));
     } else {
-      WC_TRY(launch_fill(*p, Wt, 0.0, nv));
-      WC_TRY(launch_multiaxpy(*p, Wt, V, jd, S_Y, 1.0, false, 0));
-      WC_TRY(launch_pc_apply(*p, Wt, Zb, false, nullptr));
+      WC_TRY(launch_fill(*p, T, 0.0, nv));
+      WC_TRY(launch_multiaxpy(*p, T, V, jd, S_Y, 1.0, false, nullptr, nullptr));
+      WC_TRY(launch_pc_apply(*p, T, Zb, false, nullptr));
       WC_TRY(launch_lincomb3(*p, x, x, Zb, nullptr, -1, 1.0, 1.0, 0.0));
     }
     first = false;
@@ -461,7 +479,16 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   p->opts = *opts;
   p->stream = (hipStream_t)stream;
   p->nvec = 2 * (size_t)p->n * p->m;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      p->num_cu = cus;
+  }
   const Sizes sz = sizes_of(prob, opts);
+  if (const char *e = std::getenv("WC_TS")) p->ts_time = std::atoi(e);
+  if (const char *e = std::getenv("WC_TX")) p->tx_cols = std::atoi(e);
 
   // ---- FP64 tables ----
   const int n = p->n, N1 = p->N1, M = p->M;

@@ -13,7 +13,7 @@ namespace wc {
 
 constexpr int kThreads = 256;        // threads per workgroup for every kernel
 constexpr int kRedBlocks = 1024;     // max workgroups of the streaming reductions
-constexpr int kMaxRestart = 64;
+constexpr int kMaxRestart = 32;
 constexpr int kMaxPartials = 1 << 16;
 
 template <typename T>
@@ -32,12 +32,18 @@ enum ScalarSlot : int {
   S_CV0 = 16, S_CV1, S_CV2,
   // w/x/r update
   S_CWZ = 20, S_CW0, S_CW1, S_CX, S_CRR, S_CRV,
-  // GMRES
-  S_BETA = 32, S_HNORM, S_INVH,
-  S_H1 = 64,     // kMaxRestart+1 values
-  S_H2 = 160,    // kMaxRestart+1 values
-  S_Y = 256,     // kMaxRestart values (least-squares solution)
-  S_DOT = 340,   // scratch dot results
+  // GMRES: classical Gram-Schmidt with a DGKS-triggered second pass; basis vectors are
+  // stored unnormalised and their squared norms kept here
+  S_WN2 = 32,    // ||w||^2 before projection
+  S_WP2,         // ||w'||^2 after the first projection
+  S_WPP2,        // ||w''||^2 after the second projection (when taken)
+  S_REORTH,      // 1 when the second projection is needed
+  S_NU2 = 64,    // kMaxRestart+1 squared norms of the stored basis vectors
+  S_D1 = 104,    // kMaxRestart+1 raw dots <V_i, w>, first pass
+  S_D2 = 144,    // second pass
+  S_GSC = 184,   // kMaxRestart+1 projection coefficients of the current pass
+  S_Y = 224,     // kMaxRestart update coefficients
+  S_DOT = 300,   // scratch dot results
   S_COUNT = 512
 };
 
@@ -73,6 +79,9 @@ struct wc_plan {
   double tau = 0, alpha = 0, h = 0, inv_h2 = 0;
   bool var_coeff = false;
   bool pc_ok = false;            // the GPU preconditioner covers this problem
+  int num_cu = 256;              // compute units of the plan's device
+  int ts_time = 0;               // time-FFT tile width (0: default)
+  int tx_cols = 0;               // x2-pass tile width (0: default)
   wc_opts opts{};
   hipStream_t stream = nullptr;
   size_t nvec = 0;          // 2*n*m
@@ -148,13 +157,18 @@ hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, 
 hipError_t launch_minres_update(const wc_plan &p, double *w0, const double *w1,
                                 const double *z, double *x, double *r, const double *vnew);
 hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double tol);
+// <basis_i, w> for i < nb (plus <w, w> when self) -> partials [sum][block]; *nblocks out.
+// gate (device pointer or null): the launch does nothing when *gate == 0.
 hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
-                           int slot);
+                           bool self, const double *gate, int *nblocks);
+// w += sign * sum_i scal[slot+i] basis_i; partials of ||w||^2 when norm.
 hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb,
-                            int slot, double sign, bool norm, int norm_slot);
-hipError_t launch_scale(const wc_plan &p, double *dst, const double *src, int slot_inv);
+                            int slot, double sign, bool norm, const double *gate,
+                            int *nblocks);
+// Gram-Schmidt bookkeeping of GMRES iteration j (one block): stage 1 first-pass dots,
+// 2 first-pass norm and DGKS test, 3 second-pass dots, 4 second-pass norm.
+hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count);
 hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count);
-hipError_t launch_gmres_scalar(const wc_plan &p, int stage, int j);
 
 // ---- preconditioner (wc_pc.hip) --------------------------------------------
 // w = P^{-1} v.  With dot = true the last pass also writes per-block partial sums of

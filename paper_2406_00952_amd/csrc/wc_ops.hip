@@ -104,26 +104,38 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
     const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
     const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
     double zprev = 0.0, xprev = 0.0;
-#pragma unroll 4
-    for (int kk = 0; kk < a.n; ++kk) {
-      const int k = dir == 0 ? kk : a.n - 1 - kk;
-      const double *xk = xs + (size_t)k * a.m;
-      const double xc = xk[s];
-      const double kx = apply_stencil(st, xk, s);
-      const double xok = xo[(size_t)k * a.m + s];
-      double out;
-      if (dir == 0) {
-        const double z = (xc - xprev - omt * zprev) * ith;
-        out = z + a.tau * kx - a.alpha * xok;
-        zprev = z;
-        xprev = xc;
-      } else {
-        const double u = (xc - omt * zprev) * ith;
-        out = (u - zprev) + a.tau * kx + a.alpha * xok;
-        zprev = u;
+    // the loads of KB time levels are issued before the recurrence consumes them
+    constexpr int KB = 8;
+    for (int kk0 = 0; kk0 < a.n; kk0 += KB) {
+      double xc[KB], kx[KB], xok[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int kk = kk0 + u < a.n ? kk0 + u : a.n - 1;
+        const int k = dir == 0 ? kk : a.n - 1 - kk;
+        const double *xk = xs + (size_t)k * a.m;
+        xc[u] = xk[s];
+        kx[u] = apply_stencil(st, xk, s);
+        xok[u] = xo[(size_t)k * a.m + s];
       }
-      yo[(size_t)k * a.m + s] = out;
-      acc += out * (a.sym ? xok : xc);
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int kk = kk0 + u;
+        if (kk >= a.n) break;
+        const int k = dir == 0 ? kk : a.n - 1 - kk;
+        double out;
+        if (dir == 0) {
+          const double z = (xc[u] - xprev - omt * zprev) * ith;
+          out = z + a.tau * kx[u] - a.alpha * xok[u];
+          zprev = z;
+          xprev = xc[u];
+        } else {
+          const double uu = (xc[u] - omt * zprev) * ith;
+          out = (uu - zprev) + a.tau * kx[u] + a.alpha * xok[u];
+          zprev = uu;
+        }
+        yo[(size_t)k * a.m + s] = out;
+        acc += out * (a.sym ? xok[u] : xc[u]);
+      }
     }
   }
   const double r = block_sum(acc, red);
@@ -343,34 +355,41 @@ __global__ __launch_bounds__(kThreads) void k_minres_scalar(const double *__rest
   }
 }
 
-// <basis_i, w> for i < nb, basis vectors stored contiguously with stride nv.
-template <int NB>
+// <basis_i, w> for i < NB (and <w, w> when SELF), basis vectors contiguous with stride nv.
+// partials[j * gridDim.x + block].  Does nothing when gate && *gate == 0.
+template <int NB, bool SELF>
 __global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict__ basis,
                                                        const double *__restrict__ w, size_t nv,
-                                                       double *__restrict__ partials) {
+                                                       double *__restrict__ partials,
+                                                       const double *__restrict__ gate) {
+  if (gate && *gate == 0.0) return;
   __shared__ double red[kThreads / 64];
-  double acc[NB];
+  constexpr int NS = NB + (SELF ? 1 : 0);
+  double acc[NS];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+  for (int j = 0; j < NS; ++j) acc[j] = 0.0;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
        i += (size_t)gridDim.x * kThreads) {
     const double wi = w[i];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
+    if (SELF) acc[NS - 1] += wi * wi;
   }
-  for (int j = 0; j < NB; ++j) {
+  for (int j = 0; j < NS; ++j) {
     const double r = block_sum(acc[j], red);
     if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = r;
   }
 }
 
-// w += sign * sum_i scal[slot+i] basis_i  (optional partials of ||w||^2)
+// w += sign * sum_i scal[slot+i] basis_i  (optional partials of ||w||^2); gated like above
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
                                                         const double *__restrict__ basis,
                                                         size_t nv, const double *__restrict__ scal,
                                                         int slot, double sign,
-                                                        double *__restrict__ partials) {
+                                                        double *__restrict__ partials,
+                                                        const double *__restrict__ gate) {
+  if (gate && *gate == 0.0) return;
   __shared__ double red[kThreads / 64];
   double c[NB];
 #pragma unroll
@@ -390,16 +409,45 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
   }
 }
 
-// dst = src / sqrt(scal[slot])
-__global__ __launch_bounds__(kThreads) void k_scale_invnorm(double *__restrict__ dst,
-                                                            const double *__restrict__ src,
-                                                            size_t nv,
-                                                            const double *__restrict__ scal,
-                                                            int slot) {
-  const double c = 1.0 / sqrt(scal[slot]);
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads)
-    dst[i] = src[i] * c;
+// Gram-Schmidt bookkeeping for GMRES iteration j (basis V_0..V_j, new vector w).
+//  stage 1: D1_i = <V_i, w>, WN2 = ||w||^2, GSC_i = D1_i / NU2_i
+//  stage 2: WP2 = ||w'||^2; REORTH = WP2 < WN2/2 (the projection removed more than half of
+//           the norm: orthogonality may be lost, project again); else NU2_{j+1} = WP2
+//  stage 3 (when REORTH): D2_i = <V_i, w'>, GSC_i = D2_i / NU2_i
+//  stage 4 (when REORTH): WPP2 = ||w''||^2, NU2_{j+1} = WPP2
+__global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restrict__ partials,
+                                                          int count, double *__restrict__ S,
+                                                          int stage, int j) {
+  __shared__ double red[kThreads / 64];
+  if ((stage == 3 || stage == 4) && S[S_REORTH] == 0.0) return;
+  const int nsum = stage == 1 ? j + 2 : (stage == 3 ? j + 1 : 1);
+  for (int t = 0; t < nsum; ++t) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kThreads) acc += partials[(size_t)t * count + i];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+      if (stage == 1) {
+        if (t <= j) {
+          S[S_D1 + t] = r;
+          S[S_GSC + t] = r / S[S_NU2 + t];
+        } else {
+          S[S_WN2] = r;
+        }
+      } else if (stage == 2) {
+        S[S_WP2] = r;
+        const bool again = r < 0.5 * S[S_WN2];
+        S[S_REORTH] = again ? 1.0 : 0.0;
+        S[S_WPP2] = r;
+        if (!again) S[S_NU2 + j + 1] = r;
+      } else if (stage == 3) {
+        S[S_D2 + t] = r;
+        S[S_GSC + t] = r / S[S_NU2 + t];
+      } else {
+        S[S_WPP2] = r;
+        S[S_NU2 + j + 1] = r;
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(double *__restrict__ dst, double val,
@@ -492,75 +540,56 @@ hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double 
   return hipGetLastError();
 }
 
-template <template <int> class K> struct NbDispatch;
-
 #define WC_NB_CASES(X)                                                                         \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)      \
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)  \
   X(32)
 
 hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
-                           int slot) {
+                           bool self, const double *gate, int *nblocks) {
   const int g = red_blocks(p.nvec);
-  int done = 0;
-  while (done < nb) {
-    const int chunk = nb - done > 32 ? 32 : nb - done;
-    const double *bs = basis + (size_t)done * p.nvec;
-    hipError_t e;
-    {
-    ProfScope ps(p, K_MULTIDOT, 8.0 * p.nvec * (chunk + 1));
-    switch (chunk) {
-#define CASE_NB(K)                                                                            \
-  case K:                                                                                     \
-    hipLaunchKernelGGL(k_multidot<K>, dim3(g), dim3(kThreads), 0, p.stream, bs, w, p.nvec,    \
-                       p.d_partials);                                                          \
+  if (nblocks) *nblocks = g;
+  ProfScope ps(p, K_MULTIDOT, 8.0 * p.nvec * (nb + 1));
+  switch (nb) {
+#define CASE_NB(K)                                                                           \
+  case K:                                                                                    \
+    if (self)                                                                                \
+      hipLaunchKernelGGL((k_multidot<K, true>), dim3(g), dim3(kThreads), 0, p.stream, basis, \
+                         w, p.nvec, p.d_partials, gate);                                     \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_multidot<K, false>), dim3(g), dim3(kThreads), 0, p.stream,       \
+                         basis, w, p.nvec, p.d_partials, gate);                              \
     break;
-      WC_NB_CASES(CASE_NB)
+    WC_NB_CASES(CASE_NB)
 #undef CASE_NB
-      default: return hipErrorInvalidValue;
-    }
-    e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    e = launch_finalize(p, p.d_partials, g, chunk, slot + done);
-    if (e != hipSuccess) return e;
-    done += chunk;
+    default: return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb, int slot,
-                            double sign, bool norm, int norm_slot) {
+                            double sign, bool norm, const double *gate, int *nblocks) {
   const int g = red_blocks(p.nvec);
-  int done = 0;
-  while (done < nb) {
-    const int chunk = nb - done > 32 ? 32 : nb - done;
-    const bool last = done + chunk == nb;
-    double *parts = (norm && last) ? p.d_partials : nullptr;
-    const double *bs = basis + (size_t)done * p.nvec;
-    ProfScope ps(p, K_MULTIAXPY, 8.0 * p.nvec * (chunk + 2));
-    switch (chunk) {
+  if (nblocks) *nblocks = g;
+  double *parts = norm ? p.d_partials : nullptr;
+  ProfScope ps(p, K_MULTIAXPY, 8.0 * p.nvec * (nb + 2));
+  switch (nb) {
 #define CASE_NB(K)                                                                            \
   case K:                                                                                     \
-    hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, bs, p.nvec,   \
-                       p.d_scal, slot + done, sign, parts);                                    \
+    hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, basis, p.nvec, \
+                       p.d_scal, slot, sign, parts, gate);                                    \
     break;
-      WC_NB_CASES(CASE_NB)
+    WC_NB_CASES(CASE_NB)
 #undef CASE_NB
-      default: return hipErrorInvalidValue;
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    done += chunk;
+    default: return hipErrorInvalidValue;
   }
-  if (norm) return launch_finalize(p, p.d_partials, g, 1, norm_slot);
-  return hipSuccess;
+  return hipGetLastError();
 }
 
-hipError_t launch_scale(const wc_plan &p, double *dst, const double *src, int slot_inv) {
-  ProfScope ps(p, K_SCALE, 16.0 * p.nvec);
-  hipLaunchKernelGGL(k_scale_invnorm, dim3(red_blocks(p.nvec)), dim3(kThreads), 0, p.stream,
-                     dst, src, p.nvec, p.d_scal, slot_inv);
+hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count) {
+  ProfScope ps(p, K_FINALIZE, 8.0 * count * (j + 2));
+  hipLaunchKernelGGL(k_gs_finalize, dim3(1), dim3(kThreads), 0, p.stream, p.d_partials, count,
+                     p.d_scal, stage, j);
   return hipGetLastError();
 }
 

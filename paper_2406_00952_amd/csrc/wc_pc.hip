@@ -16,9 +16,13 @@
 // complex FFT with O(N1) pre/post-processing (even outputs directly, odd outputs as a
 // running sum).  All normalisations (1/n and (2/N1)^dims) are folded into step 2.
 //
-// Passes over HBM (2D): time FFT, x1-DST (written x2-contiguous), fused [x2-DST, step 2,
-// x2-iDST], x1-iDST (written back x1-contiguous), inverse time FFT.  1D: three passes.
-// Every FFT is a Stockham radix-8/4/2 transform staged in LDS.
+// Passes over HBM (2D): [time FFT], [x1-DST, rows in place], [x2-DST, step 2, x2-iDST on
+// column tiles in place], [x1-iDST, rows in place], [inverse time FFT].  1D: [time FFT],
+// [DST, step 2, iDST on rows], [inverse time FFT].
+//
+// Every FFT is a Stockham radix-8/4/2 transform executed by ONE wavefront on lines it owns
+// in LDS; waves synchronise only themselves, so the four waves of a workgroup never wait
+// on each other between stages.  The DST running sum is a segmented wave-shuffle scan.
 
 #include "wc_internal.h"
 
@@ -33,6 +37,26 @@ template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
 template <typename T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
 template <typename T> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
+
+// Orders the LDS accesses of one wavefront (LDS operations of a wave complete in order;
+// this stops the compiler from moving them across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS position of FFT index k: one pad slot every 2^PS elements breaks the power-of-two
+// strides of the Stockham writes so the lanes of a wave hit distinct banks.
+template <int PS> __device__ __forceinline__ int pk(int k) { return k + (k >> PS); }
+template <int PS> constexpr int padded(int n) { return n + (n >> PS) + 1; }
+
+template <typename T> __device__ __forceinline__ cx<T> shfl_up_cx(cx<T> v, int d) {
+  return cx<T>{__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64)};
+}
+template <typename T> __device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src) {
+  return cx<T>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
 
 // ---- small DFTs in registers, natural order in and out ---------------------
 template <typename T, bool INV> __device__ __forceinline__ void dft2(cx<T> *v) {
@@ -73,141 +97,179 @@ template <typename T, int R, bool INV> __device__ __forceinline__ void dftR(cx<T
   else dft8<T, INV>(v);
 }
 
-// One Stockham stage on B batched sequences of length N stored as buf[k*B + b].
-// tw[p] = e^{-2 pi i p/N}.  All reads of the stage complete before any write.
-template <typename T, int N, int R, int NS, int B, bool INV>
-__device__ __forceinline__ void fft_stage(cx<T> *buf, const cx<T> *__restrict__ tw, int tid) {
+// One Stockham stage executed by one wave on B lines of length N stored at
+// buf[pk(k)*S + b].  tw[p] = e^{-2 pi i p/N} (LDS or global).  Butterfly index j runs
+// fastest across lanes.  For radix 8 only w^1 and w^2 are looked up; w^3..w^7 are
+// products of those.
+template <typename T, int N, int R, int NS, int B, int S, int PS, bool INV>
+__device__ __forceinline__ void wstage(cx<T> *buf, const cx<T> *__restrict__ tw, int lane) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NB * B;
-  constexpr int IT = (TOTAL + kThreads - 1) / kThreads;
+  constexpr int IT = (TOTAL + 63) / 64;
   cx<T> v[IT][R];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (TOTAL % kThreads == 0 || idx < TOTAL) {
-      const int b = idx % B, j = idx / B;
+    const int idx = lane + 64 * it;
+    if (TOTAL % 64 == 0 || idx < TOTAL) {
+      const int j = idx % NB, b = idx / NB;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * NB) * B + b];
+      for (int r = 0; r < R; ++r) v[it][r] = buf[pk<PS>(j + r * NB) * S + b];
       if constexpr (NS > 1) {
         const int k = j % NS;
+        constexpr int STEP = N / (NS * R);
+        cx<T> w[R];
+        w[1] = tw[k * STEP];
+        if constexpr (R >= 4) w[2] = tw[2 * k * STEP];
+        if constexpr (R >= 4) w[3] = cmul(w[1], w[2]);
+        if constexpr (R == 8) {
+          w[4] = cmul(w[2], w[2]);
+          w[5] = cmul(w[1], w[4]);
+          w[6] = cmul(w[2], w[4]);
+          w[7] = cmul(w[3], w[4]);
+        }
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[k * r * (N / (NS * R))];
-          if (INV) w.y = -w.y;
-          v[it][r] = cmul(v[it][r], w);
+          cx<T> ww = w[r];
+          if (INV) ww.y = -ww.y;
+          v[it][r] = cmul(v[it][r], ww);
         }
       }
       dftR<T, R, INV>(v[it]);
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (TOTAL % kThreads == 0 || idx < TOTAL) {
-      const int b = idx % B, j = idx / B;
-      const int k = j % NS;
-      const int base = (j / NS) * NS * R + k;
+    const int idx = lane + 64 * it;
+    if (TOTAL % 64 == 0 || idx < TOTAL) {
+      const int j = idx % NB, b = idx / NB;
+      const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * NS) * B + b] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[pk<PS>(base + r * NS) * S + b] = v[it][r];
     }
   }
-  __syncthreads();
+  wave_sync();
 }
 
-// Complete length-N FFT (forward e^{-2 pi i}, inverse unnormalised e^{+2 pi i}).
-template <typename T, int N, int NS, int B, bool INV>
-__device__ __forceinline__ void fft_lds(cx<T> *buf, const cx<T> *__restrict__ tw, int tid) {
+template <typename T, int N, int NS, int B, int S, int PS, bool INV>
+__device__ __forceinline__ void wfft(cx<T> *buf, const cx<T> *__restrict__ tw, int lane) {
   if constexpr (NS < N) {
     constexpr int REM = N / NS;
     constexpr int R = REM >= 8 ? 8 : REM;
-    fft_stage<T, N, R, NS, B, INV>(buf, tw, tid);
-    fft_lds<T, N, NS * R, B, INV>(buf, tw, tid);
+    wstage<T, N, R, NS, B, S, PS, INV>(buf, tw, lane);
+    wfft<T, N, NS * R, B, S, PS, INV>(buf, tw, lane);
   }
 }
 
 // Unnormalised DST-I, Y_j = sum_{i=1}^{N1-1} x_i sin(pi i j/N1), of B complex lines held
-// in buf[i*B + b] (i = 1..N1-1; slot 0 is scratch).  Result in the same slots.
+// by one wave at buf[i*S + b] (i = 1..N1-1; slot 0 is scratch).  Result in the same slots.
 //   y_i = sin(pi i/N1)(x_i + x_{N1-i}) + (x_i - x_{N1-i})/2,  F = FFT_N1(y)
 //   C_k = (F_k + F_{N1-k})/2,  S_k = i (F_k - F_{N1-k})/2
 //   Y_{2k} = S_k,  Y_{2k+1} = C_0/2 + C_1 + ... + C_k
-template <typename T, int N1, int B>
-__device__ __forceinline__ void dst_lds(cx<T> *buf, const cx<T> *__restrict__ tw,
-                                        const T *__restrict__ sintab, int tid) {
+template <typename T, int N1, int B, int S, int PS>
+__device__ __forceinline__ void wdst(cx<T> *buf, const cx<T> *__restrict__ tw,
+                                     const T *__restrict__ sintab, int lane) {
   constexpr int H = N1 / 2;
   constexpr int ITEMS = H * B;
-  constexpr int IT = (ITEMS + kThreads - 1) / kThreads;
-  for (int idx = tid; idx < ITEMS; idx += kThreads) {
-    const int b = idx % B, i = idx / B + 1;
-    const cx<T> xa = buf[i * B + b];
-    const cx<T> xb = buf[(N1 - i) * B + b];
+  for (int idx = lane; idx < ITEMS; idx += 64) {
+    const int i = 1 + idx % H, b = idx / H;
+    const cx<T> xa = buf[pk<PS>(i) * S + b];
+    const cx<T> xb = buf[pk<PS>(N1 - i) * S + b];
     const T s = sintab[i];
     const cx<T> sum = cadd(xa, xb);
     const cx<T> dif = cscale(csub(xa, xb), (T)0.5);
-    buf[i * B + b] = cadd(cscale(sum, s), dif);
-    if (i != H) buf[(N1 - i) * B + b] = csub(cscale(sum, s), dif);
+    buf[pk<PS>(i) * S + b] = cadd(cscale(sum, s), dif);
+    if (i != H) buf[pk<PS>(N1 - i) * S + b] = csub(cscale(sum, s), dif);
     if (i == 1) buf[b] = cx<T>{(T)0, (T)0};
   }
-  __syncthreads();
-  fft_lds<T, N1, 1, B, false>(buf, tw, tid);
-  cx<T> cc[IT], ss[IT];
+  wave_sync();
+  wfft<T, N1, 1, B, S, PS, false>(buf, tw, lane);
+  // post-processing: every lane owns CH consecutive k of one line; the running sum is a
+  // sequential scan inside the chunk plus a shuffle scan of the chunk totals.
+  constexpr int CH = ITEMS >= 64 ? ITEMS / 64 : 1;
+  constexpr int G = H / CH;  // lanes per line
+  const int b = lane / G, g = lane % G, k0 = g * CH;
+  const bool valid = b < B;
+  cx<T> cc[CH], ss[CH];
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (ITEMS % kThreads == 0 || idx < ITEMS) {
-      const int b = idx % B, k = idx / B;
-      const cx<T> Fk = buf[k * B + b];
-      const cx<T> Fm = buf[((N1 - k) & (N1 - 1)) * B + b];
+  for (int c = 0; c < CH; ++c) {
+    cc[c] = cx<T>{(T)0, (T)0};
+    ss[c] = cx<T>{(T)0, (T)0};
+    if (valid) {
+      const int k = k0 + c;
+      const cx<T> Fk = buf[pk<PS>(k) * S + b];
+      const cx<T> Fm = buf[pk<PS>((N1 - k) & (N1 - 1)) * S + b];
       cx<T> C = cscale(cadd(Fk, Fm), (T)0.5);
       if (k == 0) C = cscale(C, (T)0.5);
-      cc[it] = C;
-      ss[it] = mul_i(cscale(csub(Fk, Fm), (T)0.5));
+      cc[c] = C;
+      ss[c] = mul_i(cscale(csub(Fk, Fm), (T)0.5));
     }
   }
-  __syncthreads();
 #pragma unroll
-  for (int it = 0; it < IT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (ITEMS % kThreads == 0 || idx < ITEMS) {
-      const int b = idx % B, k = idx / B;
-      buf[(2 * k + 1) * B + b] = cc[it];
-      if (k > 0) buf[(2 * k) * B + b] = ss[it];
+  for (int c = 1; c < CH; ++c) cc[c] = cadd(cc[c], cc[c - 1]);
+  const cx<T> tot = cc[CH - 1];
+  cx<T> inc = tot;
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const cx<T> y = shfl_up_cx(inc, off);
+    if (g >= off) inc = cadd(inc, y);
+  }
+  const cx<T> excl = csub(inc, tot);
+  wave_sync();
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int k = k0 + c;
+      buf[pk<PS>(2 * k + 1) * S + b] = cadd(cc[c], excl);
+      if (k > 0) buf[pk<PS>(2 * k) * S + b] = ss[c];
     }
   }
-  __syncthreads();
-  // inclusive running sum over the odd slots 2k+1, k = 0..H-1 (Hillis-Steele)
-#pragma unroll 1
-  for (int off = 1; off < H; off <<= 1) {
-    cx<T> val[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = tid + it * kThreads;
-      if (ITEMS % kThreads == 0 || idx < ITEMS) {
-        const int b = idx % B, k = idx / B;
-        cx<T> v = buf[(2 * k + 1) * B + b];
-        if (k >= off) v = cadd(v, buf[(2 * (k - off) + 1) * B + b]);
-        val[it] = v;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = tid + it * kThreads;
-      if (ITEMS % kThreads == 0 || idx < ITEMS) {
-        const int b = idx % B, k = idx / B;
-        buf[(2 * k + 1) * B + b] = val[it];
-      }
-    }
-    __syncthreads();
-  }
+  wave_sync();
 }
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-template <typename P, int N> struct TileCfg {
-  static constexpr int kLds = 65536;
-  static constexpr int TS = clampi(kLds / (N * 2 * (int)sizeof(P)), 1, 16);    // time FFT columns
-  static constexpr int L = clampi(kLds / (N * 2 * (int)sizeof(P)), 1, 16);     // DST lines
-  static constexpr int U = clampi(kLds / (N * 4 * (int)sizeof(P)), 1, 8);      // paired line units
+constexpr int oddize(int b) { return b <= 2 ? b : (b | 1); }
+
+// LDS budget of a tile workgroup: two such workgroups fit in the 160 KiB of a gfx950 CU.
+constexpr int kTileLds = 81920;
+constexpr int kCuLds = 163840;
+constexpr int blocks_per_cu(int lds) { return lds > 0 ? kCuLds / lds : 0; }
+
+// Time FFT tile: TS spatial columns x N time levels (4 waves, TS/4 columns each).
+template <typename P, int N, int TS> struct TimeCfg {
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 4;
+  static constexpr int PN = padded<PS>(N);
+  static constexpr int S = TS + 1;  // odd column stride
+  static constexpr int TILE = PN * S * CXB;
+  static constexpr bool FITS = TILE <= kCuLds - 1024;
+  // twiddles in LDS when that does not cost a resident workgroup
+  static constexpr bool TW_LDS = blocks_per_cu(TILE + N * CXB) == blocks_per_cu(TILE);
+};
+
+template <typename P, int N1> struct RowCfg {
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 3;
+  static constexpr int PN = padded<PS>(N1);
+  static constexpr int B = clampi(512 / N1, 1, 64);     // lines per wave
+  static constexpr int S = oddize(B);
+  static constexpr int UNITS = clampi(256 / N1, 1, 32);  // paired units per wave (1D)
+  static constexpr int SU = oddize(2 * UNITS);
+  static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);  // twiddles + sine table
+  static constexpr int WPB = clampi((kTileLds - TAB) / (PN * S * CXB), 1, 4);   // waves/block
+  static constexpr int WPBU = clampi((kTileLds - TAB) / (PN * SU * CXB), 1, 4);
+};
+
+// x2 pass tile: TX x1-columns of both block rows (4 waves, TX/4 columns each).
+template <typename P, int N1, int TX> struct ColCfg {
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 4;
+  static constexpr int PN = padded<PS>(N1);
+  static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);
+  static constexpr int S = 2 * TX + 1;
+  static constexpr int TILE = PN * S * CXB;
+  static constexpr bool FITS = TILE <= kCuLds - 1024;
+  static constexpr bool TAB_LDS = blocks_per_cu(TILE + TAB) == blocks_per_cu(TILE);
 };
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -224,35 +286,83 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// ---- per-mode operation of step 2 ---------------------------------------------
+// kind 0: P_S, [a; b] <- c [[conj(L), alpha], [-alpha, L]] [a; b] / (|L|^2 + alpha^2)
+// kind 1: |P_S|, scale c / sqrt(|L|^2 + alpha^2);  kind 2: P_MS, c / (sigma_l + tau mu)
+template <typename P>
+__device__ __forceinline__ void mode_op(cx<P> &a, cx<P> &b, cx<P> l, P musum, int kind, P tau,
+                                        P alpha, P cnorm) {
+  if (kind == 0) {
+    const cx<P> Lm = {l.x + tau * musum, l.y};
+    const P c = cnorm / (Lm.x * Lm.x + Lm.y * Lm.y + alpha * alpha);
+    const cx<P> ca = {Lm.x * a.x + Lm.y * a.y, Lm.x * a.y - Lm.y * a.x};
+    const cx<P> lb = cmul(Lm, b);
+    const cx<P> na = cscale(cx<P>{ca.x + alpha * b.x, ca.y + alpha * b.y}, c);
+    const cx<P> nb = cscale(cx<P>{lb.x - alpha * a.x, lb.y - alpha * a.y}, c);
+    a = na;
+    b = nb;
+  } else {
+    P s;
+    if (kind == 1) {
+      const P re = l.x + tau * musum;
+      s = cnorm / sqrt(re * re + l.y * l.y + alpha * alpha);
+    } else {
+      s = cnorm / (sqrt(l.x * l.x + l.y * l.y + alpha * alpha) + tau * musum);
+    }
+    a = cscale(a, s);
+    b = cscale(b, s);
+  }
+}
+
 // ---- step 1a: time transform of both block rows ------------------------------
 // v: 2 x (n, m) FP64.  W: [q][half][s] complex, q = 0..n/2-1 <-> frequency l = q+1.
-template <typename P, int N, int TS>
+template <typename P, int N, int TS_>
 __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict__ v,
                                                        cx<P> *__restrict__ W,
                                                        const cx<double> *__restrict__ dtw,
-                                                       const cx<P> *__restrict__ tw, int m) {
-  __shared__ cx<P> buf[N * TS];
-  const int tid = threadIdx.x;
+                                                       const cx<P> *__restrict__ twg, int m) {
+  using C = TimeCfg<P, N, TS_>;
+  constexpr int TS = TS_, S = C::S, PS = C::PS;
+  __shared__ cx<P> buf[C::PN * S];
+  __shared__ cx<P> stw[C::TW_LDS ? N : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = blockIdx.x * TS;
   const double *v1 = v;
   const double *v2 = v + (size_t)N * m;
-  for (int idx = tid; idx < N * TS; idx += kThreads) {
+  // all global loads of the tile are issued before any is consumed
+  constexpr int LIT = (N * TS + kThreads - 1) / kThreads;
+  double ra[LIT], rb[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
     const int k = idx / TS, s = idx % TS, gs = s0 + s;
-    double a = 0.0, b = 0.0;
-    if (gs < m) {
-      a = v1[(size_t)k * m + gs];
-      b = v2[(size_t)k * m + gs];
+    ra[it] = 0.0;
+    rb[it] = 0.0;
+    if ((N * TS % kThreads == 0 || idx < N * TS) && gs < m) {
+      ra[it] = v1[(size_t)k * m + gs];
+      rb[it] = v2[(size_t)k * m + gs];
     }
-    const cx<double> d = dtw[k];
-    buf[idx] = cx<P>{(P)(a * d.x - b * d.y), (P)(a * d.y + b * d.x)};
+  }
+  if constexpr (C::TW_LDS)
+    for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
+    if (N * TS % kThreads == 0 || idx < N * TS) {
+      const int k = idx / TS, s = idx % TS;
+      const cx<double> d = dtw[k];
+      const double a = ra[it], b = rb[it];
+      buf[pk<PS>(k) * S + s] = cx<P>{(P)(a * d.x - b * d.y), (P)(a * d.y + b * d.x)};
+    }
   }
   __syncthreads();
-  fft_lds<P, N, 1, TS, false>(buf, tw, tid);
+  wfft<P, N, 1, TS / 4, S, PS, false>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  __syncthreads();
   for (int idx = tid; idx < (N / 2) * TS; idx += kThreads) {
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
     if (gs >= m) continue;
-    const cx<P> Zl = buf[(q + 1) * TS + s];
-    const cx<P> Zp = buf[((N - q) & (N - 1)) * TS + s];  // frequency (1-l) mod n
+    const cx<P> Zl = buf[pk<PS>(q + 1) * S + s];
+    const cx<P> Zp = buf[pk<PS>((N - q) & (N - 1)) * S + s];  // frequency (1-l) mod n
     const cx<P> A = {(Zl.x + Zp.x) * (P)0.5, (Zl.y - Zp.y) * (P)0.5};
     const cx<P> D = {(Zl.x - Zp.x) * (P)0.5, (Zl.y + Zp.y) * (P)0.5};
     W[((size_t)q * 2 + 0) * m + gs] = A;
@@ -261,36 +371,56 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
 }
 
 // ---- step 3b: inverse time transform, real output, optional fused <w, dotv> ----
-template <typename P, int N, int TS>
+template <typename P, int N, int TS_>
 __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
                                                        double *__restrict__ out,
                                                        const cx<double> *__restrict__ dtw,
-                                                       const cx<P> *__restrict__ tw, int m,
+                                                       const cx<P> *__restrict__ twg, int m,
                                                        const double *__restrict__ dotv,
                                                        double *__restrict__ partials) {
-  __shared__ cx<P> buf[N * TS];
+  using C = TimeCfg<P, N, TS_>;
+  constexpr int TS = TS_, S = C::S, PS = C::PS;
+  __shared__ cx<P> buf[C::PN * S];
+  __shared__ cx<P> stw[C::TW_LDS ? N : 1];
   __shared__ double red[kThreads / 64];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = blockIdx.x * TS;
-  for (int idx = tid; idx < (N / 2) * TS; idx += kThreads) {
+  constexpr int HT = (N / 2) * TS;
+  constexpr int LIT = (HT + kThreads - 1) / kThreads;
+  cx<P> ra[LIT], rb[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
-    cx<P> A = {(P)0, (P)0}, Bv = {(P)0, (P)0};
-    if (gs < m) {
-      A = W[((size_t)q * 2 + 0) * m + gs];
-      Bv = W[((size_t)q * 2 + 1) * m + gs];
+    ra[it] = cx<P>{(P)0, (P)0};
+    rb[it] = cx<P>{(P)0, (P)0};
+    if ((HT % kThreads == 0 || idx < HT) && gs < m) {
+      ra[it] = W[((size_t)q * 2 + 0) * m + gs];
+      rb[it] = W[((size_t)q * 2 + 1) * m + gs];
     }
-    buf[(q + 1) * TS + s] = cx<P>{A.x - Bv.y, A.y + Bv.x};                  // A + iB
-    buf[((N - q) & (N - 1)) * TS + s] = cx<P>{A.x + Bv.y, Bv.x - A.y};      // conj(A) + i conj(B)
+  }
+  if constexpr (C::TW_LDS)
+    for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
+    if (HT % kThreads == 0 || idx < HT) {
+      const int q = idx / TS, s = idx % TS;
+      const cx<P> A = ra[it], Bv = rb[it];
+      buf[pk<PS>(q + 1) * S + s] = cx<P>{A.x - Bv.y, A.y + Bv.x};              // A + iB
+      buf[pk<PS>((N - q) & (N - 1)) * S + s] = cx<P>{A.x + Bv.y, Bv.x - A.y};  // conj(A) + i conj(B)
+    }
   }
   __syncthreads();
-  fft_lds<P, N, 1, TS, true>(buf, tw, tid);
+  wfft<P, N, 1, TS / 4, S, PS, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  __syncthreads();
   double acc = 0.0;
   double *o1 = out;
   double *o2 = out + (size_t)N * m;
   for (int idx = tid; idx < N * TS; idx += kThreads) {
     const int k = idx / TS, s = idx % TS, gs = s0 + s;
     if (gs >= m) continue;
-    const cx<P> z = buf[idx];
+    const cx<P> z = buf[pk<PS>(k) * S + s];
     const cx<double> d = dtw[k];  // multiply by conj(d)
     const double zx = (double)z.x, zy = (double)z.y;
     const double r1 = zx * d.x + zy * d.y;
@@ -306,136 +436,183 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   }
 }
 
-// ---- x1 sine transform of (n) slabs of M x M, with a transposing store/load -----
-// ROWS_IN: src rows [x2][x1] -> dst [j1][x2];  otherwise src [j1][x2] -> dst rows [x2][x1].
-template <typename P, int N1, int L, bool ROWS_IN>
-__global__ __launch_bounds__(kThreads) void k_dst_x1(const cx<P> *__restrict__ src,
-                                                     cx<P> *__restrict__ dst,
-                                                     const cx<P> *__restrict__ tw,
-                                                     const P *__restrict__ sintab) {
-  constexpr int M = N1 - 1;
-  __shared__ cx<P> buf[N1 * L];
-  const int tid = threadIdx.x;
-  const size_t slab = blockIdx.y;
-  const int r0 = blockIdx.x * L;
-  const cx<P> *S = src + slab * (size_t)M * M;
-  cx<P> *D = dst + slab * (size_t)M * M;
-  if (ROWS_IN) {
-    for (int idx = tid; idx < L * M; idx += kThreads) {
-      const int x1 = idx % M, r = idx / M;
-      cx<P> val = {(P)0, (P)0};
-      if (r0 + r < M) val = S[(size_t)(r0 + r) * M + x1];
-      buf[(x1 + 1) * L + r] = val;
-    }
-  } else {
-    for (int idx = tid; idx < L * M; idx += kThreads) {
-      const int r = idx % L, j1 = idx / L;
-      cx<P> val = {(P)0, (P)0};
-      if (r0 + r < M) val = S[(size_t)j1 * M + r0 + r];
-      buf[(j1 + 1) * L + r] = val;
-    }
+// ---- sine transform of contiguous rows, in place (2D x1 passes) ------------------
+// nlines rows of M complex each; every wave owns B rows at a time.
+template <typename P, int N1>
+__global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, int nlines,
+                                                       const cx<P> *__restrict__ twg,
+                                                       const P *__restrict__ sing) {
+  using R = RowCfg<P, N1>;
+  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  __shared__ cx<P> lds[R::WPB][R::PN * S];
+  __shared__ cx<P> stw[N1];
+  __shared__ P ssin[N1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    stw[i] = twg[i];
+    ssin[i] = sing[i];
   }
   __syncthreads();
-  dst_lds<P, N1, L>(buf, tw, sintab, tid);
-  if (ROWS_IN) {
-    for (int idx = tid; idx < L * M; idx += kThreads) {
-      const int r = idx % L, j1 = idx / L;
-      if (r0 + r < M) D[(size_t)j1 * M + r0 + r] = buf[(j1 + 1) * L + r];
+  cx<P> *buf = lds[wv];
+  const int ngroups = (nlines + B - 1) / B;
+  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
+    const int l0 = grp * B;
+    constexpr int LIT = (B * M + 63) / 64;
+    cx<P> r[LIT];
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const int idx = lane + 64 * it;
+      const int b = idx / M, x = idx % M;
+      r[it] = cx<P>{(P)0, (P)0};
+      if (idx < B * M && l0 + b < nlines) r[it] = W[(size_t)(l0 + b) * M + x];
     }
-  } else {
-    for (int idx = tid; idx < L * M; idx += kThreads) {
-      const int x1 = idx % M, r = idx / M;
-      if (r0 + r < M) D[(size_t)(r0 + r) * M + x1] = buf[(x1 + 1) * L + r];
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const int idx = lane + 64 * it;
+      if (idx < B * M) buf[pk<PS>(idx % M + 1) * S + idx / M] = r[it];
     }
+    wave_sync();
+    wdst<P, N1, B, S, PS>(buf, stw, ssin, lane);
+    for (int idx = lane; idx < B * M; idx += 64) {
+      const int b = idx / M, x = idx % M;
+      if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
+    }
+    wave_sync();
   }
 }
 
-// ---- last space direction: DST, step 2, inverse DST, on both block rows --------
-// Lines are contiguous.  A "unit" is (q) in 1D or (q, j1) in 2D and owns the two half
-// lines at ((q*2 + h) * M [+ j1]) * M.  kind: 0 P_S (2x2), 1 |P_S|, 2 P_MS.
-template <typename P, int N1, int U, int DIMS>
-__global__ __launch_bounds__(kThreads) void k_pair_mode(cx<P> *__restrict__ Wd,
-                                                        const cx<P> *__restrict__ tw,
-                                                        const P *__restrict__ sintab,
+// ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
+// W layout [q][half][x]; every wave owns UNITS frequencies (2*UNITS lines) at a time.
+template <typename P, int N1>
+__global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, int nunits,
+                                                        const cx<P> *__restrict__ twg,
+                                                        const P *__restrict__ sing,
                                                         const cx<P> *__restrict__ lam,
-                                                        const P *__restrict__ mu, int nunits,
-                                                        int kind, P tau, P alpha, P cnorm) {
-  constexpr int M = N1 - 1;
-  constexpr int B = 2 * U;
-  __shared__ cx<P> buf[N1 * B];
-  const int tid = threadIdx.x;
-  const int unit0 = blockIdx.x * U;
-  auto line_off = [&](int unit, int h) -> size_t {
-    if (DIMS == 1) return ((size_t)unit * 2 + h) * M;
-    const int q = unit / M, j1 = unit % M;
-    return (((size_t)q * 2 + h) * M + j1) * M;
-  };
-  for (int idx = tid; idx < B * M; idx += kThreads) {
-    const int x = idx % M, bh = idx / M;
-    const int unit = unit0 + (bh >> 1);
-    cx<P> val = {(P)0, (P)0};
-    if (unit < nunits) val = Wd[line_off(unit, bh & 1) + x];
-    buf[(x + 1) * B + bh] = val;
+                                                        const P *__restrict__ mu, int kind,
+                                                        P tau, P alpha, P cnorm) {
+  using R = RowCfg<P, N1>;
+  constexpr int M = N1 - 1, UNITS = R::UNITS, B = 2 * UNITS, S = R::SU, PS = R::PS;
+  __shared__ cx<P> lds[R::WPBU][R::PN * S];
+  __shared__ cx<P> stw[N1];
+  __shared__ P ssin[N1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    stw[i] = twg[i];
+    ssin[i] = sing[i];
   }
   __syncthreads();
-  dst_lds<P, N1, B>(buf, tw, sintab, tid);
-  for (int idx = tid; idx < U * M; idx += kThreads) {
-    const int u = idx % U, j = idx / U;
-    const int unit = unit0 + u;
-    if (unit >= nunits) continue;
-    int q;
-    P musum;
-    if (DIMS == 1) {
-      q = unit;
-      musum = mu[j];
-    } else {
-      q = unit / M;
-      musum = mu[unit % M] + mu[j];
+  cx<P> *buf = lds[wv];
+  const int ngroups = (nunits + UNITS - 1) / UNITS;
+  for (int grp = blockIdx.x * R::WPBU + wv; grp < ngroups; grp += gridDim.x * R::WPBU) {
+    const int u0 = grp * UNITS;
+    const int nl = 2 * nunits;
+    constexpr int LIT = (B * M + 63) / 64;
+    cx<P> r[LIT];
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const int idx = lane + 64 * it;
+      const int b = idx / M, x = idx % M;
+      r[it] = cx<P>{(P)0, (P)0};
+      if (idx < B * M && 2 * u0 + b < nl) r[it] = W[(size_t)(2 * u0 + b) * M + x];
     }
-    const cx<P> l = lam[q];
-    const cx<P> a = buf[(j + 1) * B + 2 * u];
-    const cx<P> b = buf[(j + 1) * B + 2 * u + 1];
-    cx<P> na, nb;
-    if (kind == 0) {
-      const cx<P> Lm = {l.x + tau * musum, l.y};
-      const P det = Lm.x * Lm.x + Lm.y * Lm.y + alpha * alpha;
-      const P c = cnorm / det;
-      // [a; b] <- c [[conj(Lm), alpha], [-alpha, Lm]] [a; b]
-      const cx<P> ca = {Lm.x * a.x + Lm.y * a.y, Lm.x * a.y - Lm.y * a.x};
-      const cx<P> lb = cmul(Lm, b);
-      na = cscale(cx<P>{ca.x + alpha * b.x, ca.y + alpha * b.y}, c);
-      nb = cscale(cx<P>{lb.x - alpha * a.x, lb.y - alpha * a.y}, c);
-    } else {
-      P s;
-      if (kind == 1) {
-        const P re = l.x + tau * musum;
-        s = cnorm / sqrt(re * re + l.y * l.y + alpha * alpha);
-      } else {
-        s = cnorm / (sqrt(l.x * l.x + l.y * l.y + alpha * alpha) + tau * musum);
-      }
-      na = cscale(a, s);
-      nb = cscale(b, s);
+#pragma unroll
+    for (int it = 0; it < LIT; ++it) {
+      const int idx = lane + 64 * it;
+      if (idx < B * M) buf[pk<PS>(idx % M + 1) * S + idx / M] = r[it];
     }
-    buf[(j + 1) * B + 2 * u] = na;
-    buf[(j + 1) * B + 2 * u + 1] = nb;
+    wave_sync();
+    wdst<P, N1, B, S, PS>(buf, stw, ssin, lane);
+    for (int idx = lane; idx < UNITS * M; idx += 64) {
+      const int u = idx / M, j = idx % M;
+      if (u0 + u >= nunits) continue;
+      cx<P> a = buf[pk<PS>(j + 1) * S + 2 * u];
+      cx<P> bb = buf[pk<PS>(j + 1) * S + 2 * u + 1];
+      mode_op<P>(a, bb, lam[u0 + u], mu[j], kind, tau, alpha, cnorm);
+      buf[pk<PS>(j + 1) * S + 2 * u] = a;
+      buf[pk<PS>(j + 1) * S + 2 * u + 1] = bb;
+    }
+    wave_sync();
+    wdst<P, N1, B, S, PS>(buf, stw, ssin, lane);
+    for (int idx = lane; idx < B * M; idx += 64) {
+      const int b = idx / M, x = idx % M;
+      if (2 * u0 + b < nl) W[(size_t)(2 * u0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
+    }
+    wave_sync();
+  }
+}
+
+// ---- 2D: x2-DST, step 2, x2-iDST on tiles of TX x1-columns (both block rows) -------
+// W layout [q][half][x2][x1], x1 already sine transformed (index j1).
+template <typename P, int N1, int TX_>
+__global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
+                                                        const cx<P> *__restrict__ twg,
+                                                        const P *__restrict__ sing,
+                                                        const cx<P> *__restrict__ lam,
+                                                        const P *__restrict__ mu, int kind,
+                                                        P tau, P alpha, P cnorm) {
+  using C = ColCfg<P, N1, TX_>;
+  constexpr int M = N1 - 1, TX = TX_, S = C::S, PS = C::PS;
+  constexpr int CPW = TX / 4;  // columns per wave
+  __shared__ cx<P> buf[C::PN * S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = blockIdx.y;
+  const int c0 = blockIdx.x * TX;
+  cx<P> *slab0 = W + ((size_t)q * 2 + 0) * M * M;
+  cx<P> *slab1 = W + ((size_t)q * 2 + 1) * M * M;
+  // tile column 2c+h holds (block row h, x1 column c0+c)
+  constexpr int TT = 2 * TX * M;
+  constexpr int LIT = (TT + kThreads - 1) / kThreads;
+  cx<P> r[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
+    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+    r[it] = cx<P>{(P)0, (P)0};
+    if (idx < TT && c0 + c < M) r[it] = (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c];
+  }
+  if constexpr (C::TAB_LDS) {
+    for (int i = tid; i < N1; i += kThreads) {
+      stw[i] = twg[i];
+      ssin[i] = sing[i];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * kThreads;
+    if (idx < TT) {
+      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+      buf[pk<PS>(x2 + 1) * S + 2 * c + h] = r[it];
+    }
   }
   __syncthreads();
-  dst_lds<P, N1, B>(buf, tw, sintab, tid);
-  for (int idx = tid; idx < B * M; idx += kThreads) {
-    const int x = idx % M, bh = idx / M;
-    const int unit = unit0 + (bh >> 1);
-    if (unit < nunits) Wd[line_off(unit, bh & 1) + x] = buf[(x + 1) * B + bh];
+  const cx<P> *tw = C::TAB_LDS ? stw : twg;
+  const P *sn = C::TAB_LDS ? ssin : sing;
+  cx<P> *wb = buf + wv * 2 * CPW;
+  wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
+  const cx<P> l = lam[q];
+  for (int idx = lane; idx < CPW * M; idx += 64) {
+    const int c = idx / M, j2 = idx % M;
+    const int j1 = c0 + wv * CPW + c;
+    if (j1 >= M) continue;
+    cx<P> a = wb[pk<PS>(j2 + 1) * S + 2 * c];
+    cx<P> bb = wb[pk<PS>(j2 + 1) * S + 2 * c + 1];
+    mode_op<P>(a, bb, l, mu[j1] + mu[j2], kind, tau, alpha, cnorm);
+    wb[pk<PS>(j2 + 1) * S + 2 * c] = a;
+    wb[pk<PS>(j2 + 1) * S + 2 * c + 1] = bb;
+  }
+  wave_sync();
+  wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
+  __syncthreads();
+  for (int idx = tid; idx < TT; idx += kThreads) {
+    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+    if (c0 + c < M)
+      (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
   }
 }
 
 // ---- host dispatch -------------------------------------------------------------
-struct PcArgs {
-  const wc_plan *p;
-  const double *v;
-  double *w;
-  double *partials;
-};
-
 template <typename P> struct Tabs;
 template <> struct Tabs<double> {
   static const cx<double> *twt(const wc_plan &p) { return (const cx<double> *)p.d_twt64; }
@@ -452,68 +629,121 @@ template <> struct Tabs<float> {
   static const float *mu(const wc_plan &p) { return p.d_mu32; }
 };
 
+int row_grid(int wave_groups, int wpb) {
+  int g = (wave_groups + wpb - 1) / wpb;
+  return g < 1 ? 1 : (g > 8192 ? 8192 : g);
+}
+
+// Tile widths: a plan's choice (autotuned or set) or the widest tile that keeps two
+// workgroups resident per CU.
+template <typename P, int N> constexpr int default_ts() {
+  if constexpr (TimeCfg<P, N, 16>::FITS && blocks_per_cu(TimeCfg<P, N, 16>::TILE) >= 2) return 16;
+  else if constexpr (TimeCfg<P, N, 8>::FITS && blocks_per_cu(TimeCfg<P, N, 8>::TILE) >= 2) return 8;
+  else return 4;
+}
+template <typename P, int N1> constexpr int default_tx() {
+  if constexpr (ColCfg<P, N1, 8>::FITS && blocks_per_cu(ColCfg<P, N1, 8>::TILE) >= 2) return 8;
+  else return 4;
+}
+
+template <typename P, int N, int TS>
+hipError_t tfft_fwd_ts(const wc_plan &p, const double *v) {
+  if constexpr (!TimeCfg<P, N, TS>::FITS) {
+    return tfft_fwd_ts<P, N, 4>(p, v);
+  } else {
+    dim3 grid((p.m + TS - 1) / TS);
+    ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
+    hipLaunchKernelGGL((k_tfft_fwd<P, N, TS>), grid, dim3(kThreads), 0, p.stream, v,
+                       (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m);
+    return hipGetLastError();
+  }
+}
+
+template <typename P, int N, int TS>
+hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *nparts) {
+  if constexpr (!TimeCfg<P, N, TS>::FITS) {
+    return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
+  } else {
+    dim3 grid((p.m + TS - 1) / TS);
+    *nparts = grid.x;
+    ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
+    hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(kThreads), 0, p.stream,
+                       (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
+                       p.m, dotv, p.d_partials);
+    return hipGetLastError();
+  }
+}
+
 template <typename P, int N>
 hipError_t run_tfft_fwd(const wc_plan &p, const double *v) {
-  constexpr int TS = TileCfg<P, N>::TS;
-  dim3 grid((p.m + TS - 1) / TS);
-  ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
-  hipLaunchKernelGGL((k_tfft_fwd<P, N, TS>), grid, dim3(kThreads), 0, p.stream, v,
-                     (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m);
-  return hipGetLastError();
+  switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
+    case 4: return tfft_fwd_ts<P, N, 4>(p, v);
+    case 8: return tfft_fwd_ts<P, N, 8>(p, v);
+    default: return tfft_fwd_ts<P, N, 16>(p, v);
+  }
 }
 
 template <typename P, int N>
 hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts) {
-  constexpr int TS = TileCfg<P, N>::TS;
-  dim3 grid((p.m + TS - 1) / TS);
-  *nparts = grid.x;
-  ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
-  hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(kThreads), 0, p.stream,
-                     (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
-                     p.m, dotv, p.d_partials);
-  return hipGetLastError();
+  switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
+    case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
+    case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts);
+    default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts);
+  }
+}
+
+template <typename P, int N1, int TX>
+hipError_t cols_tx(const wc_plan &p, int kind, double c) {
+  if constexpr (!ColCfg<P, N1, TX>::FITS) {
+    return cols_tx<P, N1, 4>(p, kind, c);
+  } else {
+    constexpr int M = N1 - 1;
+    dim3 gc((M + TX - 1) / TX, p.n / 2);
+    ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
+    hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(kThreads), 0, p.stream,
+                       (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
+                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
+    return hipGetLastError();
+  }
 }
 
 template <typename P, int N1>
 hipError_t run_space(const wc_plan &p) {
-  constexpr int L = TileCfg<P, N1>::L;
-  constexpr int U = TileCfg<P, N1>::U;
+  using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
   const double c = (1.0 / p.n) * (p.dims == 2 ? (2.0 / N1) * (2.0 / N1) : (2.0 / N1));
+  cx<P> *W = (cx<P> *)p.d_specA;
+  const double bytes = 2.0 * p.nvec * sizeof(P);
   if (p.dims == 1) {
     const int nunits = p.n / 2;
-    dim3 grid((nunits + U - 1) / U);
-    ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_pair_mode<P, N1, U, 1>), grid, dim3(kThreads), 0, p.stream,
-                       (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
-                       Tabs<P>::mu(p), nunits, kind, (P)p.tau, (P)p.alpha, (P)c);
+    dim3 grid(row_grid((nunits + R::UNITS - 1) / R::UNITS, R::WPBU));
+    ProfScope ps(p, K_PAIR_MODE, bytes);
+    hipLaunchKernelGGL((k_pair_rows<P, N1>), grid, dim3(64 * R::WPBU),
+                       0, p.stream,
+                       W, nunits, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
+                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
     return hipGetLastError();
   }
-  dim3 g1((M + L - 1) / L, p.n);
+  const int nlines = p.n * M;  // n/2 frequencies x 2 block rows x M rows
+  dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
   hipError_t e;
   {
-    ProfScope ps(p, K_DST_X1_FWD, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_dst_x1<P, N1, L, true>), g1, dim3(kThreads), 0, p.stream,
-                       (const cx<P> *)p.d_specA, (cx<P> *)p.d_specB, Tabs<P>::tws(p),
-                       Tabs<P>::sin(p));
+    ProfScope ps(p, K_DST_X1_FWD, bytes);
+    hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
+                       p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
-  const int nunits = (p.n / 2) * M;
-  dim3 g2((nunits + U - 1) / U);
-  {
-    ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_pair_mode<P, N1, U, 2>), g2, dim3(kThreads), 0, p.stream,
-                       (cx<P> *)p.d_specB, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
-                       Tabs<P>::mu(p), nunits, kind, (P)p.tau, (P)p.alpha, (P)c);
-    e = hipGetLastError();
+  switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
+    case 4: e = cols_tx<P, N1, 4>(p, kind, c); break;
+    case 16: e = cols_tx<P, N1, 16>(p, kind, c); break;
+    default: e = cols_tx<P, N1, 8>(p, kind, c); break;
   }
   if (e != hipSuccess) return e;
-  ProfScope ps(p, K_DST_X1_INV, 2.0 * p.nvec * sizeof(P));
-  hipLaunchKernelGGL((k_dst_x1<P, N1, L, false>), g1, dim3(kThreads), 0, p.stream,
-                     (const cx<P> *)p.d_specB, (cx<P> *)p.d_specA, Tabs<P>::tws(p),
-                     Tabs<P>::sin(p));
+  ProfScope ps(p, K_DST_X1_INV, bytes);
+  hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
+                     W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
   return hipGetLastError();
 }
 
@@ -564,12 +794,10 @@ hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool do
 }
 
 int pc_partials_needed(int n, int m, int precision) {
-  int ts = 1;
-  const int es = precision == WC_MIXED ? 8 : 16;
-  ts = 65536 / (n * es);
-  if (ts < 1) ts = 1;
-  if (ts > 16) ts = 16;
-  return (m + ts - 1) / ts;
+  // bound on the inverse time FFT's grid: every tile has at least 4 spatial columns
+  (void)n;
+  (void)precision;
+  return (m + 3) / 4;
 }
 
 }  // namespace wc

@@ -42,7 +42,7 @@ def test_status_strings(wc):
 
 @pytest.mark.parametrize("bad", [
     dict(dims=3), dict(M=0), dict(n=1), dict(theta=0.3), dict(theta=1.2), dict(gamma=0.0),
-    dict(gamma=-1.0), dict(T=0.0), dict(tol=0.0), dict(restart=0), dict(restart=65),
+    dict(gamma=-1.0), dict(T=0.0), dict(tol=0.0), dict(restart=0), dict(restart=33),
     dict(maxit=0), dict(gamma=float("nan")),
 ])
 def test_invalid_arguments_rejected(wc, bad):
