@@ -189,7 +189,7 @@ def main():
                    "gamma": args.gamma, "zeta": "pi", "method": args.method,
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
                    "dof": 2 * n * m, "seed": args.seed},
-        "iters": iters, "relres": relres,
+        "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
         "solves_per_s": round(1000.0 / ms_per_step, 3),
         "pc_apply": {"ms": round(pc_ms, 4), "model_bytes": pc_bytes, "GBps": round(pc_gbs, 1),
                      "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4), "kernels": pc_kernels},

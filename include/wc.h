@@ -103,6 +103,7 @@ typedef struct {
   double relres_est;  /* recurrence estimate at exit */
   double ms;          /* wall time of the Krylov solve */
   int mg_cycles_max;  /* largest V-cycle count of any spatial solve (variable a) */
+  int reorth;         /* GMRES: iterations that needed a second Gram-Schmidt pass */
 } wc_info;
 
 typedef struct wc_plan wc_plan;

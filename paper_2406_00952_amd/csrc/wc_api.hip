@@ -25,7 +25,7 @@ const char *kernel_name(int id) {
   static const char *names[K_COUNT] = {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
-      "multiaxpy", "scale", "fill"};
+      "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -303,7 +303,9 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       double *Zj = flex ? Zb + (size_t)j * nv : Zb;
       int np = 0;
       WC_TRY(launch_pc_apply(*p, Vj, Zj, false, nullptr));
-      WC_TRY(launch_matvec(*p, Zj, Vn, p->d_partials, nullptr));
+      // Arnoldi on E = Ahat P^{-1} - I (same Krylov space, H = H_E + I): Ahat z - v is
+      // not dominated by v, so one classical Gram-Schmidt pass normally suffices
+      WC_TRY(launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj));
       WC_TRY(launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np));
       WC_TRY(launch_gs_finalize(*p, 1, j, np));
       WC_TRY(launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np));
@@ -315,11 +317,16 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       WC_TRY(sync_read(p, S_WN2, S_D2 + j + 1 - S_WN2));
       const bool two = p->h_scal[S_REORTH] != 0.0;
       reorth += two ? 1 : 0;
+      if (!two && p->prof.on) {
+        p->prof.void_last(K_MULTIDOT_RE);
+        p->prof.void_last(K_MULTIAXPY_RE);
+      }
       const double nn = std::sqrt(std::max(p->h_scal[S_NU2 + j + 1], 0.0));
       nu[j + 1] = nn;
       double *h = &H[(size_t)j * (k + 1)];  // column j of the Hessenberg matrix
       for (int i = 0; i <= j; ++i)
         h[i] = (p->h_scal[S_D1 + i] + (two ? p->h_scal[S_D2 + i] : 0.0)) / (nu[i] * nu[j]);
+      h[j] += 1.0;
       const double hn = nn / nu[j];
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * h[i] + sn[i] * h[i + 1];
@@ -363,6 +370,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     info->restarts = cycles;
     info->relres = relres;
     info->relres_est = relres_est;
+    info->reorth = reorth;
     info->status = st;
   }
   return st;

@@ -14,6 +14,11 @@ namespace wc {
 constexpr int kThreads = 256;        // threads per workgroup for every kernel
 constexpr int kRedBlocks = 1024;     // max workgroups of the streaming reductions
 constexpr int kMaxRestart = 32;
+// GMRES second Gram-Schmidt pass when the first pass leaves less than this
+// fraction of the squared norm of E v_j (E = Ahat P^{-1} - I).  With the shift
+// the drop reflects the convergence rate, not the preconditioner's quality; a
+// hundredfold drop in norm costs about two digits of orthogonality.
+constexpr double kReorthEta2 = 1e-4;
 constexpr int kMaxPartials = 1 << 16;
 
 template <typename T>
@@ -53,7 +58,7 @@ enum SolveStatusCode : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_BREAKDOWN = 2,
 enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
-  K_MULTIAXPY, K_SCALE, K_FILL, K_COUNT
+  K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_COUNT
 };
 const char *kernel_name(int id);
 
@@ -68,6 +73,11 @@ struct Profiler {
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
+  // the launch ran but did no work (a device-gated pass): it moved no bytes
+  void void_last(int kid) {
+    for (auto it = recs.rbegin(); it != recs.rend(); ++it)
+      if (it->kid == kid) { it->bytes = 0.0; return; }
+  }
 };
 
 }  // namespace wc
@@ -140,8 +150,9 @@ struct ProfScope {
 namespace wc {
 
 // ---- launchers (wc_ops.hip) -------------------------------------------------
+// y = Ahat x (GMRES layout) or A x (MINRES layout); with sub, y = (.) x - sub.
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
-                         int *nblocks_out);
+                         int *nblocks_out, const double *sub = nullptr);
 hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
                       double *b);
 hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u);

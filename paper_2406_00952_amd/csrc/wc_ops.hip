@@ -89,8 +89,11 @@ struct MvArgs {
 // Output block rows: A (sym) = [alpha x1 + T^T x2; T x1 - alpha x2],
 //                    A_hat   = [T x1 - alpha x2; alpha x1 + T^T x2].
 // partials[dir*gridDim.x + block] = this block's share of <y, x>.
+// With sub != nullptr the kernel writes y - sub (same layout as y) and the
+// partial sums are not meaningful.
 __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ x,
-                                                     double *__restrict__ y, MvArgs a,
+                                                     double *__restrict__ y,
+                                                     const double *__restrict__ sub, MvArgs a,
                                                      double *__restrict__ partials) {
   __shared__ double red[kThreads / 64];
   const int dir = blockIdx.y;
@@ -100,14 +103,16 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
   if (s < a.m) {
     const double *xs = dir == 0 ? x : x + nm;
     const double *xo = dir == 0 ? x + nm : x;
-    double *yo = a.sym ? (dir == 0 ? y + nm : y) : (dir == 0 ? y : y + nm);
+    const size_t ooff = a.sym ? (dir == 0 ? nm : 0) : (dir == 0 ? 0 : nm);
+    double *yo = y + ooff;
+    const double *so = sub ? sub + ooff : nullptr;
     const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
     const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
     double zprev = 0.0, xprev = 0.0;
     // the loads of KB time levels are issued before the recurrence consumes them
     constexpr int KB = 8;
     for (int kk0 = 0; kk0 < a.n; kk0 += KB) {
-      double xc[KB], kx[KB], xok[KB];
+      double xc[KB], kx[KB], xok[KB], sk[KB];
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         const int kk = kk0 + u < a.n ? kk0 + u : a.n - 1;
@@ -116,6 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
         xc[u] = xk[s];
         kx[u] = apply_stencil(st, xk, s);
         xok[u] = xo[(size_t)k * a.m + s];
+        sk[u] = so ? so[(size_t)k * a.m + s] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
           out = (uu - zprev) + a.tau * kx[u] + a.alpha * xok[u];
           zprev = uu;
         }
-        yo[(size_t)k * a.m + s] = out;
+        yo[(size_t)k * a.m + s] = out - sk[u];
         acc += out * (a.sym ? xok[u] : xc[u]);
       }
     }
@@ -411,8 +417,8 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
 
 // Gram-Schmidt bookkeeping for GMRES iteration j (basis V_0..V_j, new vector w).
 //  stage 1: D1_i = <V_i, w>, WN2 = ||w||^2, GSC_i = D1_i / NU2_i
-//  stage 2: WP2 = ||w'||^2; REORTH = WP2 < WN2/2 (the projection removed more than half of
-//           the norm: orthogonality may be lost, project again); else NU2_{j+1} = WP2
+//  stage 2: WP2 = ||w'||^2; REORTH = WP2 < kReorthEta2 * WN2 (the projection cancelled
+//           most of the norm: orthogonality may be lost, project again); else NU2_{j+1} = WP2
 //  stage 3 (when REORTH): D2_i = <V_i, w'>, GSC_i = D2_i / NU2_i
 //  stage 4 (when REORTH): WPP2 = ||w''||^2, NU2_{j+1} = WPP2
 __global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restrict__ partials,
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restri
         }
       } else if (stage == 2) {
         S[S_WP2] = r;
-        const bool again = r < 0.5 * S[S_WN2];
+        const bool again = r < kReorthEta2 * S[S_WN2];
         S[S_REORTH] = again ? 1.0 : 0.0;
         S[S_WPP2] = r;
         if (!again) S[S_NU2 + j + 1] = r;
@@ -467,12 +473,12 @@ int red_blocks(size_t n) {
 }
 
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
-                         int *nblocks_out) {
+                         int *nblocks_out, const double *sub) {
   MvArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
            p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface};
   dim3 grid((p.m + kThreads - 1) / kThreads, 2);
-  ProfScope ps(p, K_MATVEC, 16.0 * p.nvec);
-  hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, a, partials);
+  ProfScope ps(p, K_MATVEC, (sub ? 24.0 : 16.0) * p.nvec);
+  hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, sub, a, partials);
   if (nblocks_out) *nblocks_out = 2 * grid.x;
   return hipGetLastError();
 }
@@ -549,7 +555,7 @@ hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const 
                            bool self, const double *gate, int *nblocks) {
   const int g = red_blocks(p.nvec);
   if (nblocks) *nblocks = g;
-  ProfScope ps(p, K_MULTIDOT, 8.0 * p.nvec * (nb + 1));
+  ProfScope ps(p, gate ? K_MULTIDOT_RE : K_MULTIDOT, 8.0 * p.nvec * (nb + 1));
   switch (nb) {
 #define CASE_NB(K)                                                                           \
   case K:                                                                                    \
@@ -572,7 +578,7 @@ hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, in
   const int g = red_blocks(p.nvec);
   if (nblocks) *nblocks = g;
   double *parts = norm ? p.d_partials : nullptr;
-  ProfScope ps(p, K_MULTIAXPY, 8.0 * p.nvec * (nb + 2));
+  ProfScope ps(p, gate ? K_MULTIAXPY_RE : K_MULTIAXPY, 8.0 * p.nvec * (nb + 2));
   switch (nb) {
 #define CASE_NB(K)                                                                            \
   case K:                                                                                     \

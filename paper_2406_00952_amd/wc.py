@@ -57,7 +57,7 @@ class _KStat(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("relres", ctypes.c_double), ("relres_est", ctypes.c_double), ("ms", ctypes.c_double),
-                ("mg_cycles_max", ctypes.c_int)]
+                ("mg_cycles_max", ctypes.c_int), ("reorth", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -105,6 +105,7 @@ class Info:
     relres_est: float
     ms: float
     mg_cycles_max: int
+    reorth: int = 0
 
 
 def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face):
@@ -206,7 +207,7 @@ class Plan:
         if not (code == WC_OK or (allow_maxit and code == WC_E_MAXIT)):
             raise WcError(code, "wc_krylov")
         return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
-                    inf.mg_cycles_max)
+                    inf.mg_cycles_max, inf.reorth)
 
     def profile(self, enable: bool):
         self._check(_lib.wc_profile(self._h, int(bool(enable))), "wc_profile")
@@ -227,4 +228,4 @@ class Plan:
         if not (code == WC_OK or (allow_maxit and code == WC_E_MAXIT)):
             raise WcError(code, "wc_solve")
         return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
-                    inf.mg_cycles_max)
+                    inf.mg_cycles_max, inf.reorth)
