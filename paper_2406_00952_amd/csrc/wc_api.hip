@@ -25,7 +25,8 @@ const char *kernel_name(int id) {
   static const char *names[K_COUNT] = {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
-      "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re"};
+      "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re", "mg_smooth", "mg_restrict",
+      "mg_lds", "mg_norm", "mg_mix"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -68,6 +69,7 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   const double m = std::pow((double)pr->M, pr->dims);
   if (m * pr->n * 2.0 > 4.0e9) return WC_E_ARG;  // 32-bit spatial indexing inside kernels
   if (pr->a_face_host) {
+    if (op->mg_max_cycles < 1 || !(op->mg_tol >= 0) || !std::isfinite(op->mg_tol)) return WC_E_ARG;
     const size_t nf = pr->dims == 1 ? (size_t)pr->M + 1 : 2 * (size_t)pr->M * (pr->M + 1);
     for (size_t i = 0; i < nf; ++i)
       if (!(pr->a_face_host[i] > 0) || !std::isfinite(pr->a_face_host[i])) return WC_E_ARG;
@@ -75,10 +77,10 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   return WC_OK;
 }
 
-// Whether the GPU preconditioner covers this problem: a == 1, zeta == pi (real arithmetic,
-// half spectrum), n and M+1 powers of two in [4, 1024].
+// Whether the GPU preconditioner covers this problem: zeta == pi (real arithmetic, half
+// spectrum), n and M+1 powers of two in [4, 1024] (sine transforms for a == 1, a
+// multigrid hierarchy down to one point otherwise).
 bool pc_path_ok(const wc_problem *pr) {
-  if (pr->a_face_host) return false;
   if (std::fabs(pr->zeta - M_PI) > 1e-12) return false;
   return pow2_in(pr->n, 4, 1024) && pow2_in(pr->M + 1, 4, 1024);
 }
@@ -93,8 +95,33 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
 }
 
 struct Sizes {
-  size_t nvec, spec_bytes, partials, tables, vecs, total;
+  size_t nvec, spec_bytes, partials, tables, vecs, mg, total;
 };
+
+// Multigrid levels M_0 = M, M_{l+1} = (M_l - 1)/2, ..., 1; the first level whose remaining
+// pyramid fits the LDS budget of one workgroup; bytes of u and f of levels 1..ltop.
+struct MgShape {
+  int nlev = 0, ltop = 0;
+  int M[kMgMaxLevels] = {};
+  size_t work = 0, faces = 0;
+};
+
+MgShape mg_shape(int dims, int M, int n, int precision) {
+  MgShape g;
+  const size_t es = precision == WC_MIXED ? 8 : 16;
+  for (int Ml = M; g.nlev < kMgMaxLevels; Ml = (Ml - 1) / 2) {
+    g.M[g.nlev++] = Ml;
+    if (Ml <= 1) break;
+  }
+  g.ltop = g.nlev - 1;
+  for (int l = 0; l < g.nlev; ++l)
+    if (mg_lds_bytes(dims, g.M[l], precision) <= kMgLdsBytes) { g.ltop = l; break; }
+  for (int l = 1; l <= g.ltop; ++l)
+    g.work += 2 * (size_t)n * (dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
+  for (int l = 1; l < g.nlev; ++l)
+    g.faces += dims == 2 ? 2 * (size_t)g.M[l] * (g.M[l] + 1) : (size_t)g.M[l] + 1;
+  return g;
+}
 
 Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   Sizes s{};
@@ -107,9 +134,14 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.partials = parts + 64;
   s.tables = 1 << 20;
   s.vecs = (size_t)krylov_vectors(pr, op) * s.nvec * sizeof(double);
-  s.total = s.spec_bytes * (pr->dims == 2 ? 2 : 1) + s.partials * sizeof(double) + s.tables +
-            s.vecs + S_COUNT * sizeof(double);
-  if (pr->a_face_host) s.total += 2 * (size_t)(pr->M + 1) * pr->M * sizeof(double);
+  s.mg = 0;
+  if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
+    const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
+    s.mg = s.spec_bytes + g.work + (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
+           (size_t)pr->n * 6 * sizeof(double);
+  }
+  s.total = s.spec_bytes + s.partials * sizeof(double) + s.tables + s.vecs +
+            S_COUNT * sizeof(double) + s.mg;
   return s;
 }
 
@@ -138,6 +170,8 @@ void free_plan(wc_plan *p) {
   dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
+  dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
+  dfree(p->d_mg_fn2);
   dfree(p->d_vecs);
   if (p->h_scal) (void)hipHostFree(p->h_scal);
   p->h_scal = nullptr;
@@ -376,6 +410,95 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   return st;
 }
 
+// Coarse face coefficients: the coarse face between two coarse nodes sits on a fine node,
+// between two fine faces of the same line; its coefficient is their mean.
+std::vector<double> coarsen_faces(int dims, int Mf, const std::vector<double> &af) {
+  const int Mc = (Mf - 1) / 2;
+  if (dims == 1) {
+    std::vector<double> ac(Mc + 1);
+    for (int I = 0; I <= Mc; ++I) ac[I] = 0.5 * (af[2 * I] + af[2 * I + 1]);
+    return ac;
+  }
+  const double *axf = af.data();                            // (Mf, Mf+1)
+  const double *ayf = af.data() + (size_t)Mf * (Mf + 1);    // (Mf+1, Mf)
+  std::vector<double> ac(2 * (size_t)Mc * (Mc + 1));
+  double *axc = ac.data(), *ayc = ac.data() + (size_t)Mc * (Mc + 1);
+  for (int J = 0; J < Mc; ++J)
+    for (int I = 0; I <= Mc; ++I)
+      axc[(size_t)J * (Mc + 1) + I] =
+          0.5 * (axf[(size_t)(2 * J + 1) * (Mf + 1) + 2 * I] + axf[(size_t)(2 * J + 1) * (Mf + 1) + 2 * I + 1]);
+  for (int J = 0; J <= Mc; ++J)
+    for (int I = 0; I < Mc; ++I)
+      ayc[(size_t)J * Mc + I] =
+          0.5 * (ayf[(size_t)(2 * J) * Mf + 2 * I + 1] + ayf[(size_t)(2 * J + 1) * Mf + 2 * I + 1]);
+  return ac;
+}
+
+// Multigrid hierarchy, per-system shifts and the block-row rotation of P_S (see the
+// multigrid source for the algebra).
+wc_status build_multigrid(wc_plan *p, const double *a_face_host) {
+  const MgShape g = mg_shape(p->dims, p->M, p->n, p->opts.precision);
+  p->mg_nlev = g.nlev;
+  p->mg_ltop = g.ltop;
+  const size_t es = p->opts.precision == WC_MIXED ? 8 : 16;
+  std::vector<double> faces;
+  const size_t nf0 = p->dims == 1 ? (size_t)p->M + 1 : 2 * (size_t)p->M * (p->M + 1);
+  std::vector<double> cur(a_face_host, a_face_host + nf0);
+  size_t woff = 0;
+  for (int l = 0; l < g.nlev; ++l) {
+    p->mg_M[l] = g.M[l];
+    p->mg_inv_h2[l] = (double)(g.M[l] + 1) * (g.M[l] + 1);
+    if (l > 0) {
+      cur = coarsen_faces(p->dims, g.M[l - 1], cur);
+      p->mg_aoff[l] = faces.size();
+      faces.insert(faces.end(), cur.begin(), cur.end());
+    }
+    if (l >= 1 && l <= g.ltop) {
+      p->mg_woff[l] = woff;
+      woff += 2 * (size_t)p->n * (p->dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
+    }
+  }
+  const int nq = p->n / 2;
+  std::vector<double> shift(2 * (size_t)p->n), mix(6 * (size_t)nq);
+  const double a = p->alpha;
+  for (int q = 0; q < nq; ++q) {
+    const int l = q + 1;
+    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / p->n);
+    std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
+    if (std::abs(l2) < 1e-13) l2 = p->s2_remedy;
+    const std::complex<double> lam = (1.0 - e) / l2;
+    if (p->opts.method == WC_GMRES_PS) {
+      const double im = lam.imag(), s = std::hypot(im, a);
+      // mu_1 = i (Im - s)/alpha, mu_2 = i (Im + s)/alpha, cancellation-free
+      const double m1 = im >= 0 ? -a / (im + s) : (im - s) / a;
+      const double m2 = im <= 0 ? a / (s - im) : (im + s) / a;
+      const double c1 = 1.0 / std::sqrt(1.0 + m1 * m1), c2 = 1.0 / std::sqrt(1.0 + m2 * m2);
+      shift[4 * q + 0] = lam.real();
+      shift[4 * q + 1] = s;
+      shift[4 * q + 2] = lam.real();
+      shift[4 * q + 3] = -s;
+      double *t = &mix[6 * (size_t)q];
+      t[0] = c1; t[1] = 0.0; t[2] = c1 * m1;  // c1 mu1 = i c1 m1
+      t[3] = c2; t[4] = 0.0; t[5] = c2 * m2;
+    } else {
+      const double sg = std::sqrt(std::norm(lam) + a * a);
+      shift[4 * q + 0] = sg; shift[4 * q + 1] = 0.0;
+      shift[4 * q + 2] = sg; shift[4 * q + 3] = 0.0;
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (!faces.empty()) e = upload(&p->d_mg_a, faces);
+  if (e == hipSuccess) e = upload(&p->d_mg_shift, shift);
+  if (e == hipSuccess) e = upload(&p->d_mg_mix, mix);
+  if (e == hipSuccess) e = hipMalloc((void **)&p->d_mg_fn2, (size_t)p->n * sizeof(double));
+  if (e == hipSuccess && woff > 0) e = hipMalloc(&p->d_mg_work, woff);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? WC_E_NOMEM : WC_E_HIP;
+  }
+  return WC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -558,7 +681,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     if (hipMalloc(ptr, bytes) != hipSuccess) oom = true;
   };
   alloc(&p->d_specA, sz.spec_bytes);
-  if (p->dims == 2) alloc(&p->d_specB, sz.spec_bytes);
+  if (p->var_coeff) alloc(&p->d_specB, sz.spec_bytes);
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
   p->nkvec = krylov_vectors(prob, opts);
@@ -575,6 +698,13 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
       hipSuccess) {
     free_plan(p);
     return WC_E_HIP;
+  }
+  if (p->var_coeff && p->pc_ok) {
+    const wc_status ms = build_multigrid(p, prob->a_face_host);
+    if (ms != WC_OK) {
+      free_plan(p);
+      return ms;
+    }
   }
   p->footprint = sz.total;
   *out = p;
@@ -629,11 +759,13 @@ wc_status wc_krylov(wc_plan *plan, const double *b, double *x, wc_info *info) {
   wc_info *inf = info ? info : &local;
   std::memset(inf, 0, sizeof(*inf));
   const auto t0 = std::chrono::steady_clock::now();
+  plan->mg_cycles_max = 0;
   wc_status st = plan->opts.method == WC_GMRES_PS ? run_gmres(plan, b, x, inf)
                                                   : run_minres(plan, b, x, inf);
   if (hipStreamSynchronize(plan->stream) != hipSuccess) st = WC_E_HIP;
   const auto t1 = std::chrono::steady_clock::now();
   inf->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  inf->mg_cycles_max = plan->mg_cycles_max;
   inf->status = st;
   return st;
 }

@@ -19,6 +19,12 @@ constexpr int kMaxRestart = 32;
 // the drop reflects the convergence rate, not the preconditioner's quality; a
 // hundredfold drop in norm costs about two digits of orthogonality.
 constexpr double kReorthEta2 = 1e-4;
+// multigrid (variable a): LDS budget of the single-workgroup coarse cycle, capacity of
+// the per-system norm partials, and the floor of the cycle tolerance in FP32
+constexpr size_t kMgLdsBytes = 60 * 1024;
+constexpr int kMgPartials = 32768;
+constexpr double kMgTolFp32 = 1e-5;
+constexpr int kMgMaxLevels = 12;
 constexpr int kMaxPartials = 1 << 16;
 
 template <typename T>
@@ -49,6 +55,7 @@ enum ScalarSlot : int {
   S_GSC = 184,   // kMaxRestart+1 projection coefficients of the current pass
   S_Y = 224,     // kMaxRestart update coefficients
   S_DOT = 300,   // scratch dot results
+  S_MG_RELRES = 310,  // largest relative residual over the multigrid systems
   S_COUNT = 512
 };
 
@@ -58,7 +65,8 @@ enum SolveStatusCode : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_BREAKDOWN = 2,
 enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
-  K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_COUNT
+  K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_MG_SMOOTH, K_MG_RESTRICT,
+  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_COUNT
 };
 const char *kernel_name(int id);
 
@@ -118,6 +126,19 @@ struct wc_plan {
   double *d_vecs = nullptr;
   int nkvec = 0;
   size_t footprint = 0;
+  // multigrid hierarchy (variable a); level 0 is the fine grid, the last has M = 1
+  int mg_nlev = 0;
+  int mg_ltop = 0;                        // first level cycled inside LDS
+  int mg_M[wc::kMgMaxLevels] = {};
+  double mg_inv_h2[wc::kMgMaxLevels] = {};
+  size_t mg_aoff[wc::kMgMaxLevels] = {};  // level l's faces at d_mg_a + mg_aoff[l] (l >= 1)
+  size_t mg_woff[wc::kMgMaxLevels] = {};  // level l's u at d_mg_work + mg_woff[l] bytes, f after
+  double *d_mg_a = nullptr;
+  void *d_mg_work = nullptr;
+  double *d_mg_shift = nullptr;           // n complex: shift of each system
+  double *d_mg_mix = nullptr;             // n/2 x 6: rotation of the two block rows (P_S)
+  double *d_mg_fn2 = nullptr;             // n: squared right-hand side norms
+  mutable int mg_cycles_last = 0, mg_cycles_max = 0;
 
   mutable wc::Profiler prof;
 
@@ -150,6 +171,10 @@ struct ProfScope {
 namespace wc {
 
 // ---- launchers (wc_ops.hip) -------------------------------------------------
+// Step 2 for variable a: batched multigrid on d_specA (in/out), d_specB = fine solution.
+hipError_t mg_space_apply(const wc_plan &p);
+// LDS bytes of a cycle over the pyramid from an M-point level down to M = 1
+size_t mg_lds_bytes(int dims, int M, int precision);
 // y = Ahat x (GMRES layout) or A x (MINRES layout); with sub, y = (.) x - sub.
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
                          int *nblocks_out, const double *sub = nullptr);

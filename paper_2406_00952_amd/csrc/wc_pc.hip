@@ -760,11 +760,15 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  switch (p.N1) {
+  if (p.var_coeff) {
+    e = mg_space_apply(p);
+  } else {
+    switch (p.N1) {
 #define CASE_S(NN) case NN: e = run_space<P, NN>(p); break;
-    WC_POW2_CASES(CASE_S)
+      WC_POW2_CASES(CASE_S)
 #undef CASE_S
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   switch (p.n) {

@@ -69,3 +69,15 @@ def test_footprint_grows_with_restart_and_precision(wc):
     # MINRES: ten system vectors
     fmin = wc.footprint_bytes(2, 255, 256, method="minres_abs_ps")
     assert 10 * nvec < fmin < 10 * nvec + 2 * 256 * 255 * 255 * 16 * 2 + (64 << 20)
+
+
+def test_multigrid_options_and_footprint(wc):
+    a = np.ones(2 * 31 * 32)
+    base = wc.footprint_bytes(2, 31, 32, method="gmres_ps")
+    fa = wc.footprint_bytes(2, 31, 32, a_face=a, method="gmres_ps")
+    spec = 32 * 31 * 31 * 16
+    # the fine multigrid solution, coarse levels (about a third of it) and the face pyramid
+    assert base + spec < fa < base + 2 * spec
+    assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_max_cycles=0) == 0
+    assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_tol=-1.0) == 0
+    assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_tol=0.0) > 0
