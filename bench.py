@@ -49,9 +49,16 @@ def parse():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--coeff", choices=["const", "sin"], default="const",
+                    help="a = 1, or a = 1 + 0.5 sin(2 pi x1) sin(2 pi x2) (multigrid)")
     ap.add_argument("--pc-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: Poisson arrivals of a mixed request population")
+    ap.add_argument("--rates", default="5,20,60,150", help="arrival rates (requests/s), --serve")
+    ap.add_argument("--requests", type=int, default=60, help="requests per rate, --serve")
+    ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
     return ap.parse_args()
 
 
@@ -67,7 +74,8 @@ def cpu_baseline(args, d, gpu_iters):
     from oracle.precond import FastPreconditioner
     from oracle import krylov, solver as osolver
     kind, symmetric = osolver.METHODS[args.method]
-    pr = Problem(dims=args.dims, M=args.M, n=args.n, theta=args.theta, gamma=args.gamma)
+    pr = Problem(dims=args.dims, M=args.M, n=args.n, theta=args.theta, gamma=args.gamma,
+                 a_face=d.get("a_face"))
     t0 = time.perf_counter()
     op = AllAtOnce(pr)
     gt, ft = rhs_tilde(pr, d["f"], d["g"], d["y0"])
@@ -96,12 +104,90 @@ def cpu_baseline(args, d, gpu_iters):
     }
 
 
+SERVE_SHAPES = [(2, 63, 64), (2, 127, 128), (2, 255, 256), (1, 255, 256), (1, 511, 512)]
+SERVE_WEIGHTS = [0.3, 0.3, 0.15, 0.15, 0.1]
+
+
+def serve(args):
+    """Poisson arrivals of a mixed population (grid and steps from SERVE_SHAPES, theta in
+    {1, 1/2}, gamma = 10^U(-6,-2), a = 1 or the sinusoidal coefficient on grids up to
+    M = 127, FP64 or mixed precision 50/50, GMRES-P_S), served by the library's server.
+    Reports p50/p99 of submission-to-completion latency and completed solves/s per
+    arrival rate, with the latency of each request class run alone for reference."""
+    import numpy as np
+    import torch
+    import datagen
+    from paper_2406_00952_amd import wc
+
+    rng = np.random.default_rng(args.seed)
+    pool = {}
+    for (dims, M, n) in SERVE_SHAPES:
+        d = datagen.config_problem(dims, M, n, seed=args.seed, noise_sigma=1e-3)
+        pool[(dims, M, n)] = tuple(torch.from_numpy(d[k]).to("cuda") for k in ("f", "g", "y0"))
+    torch.cuda.synchronize()
+
+    def draw():
+        dims, M, n = SERVE_SHAPES[rng.choice(len(SERVE_SHAPES), p=SERVE_WEIGHTS)]
+        coeff = "sin" if (M <= 127 and rng.random() < 0.5) else "const"
+        return dict(dims=dims, M=M, n=n, theta=float(rng.choice([1.0, 0.5])),
+                    gamma=float(10.0 ** rng.uniform(-6, -2)),
+                    a_face=datagen.sinusoidal_a(dims, M) if coeff == "sin" else None,
+                    precision=str(rng.choice(["fp64", "mixed"])), method="gmres_ps")
+
+    srv = wc.Server(hbm_budget=0, max_concurrency=args.concurrency)
+    # warm the plan cache-free path once per shape (first-use costs out of the timed runs)
+    for (dims, M, n) in SERVE_SHAPES:
+        f, g, y0 = pool[(dims, M, n)]
+        y = torch.empty(n * M ** dims, dtype=torch.float64, device="cuda")
+        t = srv.submit(f, g, y0, y, torch.empty_like(y), dims=dims, M=M, n=n, theta=0.5)
+        srv.wait(t)
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        reqs = [draw() for _ in range(args.requests)]
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        outs, tickets = [], []
+        t0 = time.perf_counter()
+        due = t0
+        for kw, gap in zip(reqs, gaps):
+            due += gap
+            while time.perf_counter() < due:
+                time.sleep(min(0.0005, max(0.0, due - time.perf_counter())))
+            f, g, y0 = pool[(kw["dims"], kw["M"], kw["n"])]
+            y = torch.empty(kw["n"] * kw["M"] ** kw["dims"], dtype=torch.float64, device="cuda")
+            p = torch.empty_like(y)
+            outs.append((y, p))
+            tickets.append(srv.submit(f, g, y0, y, p, **kw))
+        lat, qs, bad = [], [], 0
+        for t in tickets:
+            info, q_ms, tot_ms = srv.wait(t)
+            lat.append(tot_ms)
+            qs.append(q_ms)
+            bad += int(info.status != wc.WC_OK or info.relres > 1e-8)
+        t1 = time.perf_counter()
+        lat = np.array(lat)
+        results.append({"rate": rate, "requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                        "queue_p50_ms": round(float(np.percentile(qs, 50)), 2),
+                        "solves_per_s": round(len(reqs) / (t1 - t0), 2), "failed": bad})
+        log(f"rate {rate}: {results[-1]}")
+        del outs
+    srv.close()
+    print(json.dumps({"metric": "served latency p50/p99 (ms) and solves/s", "n_gpus": 1,
+                      "concurrency": args.concurrency, "data": "synthetic",
+                      "population": {"shapes": SERVE_SHAPES, "weights": SERVE_WEIGHTS,
+                                     "method": "gmres_ps", "tol": 1e-8},
+                      "rates": results}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no "
               "multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
     import numpy as np
     import torch
     import datagen
@@ -110,6 +196,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     d = datagen.config_problem(args.dims, args.M, args.n, seed=args.seed, noise_sigma=1e-3)
+    d["a_face"] = datagen.sinusoidal_a(args.dims, args.M) if args.coeff == "sin" else None
     m = args.M ** args.dims
     n = args.n
     f = torch.from_numpy(d["f"]).to(dev)
@@ -118,7 +205,8 @@ def main():
     y = torch.empty(n * m, dtype=torch.float64, device=dev)
     p = torch.empty_like(y)
     plan = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma, method=args.method,
-                   precision=args.precision, restart=args.restart, tol=1e-8, maxit=500)
+                   precision=args.precision, restart=args.restart, tol=1e-8, maxit=500,
+                   a_face=d["a_face"])
     log(f"plan footprint {plan.footprint / 2**30:.2f} GiB")
     for i in range(args.warmup):
         info = plan.solve(f, g, y0, y, p)
@@ -160,7 +248,9 @@ def main():
         pc_bytes = nvec * (8 + es // 2) * 2 + 3 * 2 * nvec * (es // 2)
     else:
         pc_bytes = nvec * (8 + es // 2) * 2 + 2 * nvec * (es // 2)
-    pc_gbs = pc_bytes / (pc_ms * 1e-3) / 1e9
+    if args.coeff == "sin":  # the multigrid apply has no fixed pass count
+        pc_bytes = None
+    pc_gbs = pc_bytes / (pc_ms * 1e-3) / 1e9 if pc_bytes else None
 
     # ---- roofline: dominant kernel family of the timed region -----------------
     fam = {k: v for k, v in stats.items() if v[0] > 0}
@@ -184,15 +274,20 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64 Krylov / f32 preconditioner",
         "data": "synthetic",
-        "config": {"workload": f"heat{args.dims}d_M{args.M}_n{args.n}",
+        "config": {"workload": f"heat{args.dims}d{'_sin' if args.coeff == 'sin' else ''}"
+                               f"_M{args.M}_n{args.n}",
+                   "coeff": args.coeff,
                    "dims": args.dims, "M": args.M, "n": n, "theta": args.theta,
                    "gamma": args.gamma, "zeta": "pi", "method": args.method,
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
                    "dof": 2 * n * m, "seed": args.seed},
         "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
+        "mg_cycles_max": infos[-1].mg_cycles_max,
         "solves_per_s": round(1000.0 / ms_per_step, 3),
-        "pc_apply": {"ms": round(pc_ms, 4), "model_bytes": pc_bytes, "GBps": round(pc_gbs, 1),
-                     "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4), "kernels": pc_kernels},
+        "pc_apply": {"ms": round(pc_ms, 4), "model_bytes": pc_bytes,
+                     "GBps": round(pc_gbs, 1) if pc_gbs else None,
+                     "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4) if pc_gbs else None,
+                     "kernels": pc_kernels},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

@@ -125,6 +125,13 @@ size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts);
 wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stream,
                          wc_plan **out);
 wc_status wc_plan_destroy(wc_plan *plan);
+/* Re-point a plan at another problem of the same shape without allocating: same
+ * dims, M, n, method, precision, restart and flexible, and a_face_host given iff
+ * it was at creation (WC_E_ARG otherwise).  theta, gamma, T, zeta, s2_remedy,
+ * the coefficient values and the remaining options may change; every table is
+ * rebuilt.  Synchronises the plan's stream first.  On an error other than
+ * WC_E_ARG the plan refuses solves until a retarget succeeds. */
+wc_status wc_plan_retarget(wc_plan *plan, const wc_problem *prob, const wc_opts *opts);
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
 
 /* Right-hand side of the transformed system (Section 1: f_tilde, g_tilde
@@ -178,6 +185,51 @@ typedef struct {
 
 wc_status wc_profile(wc_plan *plan, int enable);
 int wc_profile_read(wc_plan *plan, wc_kernel_stat *out, int max);
+
+/* ---- serving ------------------------------------------------------------------
+ * A server runs whole solves (wc_solve) for submitted requests on worker threads,
+ * each with its own HIP stream on the device current at wc_server_create, so
+ * requests of different sizes share the GPU at kernel granularity and a new
+ * request starts as soon as a worker and memory are free.
+ *
+ * Admission by HBM footprint: a request needs wc_plan_footprint_bytes(prob,
+ * opts) of device memory for its plan; requests start in submission order while
+ * the plans of running requests plus the idle plan cache fit in hbm_budget
+ * bytes (idle plans are freed first when room is needed).  A request whose own
+ * footprint exceeds the budget is refused at submission (WC_E_ADMISSION).
+ * Plans are kept after a request and reused, through wc_plan_retarget, for a
+ * later request of the same shape (no device allocation then).
+ *
+ * f, g, y0, y, p, u are device pointers as for wc_solve; the caller keeps them
+ * valid and untouched until the request is done, and makes sure the inputs are
+ * complete (e.g. synchronises its stream) before submitting.  The problem
+ * struct and a_face_host are copied at submission.  Results are bitwise those
+ * of the same wc_solve run alone: the kernels' reductions have a fixed order. */
+typedef struct wc_server wc_server;
+
+/* max_concurrency: worker threads (1..64).  hbm_budget: bytes (0 = 90% of the
+ * device memory free at creation). */
+wc_status wc_server_create(size_t hbm_budget, int max_concurrency, wc_server **out);
+/* Waits for running requests, cancels queued ones, frees every plan.  No other
+ * call on the server may be in progress or follow. */
+wc_status wc_server_destroy(wc_server *srv);
+wc_status wc_server_submit(wc_server *srv, const wc_problem *prob, const wc_opts *opts,
+                           const double *f, const double *g, const double *y0, double *y,
+                           double *p, double *u, uint64_t *ticket);
+/* *done = 1 once the request finished (then info, if not NULL, holds its wc_info,
+ * whose status field is the solve's wc_status).  Returns WC_E_ARG for an unknown
+ * ticket. */
+wc_status wc_server_poll(wc_server *srv, uint64_t ticket, int *done, wc_info *info);
+/* Blocks until the request is done; like wc_server_poll otherwise.  queue_ms:
+ * submission to start; total_ms: submission to completion (host clock); either
+ * may be NULL.  The ticket is released by this call. */
+wc_status wc_server_wait(wc_server *srv, uint64_t ticket, wc_info *info, double *queue_ms,
+                         double *total_ms);
+/* Removes a request that has not started (its status becomes WC_E_CANCELLED);
+ * returns WC_E_ARG if it is unknown or already running or done. */
+wc_status wc_server_cancel(wc_server *srv, uint64_t ticket);
+/* Device bytes the server holds in plans (running plus idle). */
+size_t wc_server_bytes_in_use(wc_server *srv);
 
 /* Library build identification (static string). */
 const char *wc_version(void);

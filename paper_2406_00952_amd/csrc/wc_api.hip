@@ -145,11 +145,16 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   return s;
 }
 
+// Copies a host table to the device on the plan's stream, allocating the buffer on first
+// use.  The caller keeps src alive until the stream has been synchronised.  (A copy on
+// the legacy default stream would wait for every other blocking stream of the device.)
 template <typename T>
-hipError_t upload(T **dst, const std::vector<T> &src) {
-  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
-  if (e != hipSuccess) return e;
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+hipError_t upload(hipStream_t st, T **dst, const std::vector<T> &src) {
+  if (!*dst) {
+    hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+  }
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
 template <typename T>
@@ -487,11 +492,86 @@ wc_status build_multigrid(wc_plan *p, const double *a_face_host) {
     }
   }
   hipError_t e = hipSuccess;
-  if (!faces.empty()) e = upload(&p->d_mg_a, faces);
-  if (e == hipSuccess) e = upload(&p->d_mg_shift, shift);
-  if (e == hipSuccess) e = upload(&p->d_mg_mix, mix);
-  if (e == hipSuccess) e = hipMalloc((void **)&p->d_mg_fn2, (size_t)p->n * sizeof(double));
-  if (e == hipSuccess && woff > 0) e = hipMalloc(&p->d_mg_work, woff);
+  if (!faces.empty()) e = upload(p->stream, &p->d_mg_a, faces);
+  if (e == hipSuccess) e = upload(p->stream, &p->d_mg_shift, shift);
+  if (e == hipSuccess) e = upload(p->stream, &p->d_mg_mix, mix);
+  if (e == hipSuccess && !p->d_mg_fn2)
+    e = hipMalloc((void **)&p->d_mg_fn2, (size_t)p->n * sizeof(double));
+  if (e == hipSuccess && woff > 0 && !p->d_mg_work) e = hipMalloc(&p->d_mg_work, woff);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? WC_E_NOMEM : WC_E_HIP;
+  }
+  return WC_OK;
+}
+
+// Problem scalars and options (everything but the sizes).
+void set_scalars(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
+  p->T = prob->T;
+  p->theta = prob->theta;
+  p->gamma = prob->gamma;
+  p->zeta = prob->zeta;
+  p->s2_remedy = prob->s2_remedy;
+  p->tau = prob->T / prob->n;
+  p->alpha = p->tau / std::sqrt(prob->gamma);
+  p->pc_ok = pc_path_ok(prob);
+  p->opts = *opts;
+}
+
+// FP64 (and FP32 copies of the) eigenvalue, twiddle and sine tables of Section 3.4 and
+// the face coefficients; device buffers are allocated on first use and overwritten after.
+wc_status set_tables(wc_plan *p, const wc_problem *prob) {
+  // ---- FP64 tables ----
+  const int n = p->n, N1 = p->N1, M = p->M;
+  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M);
+  for (int l = 0; l < n; ++l) {  // check every frequency of S^(2) for a zero eigenvalue
+    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
+    const std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
+    if (std::abs(l2) < 1e-13 && p->s2_remedy == 0.0) return WC_E_SINGULAR_S2;
+  }
+  for (int q = 0; q < n / 2; ++q) {  // kept frequencies l = q + 1
+    const int l = q + 1;
+    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
+    const std::complex<double> l1 = 1.0 - e;
+    std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
+    if (std::abs(l2) < 1e-13) l2 = p->s2_remedy;
+    const std::complex<double> lv = l1 / l2;
+    lam[2 * q] = lv.real();
+    lam[2 * q + 1] = lv.imag();
+  }
+  for (int k = 0; k < n; ++k) {
+    dtw[2 * k] = std::cos(p->zeta * k / n);
+    dtw[2 * k + 1] = std::sin(p->zeta * k / n);
+    twt[2 * k] = std::cos(2.0 * M_PI * k / n);
+    twt[2 * k + 1] = -std::sin(2.0 * M_PI * k / n);
+  }
+  for (int k = 0; k < N1; ++k) {
+    tws[2 * k] = std::cos(2.0 * M_PI * k / N1);
+    tws[2 * k + 1] = -std::sin(2.0 * M_PI * k / N1);
+    sn[k] = std::sin(M_PI * k / N1);
+  }
+  for (int j = 0; j < M; ++j) {
+    const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
+    mu[j] = 4.0 * p->inv_h2 * sv * sv;
+  }
+  hipError_t e = hipSuccess;
+  const std::vector<float> lam32 = to_f32(lam), twt32 = to_f32(twt), tws32 = to_f32(tws),
+                           sn32 = to_f32(sn), mu32 = to_f32(mu);
+#define WC_UP(dst, src)                 \
+  if (e == hipSuccess) e = upload(p->stream, &p->dst, src);
+  WC_UP(d_lam64, lam) WC_UP(d_dtw, dtw) WC_UP(d_twt64, twt) WC_UP(d_tws64, tws)
+  WC_UP(d_sin64, sn) WC_UP(d_mu64, mu)
+  WC_UP(d_lam32, lam32) WC_UP(d_twt32, twt32) WC_UP(d_tws32, tws32)
+  WC_UP(d_sin32, sn32) WC_UP(d_mu32, mu32)
+#undef WC_UP
+  std::vector<double> af;
+  if (e == hipSuccess && prob->a_face_host) {
+    const size_t nf = p->dims == 1 ? (size_t)M + 1 : 2 * (size_t)M * (M + 1);
+    af.assign(prob->a_face_host, prob->a_face_host + nf);
+    e = upload(p->stream, &p->d_aface, af);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? WC_E_NOMEM : WC_E_HIP;
@@ -596,20 +676,12 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   p->n = prob->n;
   p->m = prob->dims == 1 ? prob->M : prob->M * prob->M;
   p->N1 = prob->M + 1;
-  p->T = prob->T;
-  p->theta = prob->theta;
-  p->gamma = prob->gamma;
-  p->zeta = prob->zeta;
-  p->s2_remedy = prob->s2_remedy;
-  p->tau = prob->T / prob->n;
-  p->alpha = p->tau / std::sqrt(prob->gamma);
   p->h = 1.0 / (prob->M + 1);
   p->inv_h2 = 1.0 / (p->h * p->h);
   p->var_coeff = prob->a_face_host != nullptr;
-  p->pc_ok = pc_path_ok(prob);
-  p->opts = *opts;
   p->stream = (hipStream_t)stream;
   p->nvec = 2 * (size_t)p->n * p->m;
+  set_scalars(p, prob, opts);
   {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -620,59 +692,12 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   const Sizes sz = sizes_of(prob, opts);
   if (const char *e = std::getenv("WC_TS")) p->ts_time = std::atoi(e);
   if (const char *e = std::getenv("WC_TX")) p->tx_cols = std::atoi(e);
-
-  // ---- FP64 tables ----
-  const int n = p->n, N1 = p->N1, M = p->M;
-  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M);
-  for (int l = 0; l < n; ++l) {  // check every frequency of S^(2) for a zero eigenvalue
-    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
-    const std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
-    if (std::abs(l2) < 1e-13 && p->s2_remedy == 0.0) {
+  {
+    const wc_status ts = set_tables(p, prob);
+    if (ts != WC_OK) {
       free_plan(p);
-      return WC_E_SINGULAR_S2;
+      return ts;
     }
-  }
-  for (int q = 0; q < n / 2; ++q) {  // kept frequencies l = q + 1
-    const int l = q + 1;
-    const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
-    const std::complex<double> l1 = 1.0 - e;
-    std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
-    if (std::abs(l2) < 1e-13) l2 = p->s2_remedy;
-    const std::complex<double> lv = l1 / l2;
-    lam[2 * q] = lv.real();
-    lam[2 * q + 1] = lv.imag();
-  }
-  for (int k = 0; k < n; ++k) {
-    dtw[2 * k] = std::cos(p->zeta * k / n);
-    dtw[2 * k + 1] = std::sin(p->zeta * k / n);
-    twt[2 * k] = std::cos(2.0 * M_PI * k / n);
-    twt[2 * k + 1] = -std::sin(2.0 * M_PI * k / n);
-  }
-  for (int k = 0; k < N1; ++k) {
-    tws[2 * k] = std::cos(2.0 * M_PI * k / N1);
-    tws[2 * k + 1] = -std::sin(2.0 * M_PI * k / N1);
-    sn[k] = std::sin(M_PI * k / N1);
-  }
-  for (int j = 0; j < M; ++j) {
-    const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
-    mu[j] = 4.0 * p->inv_h2 * sv * sv;
-  }
-  hipError_t e = hipSuccess;
-#define WC_UP(dst, src)                 \
-  if (e == hipSuccess) e = upload(&p->dst, src);
-  WC_UP(d_lam64, lam) WC_UP(d_dtw, dtw) WC_UP(d_twt64, twt) WC_UP(d_tws64, tws)
-  WC_UP(d_sin64, sn) WC_UP(d_mu64, mu)
-  WC_UP(d_lam32, to_f32(lam)) WC_UP(d_twt32, to_f32(twt)) WC_UP(d_tws32, to_f32(tws))
-  WC_UP(d_sin32, to_f32(sn)) WC_UP(d_mu32, to_f32(mu))
-#undef WC_UP
-  if (e == hipSuccess && prob->a_face_host) {
-    const size_t nf = p->dims == 1 ? (size_t)M + 1 : 2 * (size_t)M * (M + 1);
-    std::vector<double> af(prob->a_face_host, prob->a_face_host + nf);
-    e = upload(&p->d_aface, af);
-  }
-  if (e != hipSuccess) {
-    free_plan(p);
-    return WC_E_HIP;
   }
   // ---- workspaces ----
   bool oom = false;
@@ -694,8 +719,9 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     return WC_E_NOMEM;
   }
   std::memset(p->h_scal, 0, S_COUNT * sizeof(double));
-  if (hipMemcpy(p->d_scal, p->h_scal, S_COUNT * sizeof(double), hipMemcpyHostToDevice) !=
-      hipSuccess) {
+  if (hipMemcpyAsync(p->d_scal, p->h_scal, S_COUNT * sizeof(double), hipMemcpyHostToDevice,
+                     p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
     free_plan(p);
     return WC_E_HIP;
   }
@@ -719,6 +745,24 @@ wc_status wc_plan_destroy(wc_plan *plan) {
   }
   free_plan(plan);
   return WC_OK;
+}
+
+wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
+  if (!p) return WC_E_ARG;
+  wc_status vs = validate(prob, opts);
+  if (vs != WC_OK) return vs;
+  const wc_opts &o = p->opts;
+  if (prob->dims != p->dims || prob->M != p->M || prob->n != p->n ||
+      (prob->a_face_host != nullptr) != p->var_coeff || opts->method != o.method ||
+      opts->precision != o.precision || opts->restart != o.restart ||
+      opts->flexible != o.flexible)
+    return WC_E_ARG;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return WC_E_HIP;
+  set_scalars(p, prob, opts);
+  wc_status st = set_tables(p, prob);
+  if (st == WC_OK && p->var_coeff && p->pc_ok) st = build_multigrid(p, prob->a_face_host);
+  if (st != WC_OK) p->pc_ok = false;  // tables may be half written: refuse solves
+  return st;
 }
 
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream) {

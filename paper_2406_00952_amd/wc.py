@@ -69,6 +69,7 @@ _lib.wc_plan_footprint_bytes.restype = ctypes.c_size_t
 _lib.wc_plan_footprint_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Opts)]
 _lib.wc_plan_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Opts), _vp, ctypes.POINTER(_vp)]
 _lib.wc_plan_destroy.argtypes = [_vp]
+_lib.wc_plan_retarget.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Opts)]
 _lib.wc_plan_set_stream.argtypes = [_vp, _vp]
 _lib.wc_rhs.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.wc_matvec.argtypes = [_vp, _vp, _vp]
@@ -79,13 +80,29 @@ _lib.wc_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_Inf
 _lib.wc_profile.argtypes = [_vp, ctypes.c_int]
 _lib.wc_profile_read.argtypes = [_vp, ctypes.POINTER(_KStat), ctypes.c_int]
 _lib.wc_profile_read.restype = ctypes.c_int
-for _f in ("wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
+_u64 = ctypes.c_uint64
+_lib.wc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.wc_server_destroy.argtypes = [_vp]
+_lib.wc_server_submit.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Opts), _vp, _vp, _vp,
+                                  _vp, _vp, _vp, ctypes.POINTER(_u64)]
+_lib.wc_server_poll.argtypes = [_vp, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_Info)]
+_lib.wc_server_wait.argtypes = [_vp, _u64, ctypes.POINTER(_Info), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]
+_lib.wc_server_cancel.argtypes = [_vp, _u64]
+_lib.wc_server_bytes_in_use.argtypes = [_vp]
+_lib.wc_server_bytes_in_use.restype = ctypes.c_size_t
+for _f in ("wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
+           "wc_server_wait", "wc_server_cancel"):
+    getattr(_lib, _f).restype = ctypes.c_int
+for _f in ("wc_plan_retarget", "wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
            "wc_pc_apply", "wc_recover", "wc_krylov", "wc_solve"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_plan_create",
-            "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
-            "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read"]
+            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
+            "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read",
+            "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
+            "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use"]
 
 
 def status_str(code: int) -> str:
@@ -168,6 +185,7 @@ class Plan:
         self.m = M ** dims
         self.nvec = 2 * n * self.m
         self.method, self.precision = method, precision
+        self.restart, self.flexible = restart, flexible
         self.footprint = int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
     def close(self):
@@ -184,6 +202,15 @@ class Plan:
     def _check(self, code, where):
         if code not in (WC_OK,):
             raise WcError(code, where)
+
+    def retarget(self, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0, a_face=None,
+                 tol=1e-8, maxit=500, mg_max_cycles=30, mg_tol=1e-10):
+        """Same sizes and method/precision/restart: new problem data, no allocation."""
+        pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face)
+        op = _opts(self.method, self.precision, tol, maxit, self.restart, self.flexible,
+                   mg_max_cycles, mg_tol)
+        self._check(_lib.wc_plan_retarget(self._h, ctypes.byref(pr), ctypes.byref(op)),
+                    "wc_plan_retarget")
 
     def set_stream(self, stream):
         self._stream = stream
@@ -229,3 +256,74 @@ class Plan:
             raise WcError(code, "wc_solve")
         return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
                     inf.mg_cycles_max, inf.reorth)
+
+
+def _info(inf) -> Info:
+    return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
+                inf.mg_cycles_max, inf.reorth)
+
+
+class Server:
+    """Queue of whole solves on worker threads (own HIP streams), admission by the
+    plans' device footprint, idle plans cached for reuse (include/wc.h, serving)."""
+
+    def __init__(self, hbm_budget: int = 0, max_concurrency: int = 4):
+        h = _vp()
+        code = _lib.wc_server_create(ctypes.c_size_t(int(hbm_budget)), int(max_concurrency),
+                                     ctypes.byref(h))
+        if code != WC_OK:
+            raise WcError(code, "wc_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.wc_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, f, g, y0, y, p, u=None, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4,
+               zeta=np.pi, s2_remedy=1.0, a_face=None, method="gmres_ps", precision="fp64",
+               tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
+               mg_tol=1e-10) -> int:
+        """Queue one solve; the tensors must stay alive and untouched until it is done."""
+        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
+        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol)
+        t = _u64()
+        code = _lib.wc_server_submit(self._h, ctypes.byref(pr), ctypes.byref(op), _ptr(f), _ptr(g),
+                                     _ptr(y0), _ptr(y), _ptr(p), _ptr(u), ctypes.byref(t))
+        if code != WC_OK:
+            raise WcError(code, "wc_server_submit")
+        self._keep[t.value] = (f, g, y0, y, p, u)
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int(0)
+        inf = _Info()
+        code = _lib.wc_server_poll(self._h, _u64(ticket), ctypes.byref(done), ctypes.byref(inf))
+        if code != WC_OK:
+            raise WcError(code, "wc_server_poll")
+        return (_info(inf) if done.value else None)
+
+    def wait(self, ticket: int):
+        """(Info, queue_ms, total_ms); releases the ticket."""
+        inf = _Info()
+        q, tot = ctypes.c_double(0), ctypes.c_double(0)
+        code = _lib.wc_server_wait(self._h, _u64(ticket), ctypes.byref(inf), ctypes.byref(q),
+                                   ctypes.byref(tot))
+        if code != WC_OK:
+            raise WcError(code, "wc_server_wait")
+        self._keep.pop(ticket, None)
+        return _info(inf), q.value, tot.value
+
+    def cancel(self, ticket: int) -> bool:
+        return _lib.wc_server_cancel(self._h, _u64(ticket)) == WC_OK
+
+    def bytes_in_use(self) -> int:
+        return int(_lib.wc_server_bytes_in_use(self._h))

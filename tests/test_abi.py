@@ -81,3 +81,27 @@ def test_multigrid_options_and_footprint(wc):
     assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_max_cycles=0) == 0
     assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_tol=-1.0) == 0
     assert wc.footprint_bytes(2, 31, 32, a_face=a, mg_tol=0.0) > 0
+
+
+def test_server_null_arguments(wc):
+    lib = ctypes.CDLL(LIB)
+    lib.wc_server_destroy.argtypes = [ctypes.c_void_p]
+    lib.wc_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    lib.wc_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    lib.wc_server_bytes_in_use.argtypes = [ctypes.c_void_p]
+    lib.wc_server_bytes_in_use.restype = ctypes.c_size_t
+    lib.wc_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    assert lib.wc_server_destroy(None) == wc.WC_E_ARG
+    done = ctypes.c_int(0)
+    assert lib.wc_server_poll(None, 1, ctypes.byref(done), None) == wc.WC_E_ARG
+    assert lib.wc_server_cancel(None, 1) == wc.WC_E_ARG
+    assert lib.wc_server_bytes_in_use(None) == 0
+    h = ctypes.c_void_p()
+    assert lib.wc_server_create(0, 0, ctypes.byref(h)) == wc.WC_E_ARG  # no workers
+    assert lib.wc_server_create(0, 65, ctypes.byref(h)) == wc.WC_E_ARG
+
+
+def test_retarget_null_plan(wc):
+    lib = ctypes.CDLL(LIB)
+    lib.wc_plan_retarget.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.wc_plan_retarget(None, None, None) == wc.WC_E_ARG
