@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--method", default="gmres_ps")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--flexible", type=int, default=1,
+                    help="GMRES stores P^-1 v_j (same iterates; no final preconditioner apply)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--coeff", choices=["const", "sin"], default="const",
                     help="a = 1, or a = 1 + 0.5 sin(2 pi x1) sin(2 pi x2) (multigrid)")
@@ -64,6 +66,30 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCE = {"tfft": "wc_pc.hip", "dst": "wc_pc.hip", "pair": "wc_pc.hip", "mg": "wc_mg.hip"}
+
+
+def measured_traffic(kernel, workload, args):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    profiles/<kernel>_<workload>_pmc.md (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy),
+    or None when there is none for this configuration or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
+    if not os.path.exists(path) or args.precision != "fp64" or args.method != "gmres_ps":
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = KERNEL_SOURCE.get(kernel.split("_")[0], "wc_ops.hip")
+    with open(os.path.join(ROOT, "paper_2406_00952_amd", "csrc", src), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if fields.get("source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(args, d, gpu_iters):
@@ -206,7 +232,7 @@ def main():
     p = torch.empty_like(y)
     plan = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma, method=args.method,
                    precision=args.precision, restart=args.restart, tol=1e-8, maxit=500,
-                   a_face=d["a_face"])
+                   a_face=d["a_face"], flexible=bool(args.flexible))
     log(f"plan footprint {plan.footprint / 2**30:.2f} GiB")
     for i in range(args.warmup):
         info = plan.solve(f, g, y0, y, p)
@@ -252,6 +278,21 @@ def main():
         pc_bytes = None
     pc_gbs = pc_bytes / (pc_ms * 1e-3) / 1e9 if pc_bytes else None
 
+    # ---- plain copy of one system vector: the practical HBM ceiling, and the kernel
+    #      that calibrates the FETCH_SIZE / WRITE_SIZE counters (known bytes per dispatch)
+    src = torch.randn(2 * n * m, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / 10
+    copy_bytes = 2 * src.numel() * 8
+    del src, dst
+
     # ---- roofline: dominant kernel family of the timed region -----------------
     fam = {k: v for k, v in stats.items() if v[0] > 0}
     dom = max(fam, key=lambda k: fam[k][1])
@@ -265,6 +306,8 @@ def main():
                       "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1)}
                   for k, v in pc_stats.items() if v[0] > 0}
 
+    workload = (f"heat{args.dims}d{'_sin' if args.coeff == 'sin' else ''}_M{args.M}_n{args.n}")
+    traffic = measured_traffic(dom, workload, args)
     out = {
         "metric": "solve ms to 1e-8 rel. residual; PC-apply HBM GB/s; p50/p99 served latency",
         "value": round(ms_per_step, 3),
@@ -274,12 +317,12 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64 Krylov / f32 preconditioner",
         "data": "synthetic",
-        "config": {"workload": f"heat{args.dims}d{'_sin' if args.coeff == 'sin' else ''}"
-                               f"_M{args.M}_n{args.n}",
+        "config": {"workload": workload,
                    "coeff": args.coeff,
                    "dims": args.dims, "M": args.M, "n": n, "theta": args.theta,
                    "gamma": args.gamma, "zeta": "pi", "method": args.method,
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
+                   "flexible": bool(args.flexible),
                    "dof": 2 * n * m, "seed": args.seed},
         "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
         "mg_cycles_max": infos[-1].mg_cycles_max,
@@ -290,10 +333,12 @@ def main():
                      "kernels": pc_kernels},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "avg_us": round(tot_ms * 1000.0 / launches, 2),
                      "bytes_per_launch": tot_bytes / launches},
         "kernels": kernels,
+        "copy": {"bytes": copy_bytes, "ms": round(copy_ms, 4),
+                 "GBps": round(copy_bytes / (copy_ms * 1e-3) / 1e9, 1)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -110,7 +110,10 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
     const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
     double zprev = 0.0, xprev = 0.0;
     // the loads of KB time levels are issued before the recurrence consumes them
-    constexpr int KB = 8;
+#ifndef WC_MV_KB
+#define WC_MV_KB 8
+#endif
+    constexpr int KB = WC_MV_KB;
     for (int kk0 = 0; kk0 < a.n; kk0 += KB) {
       double xc[KB], kx[KB], xok[KB], sk[KB];
 #pragma unroll

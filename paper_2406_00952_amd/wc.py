@@ -16,7 +16,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libwcirc.so")
+LIB_PATH = os.environ.get("WC_LIBRARY") or os.path.join(_HERE, "lib", "libwcirc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libwcirc.so not built ({LIB_PATH}); run `python -m paper_2406_00952_amd.build`")
