@@ -117,7 +117,7 @@ MgShape mg_shape(int dims, int M, int n, int precision) {
   for (int l = 0; l < g.nlev; ++l)
     if (mg_lds_bytes(dims, g.M[l], precision) <= kMgLdsBytes) { g.ltop = l; break; }
   for (int l = 1; l <= g.ltop; ++l)
-    g.work += 2 * (size_t)n * (dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
+    g.work += (dims == 2 ? 3 : 2) * (size_t)n * (dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
   for (int l = 1; l < g.nlev; ++l)
     g.faces += dims == 2 ? 2 * (size_t)g.M[l] * (g.M[l] + 1) : (size_t)g.M[l] + 1;
   return g;
@@ -137,7 +137,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.mg = 0;
   if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
     const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
-    s.mg = s.spec_bytes + g.work + (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
+    s.mg = s.spec_bytes * (pr->dims == 2 && g.ltop > 0 ? 2 : 1) + g.work +
+           (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
            (size_t)pr->n * 6 * sizeof(double);
   }
   s.total = s.spec_bytes + s.partials * sizeof(double) + s.tables + s.vecs +
@@ -176,6 +177,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
+  dfree(p->d_mg_u2);
   dfree(p->d_mg_fn2);
   dfree(p->d_vecs);
   if (p->h_scal) (void)hipHostFree(p->h_scal);
@@ -460,7 +462,8 @@ wc_status build_multigrid(wc_plan *p, const double *a_face_host) {
     }
     if (l >= 1 && l <= g.ltop) {
       p->mg_woff[l] = woff;
-      woff += 2 * (size_t)p->n * (p->dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
+      woff += (p->dims == 2 ? 3 : 2) * (size_t)p->n *
+              (p->dims == 2 ? (size_t)g.M[l] * g.M[l] : (size_t)g.M[l]) * es;
     }
   }
   const int nq = p->n / 2;
@@ -498,6 +501,8 @@ wc_status build_multigrid(wc_plan *p, const double *a_face_host) {
   if (e == hipSuccess && !p->d_mg_fn2)
     e = hipMalloc((void **)&p->d_mg_fn2, (size_t)p->n * sizeof(double));
   if (e == hipSuccess && woff > 0 && !p->d_mg_work) e = hipMalloc(&p->d_mg_work, woff);
+  if (e == hipSuccess && p->dims == 2 && g.ltop > 0 && !p->d_mg_u2)
+    e = hipMalloc(&p->d_mg_u2, (size_t)p->n * p->m * es);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();

@@ -118,7 +118,7 @@ struct wc_plan {
   float *d_mu32 = nullptr;
   // workspaces
   void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
-  void *d_specB = nullptr;       // n*m complex (P): x2-line-contiguous copy (2D)
+  void *d_specB = nullptr;       // n*m complex (P): multigrid fine solution (variable a)
   double *d_partials = nullptr;  // reduction partials
   double *d_scal = nullptr;      // Krylov scalars (wc::S_COUNT)
   double *h_scal = nullptr;      // pinned host mirror
@@ -132,7 +132,10 @@ struct wc_plan {
   int mg_M[wc::kMgMaxLevels] = {};
   double mg_inv_h2[wc::kMgMaxLevels] = {};
   size_t mg_aoff[wc::kMgMaxLevels] = {};  // level l's faces at d_mg_a + mg_aoff[l] (l >= 1)
-  size_t mg_woff[wc::kMgMaxLevels] = {};  // level l's u at d_mg_work + mg_woff[l] bytes, f after
+  // level l >= 1 at d_mg_work + mg_woff[l] bytes: u, then (2D) a second u, then f
+  size_t mg_woff[wc::kMgMaxLevels] = {};
+  void *d_mg_u2 = nullptr;                // 2D: second fine solution buffer
+  mutable int mg_cur[wc::kMgMaxLevels] = {};  // 2D: which u buffer holds the current values
   double *d_mg_a = nullptr;
   void *d_mg_work = nullptr;
   double *d_mg_shift = nullptr;           // n complex: shift of each system

@@ -363,6 +363,162 @@ __global__ __launch_bounds__(kThreads) void k_mg_mix(const cx<P> *__restrict__ s
   }
 }
 
+
+// ---- 2D levels in global memory: four colour sweeps per pass over LDS tiles ------
+// A workgroup owns a kTile x kTile block of one system and holds it with a halo of H
+// points in LDS; it reads uin and writes uout (halos overlap other workgroups' tiles).
+// Each sweep updates its colour on a region one point narrower than the previous one,
+// so after NS sweeps the values at distance >= NS from the halo edge are
+// exactly those of NS global sweeps (the halo points are recomputed redundantly); with
+// H = NS the tile itself is exact, with H = NS + 1 also the residual on it.
+//   uc != nullptr: the loaded values are corrected by the prolongated coarse solution
+//   (the first sweep after the coarse correction then reads corrected neighbours).
+//   partials != nullptr: after the sweeps, the squared residual of the colour not swept
+//   last (the other one vanishes) is summed per tile: partials[sys * tiles + tile].
+constexpr int kTile = 32;
+constexpr int kTileThreads = 512;
+
+// Every thread owns the region points q = tid + kTileThreads*k for the whole pass: their
+// stencil weights, right-hand side and 1/(shift + diagonal) stay in registers, so the
+// sweeps only exchange values through LDS.
+//   RST: also restrict (full weighting) the residual left by the sweeps to the coarse
+//   grid: fc[sys][J][I] for the coarse points of this tile (needs H = NS + 2: the corner
+//   residuals reach one point beyond the tile).
+template <typename P, int H, int NS, bool RST>
+__global__ __launch_bounds__(kTileThreads) void k_mg_tile(const cx<P> *__restrict__ uin,
+                                                          cx<P> *__restrict__ uout,
+                                                          const cx<P> *__restrict__ f, MgLev L,
+                                                          const double *__restrict__ shifts,
+                                                          double tau, int c0, int zero,
+                                                          const cx<P> *__restrict__ uc,
+                                                          int tiles_x,
+                                                          double *__restrict__ partials,
+                                                          cx<P> *__restrict__ fc) {
+  constexpr int R = kTile + 2 * H, NPT = R * R;
+  constexpr int PPT = (NPT + kTileThreads - 1) / kTileThreads;
+  static_assert(!RST || H >= NS + 2, "restriction needs residuals one point outside the tile");
+  __shared__ cx<P> U[NPT];
+  __shared__ cx<P> RS[RST ? NPT : 1];
+  __shared__ double red[kTileThreads / 64];
+  const int M = L.M, Mc = (M - 1) / 2, sys = blockIdx.y;
+  const int tile = blockIdx.x, i0 = (tile % tiles_x) * kTile, j0 = (tile / tiles_x) * kTile;
+  const int gi0 = i0 - H, gj0 = j0 - H;  // global index of region point (0, 0)
+  const size_t np = (size_t)M * M;
+  const cx<P> *us = uin + sys * np;
+  cx<P> *uo = uout + sys * np;
+  const cx<P> *fs = f + sys * np;
+  const cx<P> *ucs = uc ? uc + (size_t)sys * Mc * Mc : nullptr;
+  const cx<double> sh = sys_shift(shifts, sys);
+  P cw[PPT], ce[PPT], cs[PPT], cn[PPT];
+  cx<P> fv[PPT], iv[PPT];
+  bool in[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int q = threadIdx.x + kTileThreads * k;
+    const int gi = gi0 + q % R, gj = gj0 + q / R;
+    in[k] = q < NPT && gi >= 0 && gi < M && gj >= 0 && gj < M;
+    cx<P> uv{(P)0, (P)0};
+    fv[k] = uv;
+    iv[k] = uv;
+    cw[k] = ce[k] = cs[k] = cn[k] = (P)0;
+    if (in[k]) {
+      const size_t o = (size_t)gj * M + gi;
+      fv[k] = fs[o];
+      if (!zero) uv = us[o];
+      if (ucs) {
+        const cx<P> e = interp<P, 2>(ucs, Mc, gi, gj);
+        uv.x += e.x;
+        uv.y += e.y;
+      }
+      const Coef c = coef_at<2>(L, gi, gj, tau);
+      cw[k] = (P)c.w; ce[k] = (P)c.e; cs[k] = (P)c.s; cn[k] = (P)c.n;
+      const double dr = sh.x + c.d, di = sh.y, inv = 1.0 / (dr * dr + di * di);
+      iv[k] = cx<P>{(P)(dr * inv), (P)(-di * inv)};
+    }
+    if (q < NPT) U[q] = uv;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < NS; ++sw) {
+    const int color = (c0 + sw) & 1, d = sw + 1;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int q = threadIdx.x + kTileThreads * k, r = q / R, c = q % R;
+      if (!in[k] || ((gi0 + c + gj0 + r) & 1) != color || r < d || r >= R - d || c < d ||
+          c >= R - d)
+        continue;
+      const cx<P> a = U[q - 1], b = U[q + 1], s = U[q - R], n = U[q + R];
+      const P x = fv[k].x + cw[k] * a.x + ce[k] * b.x + cs[k] * s.x + cn[k] * n.x;
+      const P y = fv[k].y + cw[k] * a.y + ce[k] * b.y + cs[k] * s.y + cn[k] * n.y;
+      U[q] = cx<P>{x * iv[k].x - y * iv[k].y, x * iv[k].y + y * iv[k].x};
+    }
+    __syncthreads();
+  }
+  double acc2 = 0.0;
+  const int rc = (c0 + NS) & 1;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int q = threadIdx.x + kTileThreads * k, r = q / R, c = q % R;
+    if (!in[k] || r < H || r >= H + kTile || c < H || c >= H + kTile) continue;
+    const int gi = gi0 + c, gj = gj0 + r;
+    const cx<P> up = U[q];
+    uo[(size_t)gj * M + gi] = up;
+    if (partials && ((gi + gj) & 1) == rc) {
+      const cx<P> a = U[q - 1], b = U[q + 1], s = U[q - R], n = U[q + R];
+      const double dd = (double)cw[k] + ce[k] + cs[k] + cn[k];
+      const double dr = sh.x + dd, di = sh.y;
+      const double rx = (double)fv[k].x + cw[k] * a.x + ce[k] * b.x + cs[k] * s.x +
+                        cn[k] * n.x - dr * up.x + di * up.y;
+      const double ry = (double)fv[k].y + cw[k] * a.y + ce[k] * b.y + cs[k] * s.y +
+                        cn[k] * n.y - dr * up.y - di * up.x;
+      acc2 += rx * rx + ry * ry;
+    }
+  }
+  if constexpr (RST) {
+    // residual at the points of colour rc on the tile and one point beyond it
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int q = threadIdx.x + kTileThreads * k, r = q / R, c = q % R;
+      if (!in[k] || r < H - 1 || r > H + kTile || c < H - 1 || c > H + kTile ||
+          ((gi0 + c + gj0 + r) & 1) != rc)
+        continue;
+      const cx<P> up = U[q], a = U[q - 1], b = U[q + 1], s = U[q - R], n = U[q + R];
+      const double dd = (double)cw[k] + ce[k] + cs[k] + cn[k];
+      const P dr = (P)(sh.x + dd), di = (P)sh.y;
+      RS[q] = cx<P>{fv[k].x + cw[k] * a.x + ce[k] * b.x + cs[k] * s.x + cn[k] * n.x -
+                        dr * up.x + di * up.y,
+                    fv[k].y + cw[k] * a.y + ce[k] * b.y + cs[k] * s.y + cn[k] * n.y -
+                        dr * up.y - di * up.x};
+    }
+    __syncthreads();
+    // coarse point (I, J) sits on fine (2I+1, 2J+1): 4/16 of the centre residual plus 1/16 of
+    // each corner; the edge neighbours have the other colour, whose residual vanishes
+    constexpr int KC = kTile / 2;
+    for (int t = threadIdx.x; t < KC * KC; t += kTileThreads) {
+      const int I = i0 / 2 + t % KC, J = j0 / 2 + t / KC;
+      if (I >= Mc || J >= Mc) continue;
+      const int q = (2 * J + 1 - gj0) * R + (2 * I + 1 - gi0);
+      const cx<P> c0v = RS[q], c1 = RS[q - R - 1], c2 = RS[q - R + 1], c3 = RS[q + R - 1],
+                  c4 = RS[q + R + 1];
+      fc[(size_t)sys * Mc * Mc + (size_t)J * Mc + I] =
+          cx<P>{(P)0.0625 * ((P)4 * c0v.x + c1.x + c2.x + c3.x + c4.x),
+                (P)0.0625 * ((P)4 * c0v.y + c1.y + c2.y + c3.y + c4.y)};
+    }
+  }
+  if (partials) {
+    double v = acc2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kTileThreads / 64; ++i) t += red[i];
+      partials[(size_t)sys * gridDim.x + tile] = t;
+    }
+  }
+}
+
 // ---- the small levels: one workgroup cycles one system entirely in LDS ----------
 template <int D> __device__ __forceinline__ int npts_of(int M) { return D == 2 ? M * M : M; }
 
@@ -446,13 +602,19 @@ size_t level_pts(const wc_plan &p, int l) {
   return p.dims == 2 ? (size_t)p.mg_M[l] * p.mg_M[l] : (size_t)p.mg_M[l];
 }
 
+// 2D levels keep two u buffers: a tile pass reads one and writes the other (a workgroup's
+// halo overlaps its neighbours' tiles), then mg_cur flips.
+template <typename P> cx<P> *level_u_buf(const wc_plan &p, int l, int which) {
+  if (l == 0) return (cx<P> *)(which ? p.d_mg_u2 : p.d_specB);
+  return (cx<P> *)((char *)p.d_mg_work + p.mg_woff[l]) + (size_t)which * p.n * level_pts(p, l);
+}
 template <typename P> cx<P> *level_u(const wc_plan &p, int l) {
-  if (l == 0) return (cx<P> *)p.d_specB;
-  return (cx<P> *)((char *)p.d_mg_work + p.mg_woff[l]);
+  return level_u_buf<P>(p, l, p.dims == 2 ? p.mg_cur[l] : 0);
 }
 template <typename P> cx<P> *level_f(const wc_plan &p, int l) {
   if (l == 0) return (cx<P> *)p.d_specA;
-  return level_u<P>(p, l) + (size_t)p.n * level_pts(p, l);
+  return (cx<P> *)((char *)p.d_mg_work + p.mg_woff[l]) +
+         (size_t)(p.dims == 2 ? 2 : 1) * p.n * level_pts(p, l);
 }
 
 unsigned blocks_for(size_t threads) { return (unsigned)((threads + kThreads - 1) / kThreads); }
@@ -468,7 +630,49 @@ hipError_t smooth(const wc_plan &p, int l, int color, bool zero, const cx<P> *uc
   return hipGetLastError();
 }
 
-template <typename P, int D> hipError_t vcycle(const wc_plan &p, int l, bool zero) {
+
+int tiles_x(int M) { return (M + kTile - 1) / kTile; }
+
+// pre-smoothing (red first) with the restriction of its residual to level l+1, or
+// post-smoothing (black first, coarse correction folded into the load; H = 5 when the
+// residual partials are wanted)
+template <typename P>
+hipError_t tile_sweeps(const wc_plan &p, int l, bool post, bool zero, double *partials) {
+  const int M = p.mg_M[l], tx = tiles_x(M);
+  dim3 grid(tx * tx, p.n);
+  const double arr = (double)p.n * level_pts(p, l) * sizeof(cx<P>);
+  ProfScope ps(p, post ? K_MG_SMOOTH : K_MG_RESTRICT,
+               arr * (zero ? 2.0 : 3.0) + arr / 4);
+  const int cur = p.mg_cur[l];
+  const cx<P> *uin = level_u_buf<P>(p, l, cur);
+  cx<P> *uout = level_u_buf<P>(p, l, cur ^ 1);
+  const cx<P> *f = level_f<P>(p, l);
+  const MgLev L = level(p, l);
+  if (!post)
+    hipLaunchKernelGGL((k_mg_tile<P, 6, 4, true>), grid, dim3(kTileThreads), 0, p.stream, uin,
+                       uout, f, L, p.d_mg_shift, p.tau, 0, zero ? 1 : 0, nullptr, tx, nullptr,
+                       level_f<P>(p, l + 1));
+  else if (partials)
+    hipLaunchKernelGGL((k_mg_tile<P, 5, 4, false>), grid, dim3(kTileThreads), 0, p.stream, uin,
+                       uout, f, L, p.d_mg_shift, p.tau, 1, 0, level_u<P>(p, l + 1), tx, partials,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_mg_tile<P, 4, 4, false>), grid, dim3(kTileThreads), 0, p.stream, uin,
+                       uout, f, L, p.d_mg_shift, p.tau, 1, 0, level_u<P>(p, l + 1), tx, nullptr,
+                       nullptr);
+  p.mg_cur[l] = cur ^ 1;
+  return hipGetLastError();
+}
+
+// whether the fine level's post-smoothing pass can also produce the residual partials
+bool fused_norm(const wc_plan &p) {
+  if (p.dims != 2 || p.mg_ltop == 0) return false;
+  const size_t t = (size_t)tiles_x(p.mg_M[0]);
+  return t * t * (size_t)p.n <= (size_t)kMgPartials;
+}
+
+template <typename P, int D>
+hipError_t vcycle(const wc_plan &p, int l, bool zero, double *partials = nullptr) {
   hipError_t e;
   if (l == p.mg_ltop) {
     MgLdsLevels lv{};
@@ -484,26 +688,30 @@ template <typename P, int D> hipError_t vcycle(const wc_plan &p, int l, bool zer
     return hipGetLastError();
   }
 #define WC_E(x) if ((e = (x)) != hipSuccess) return e
-  WC_E((smooth<P, D>(p, l, 0, zero, nullptr)));
-  WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
-  WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
-  WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
-  {
-    const int Mc = p.mg_M[l + 1];
+  if constexpr (D == 2) {
+    WC_E((tile_sweeps<P>(p, l, false, zero, nullptr)));  // also restricts to level l+1
+  } else {
+    WC_E((smooth<P, D>(p, l, 0, zero, nullptr)));
+    WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
+    WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
+    WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
     const size_t thr = (size_t)p.n * level_pts(p, l + 1);
     ProfScope ps(p, K_MG_RESTRICT,
                  (double)p.n * (2.0 * level_pts(p, l) + level_pts(p, l + 1)) * sizeof(cx<P>));
-    (void)Mc;
     hipLaunchKernelGGL((k_mg_restrict<P, D>), dim3(blocks_for(thr)), dim3(kThreads), 0,
                        p.stream, level_u<P>(p, l), level_f<P>(p, l), level(p, l),
                        level_f<P>(p, l + 1), p.d_mg_shift, p.tau, p.n);
     WC_E(hipGetLastError());
   }
   WC_E((vcycle<P, D>(p, l + 1, true)));
-  WC_E((smooth<P, D>(p, l, 1, false, level_u<P>(p, l + 1))));
-  WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
-  WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
-  WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
+  if constexpr (D == 2) {
+    WC_E((tile_sweeps<P>(p, l, true, false, partials)));
+  } else {
+    WC_E((smooth<P, D>(p, l, 1, false, level_u<P>(p, l + 1))));
+    WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
+    WC_E((smooth<P, D>(p, l, 1, false, nullptr)));
+    WC_E((smooth<P, D>(p, l, 0, false, nullptr)));
+  }
 #undef WC_E
   return hipSuccess;
 }
@@ -536,7 +744,7 @@ template <typename P, int D> hipError_t norms(const wc_plan &p, bool resid_mode)
 template <typename P> hipError_t mix(const wc_plan &p, bool out) {
   const size_t cnt = (size_t)(p.n / 2) * p.m;
   const double *mx = p.opts.method == WC_GMRES_PS ? p.d_mg_mix : nullptr;
-  const cx<P> *src = out ? (const cx<P> *)p.d_specB : (const cx<P> *)p.d_specA;
+  const cx<P> *src = out ? (const cx<P> *)level_u<P>(p, 0) : (const cx<P> *)p.d_specA;
   ProfScope ps(p, K_MG_MIX, 2.0 * p.n * p.m * sizeof(cx<P>));
   hipLaunchKernelGGL((k_mg_mix<P>), dim3(blocks_for(cnt)), dim3(kThreads), 0, p.stream, src,
                      (cx<P> *)p.d_specA, mx, p.m, p.n / 2, 1.0 / p.n, out ? 1 : 0);
@@ -552,11 +760,20 @@ template <typename P, int D> hipError_t mg_apply_t(const wc_plan &p) {
   const bool check = tol > 0.0;
   if (check && (e = norms<P, D>(p, false)) != hipSuccess) return e;
   int c = 0;
+  const bool fused = check && fused_norm(p);
   for (; c < p.opts.mg_max_cycles;) {
-    if ((e = vcycle<P, D>(p, 0, c == 0)) != hipSuccess) return e;
+    if ((e = vcycle<P, D>(p, 0, c == 0, fused ? p.d_partials : nullptr)) != hipSuccess) return e;
     ++c;
     if (!check) continue;
-    if ((e = norms<P, D>(p, true)) != hipSuccess) return e;
+    if (fused) {
+      const int t = tiles_x(p.mg_M[0]);
+      ProfScope ps(p, K_FINALIZE, 8.0 * p.n * t * t);
+      hipLaunchKernelGGL(k_mg_reduce, dim3(1), dim3(kThreads), 0, p.stream, p.d_partials, t * t,
+                         p.n, p.d_mg_fn2, p.d_scal, S_MG_RELRES, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = norms<P, D>(p, true)) != hipSuccess) {
+      return e;
+    }
     if ((e = hipMemcpyAsync(p.h_scal + S_MG_RELRES, p.d_scal + S_MG_RELRES, sizeof(double),
                             hipMemcpyDeviceToHost, p.stream)) != hipSuccess)
       return e;
