@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--method", default="gmres_ps")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick the preconditioner tile widths by timing them first")
+    ap.add_argument("--graphs", type=int, default=1,
+                    help="replay captured Krylov iterations (not while tracing kernels)")
     ap.add_argument("--flexible", type=int, default=1,
                     help="GMRES stores P^-1 v_j (same iterates; no final preconditioner apply)")
     ap.add_argument("--seed", type=int, default=0)
@@ -232,8 +236,10 @@ def main():
     p = torch.empty_like(y)
     plan = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma, method=args.method,
                    precision=args.precision, restart=args.restart, tol=1e-8, maxit=500,
-                   a_face=d["a_face"], flexible=bool(args.flexible))
+                   a_face=d["a_face"], flexible=bool(args.flexible), graphs=bool(args.graphs))
     log(f"plan footprint {plan.footprint / 2**30:.2f} GiB")
+    tiles = plan.autotune(reps=3) if args.autotune else (0, 0)
+    log(f"tile widths (time FFT, x2 pass): {tiles}")
     for i in range(args.warmup):
         info = plan.solve(f, g, y0, y, p)
         log(f"warmup {i}: iters {info.iters} relres {info.relres:.2e} {info.ms:.1f} ms")
@@ -322,7 +328,7 @@ def main():
                    "dims": args.dims, "M": args.M, "n": n, "theta": args.theta,
                    "gamma": args.gamma, "zeta": "pi", "method": args.method,
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
-                   "flexible": bool(args.flexible),
+                   "flexible": bool(args.flexible), "tiles_ts_tx": list(tiles),
                    "dof": 2 * n * m, "seed": args.seed},
         "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
         "mg_cycles_max": infos[-1].mg_cycles_max,

@@ -92,7 +92,11 @@ typedef struct {
   int restart;        /* GMRES restart length (1..32) */
   int flexible;       /* GMRES: store preconditioned basis (forced on for WC_MIXED) */
   int mg_max_cycles;  /* multigrid V-cycles per spatial solve (variable a) */
-  double mg_tol;      /* multigrid relative residual target (variable a) */
+  double mg_tol;      /* multigrid relative residual target (variable a); 0 = exactly
+                         mg_max_cycles cycles */
+  int graphs;         /* 1: replay each Krylov iteration's launches from a captured
+                         hipGraph (cached per plan; not while profiling, and for
+                         variable a only with mg_tol = 0) */
 } wc_opts;
 
 typedef struct {
@@ -112,7 +116,7 @@ typedef struct wc_plan wc_plan;
 const char *wc_status_str(int status);
 
 /* Defaults: GMRES_PS, FP64, tol 1e-8, maxit 500, restart 30, flexible 0,
- * mg_max_cycles 30, mg_tol 1e-10. */
+ * mg_max_cycles 30, mg_tol 1e-10, graphs 1. */
 void wc_opts_default(wc_opts *opts);
 
 /* Device bytes a plan for (problem, opts) allocates (tables, spectral
@@ -133,6 +137,12 @@ wc_status wc_plan_destroy(wc_plan *plan);
  * WC_E_ARG the plan refuses solves until a retarget succeeds. */
 wc_status wc_plan_retarget(wc_plan *plan, const wc_problem *prob, const wc_opts *opts);
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
+/* Times the preconditioner apply (reps applies per candidate, after one warm-up)
+ * for every time-FFT tile width (4, 8, 16 spatial columns per workgroup) and,
+ * in 2D with a = 1, every x2-pass tile width (4, 8, 16 columns), keeps the
+ * fastest pair in the plan and reports it (ts, tx may be NULL).  Uses the
+ * plan's Krylov vectors as scratch: call it between solves.  Synchronous. */
+wc_status wc_plan_autotune(wc_plan *plan, int reps, int *ts, int *tx);
 
 /* Right-hand side of the transformed system (Section 1: f_tilde, g_tilde
  * with M = I; eqn:main_system / eqn:main_system_nonsym).

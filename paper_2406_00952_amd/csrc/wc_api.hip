@@ -164,6 +164,59 @@ void dfree(T *&p) {
   p = nullptr;
 }
 
+void drop_graphs(wc_plan *p) {
+  for (int i = 0; i < wc_plan::kGraphSlots; ++i) {
+    if (p->gexec[i]) (void)hipGraphExecDestroy(p->gexec[i]);
+    p->gexec[i] = nullptr;
+    p->gkey[i] = nullptr;
+  }
+}
+
+bool graphs_usable(const wc_plan *p) {
+  return p->opts.graphs && !p->prof.on && !p->graphs_failed &&
+         (!p->var_coeff || p->opts.mg_tol == 0.0);  // the multigrid test reads the host
+}
+
+// Enqueues `body` (work on p->stream) directly, or replays the graph cached in `slot`,
+// capturing it on a private stream the first time (and again when `key` changed).
+// A capture that fails turns graphs off for the plan; the work is then enqueued directly.
+template <typename F>
+hipError_t run_captured(wc_plan *p, int slot, const void *key, F body) {
+  if (!graphs_usable(p)) return body();
+  if (p->gexec[slot] && p->gkey[slot] != key) {
+    (void)hipGraphExecDestroy(p->gexec[slot]);
+    p->gexec[slot] = nullptr;
+  }
+  if (!p->gexec[slot]) {
+    if (!p->cap_stream && hipStreamCreate(&p->cap_stream) != hipSuccess) {
+      (void)hipGetLastError();
+      p->graphs_failed = true;
+      return body();
+    }
+    hipStream_t saved = p->stream;
+    p->stream = p->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t eb = body();
+      const hipError_t ee = hipStreamEndCapture(p->cap_stream, &g);
+      e = eb != hipSuccess ? eb : ee;
+    }
+    p->stream = saved;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess && g) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess || !ex) {
+      (void)hipGetLastError();
+      p->graphs_failed = true;
+      return body();
+    }
+    p->gexec[slot] = ex;
+    p->gkey[slot] = key;
+  }
+  return hipGraphLaunch(p->gexec[slot], p->stream);
+}
+
 void free_plan(wc_plan *p) {
   if (!p) return;
   for (auto &r : p->prof.recs) {
@@ -178,6 +231,8 @@ void free_plan(wc_plan *p) {
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
+  drop_graphs(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_mg_fn2);
   dfree(p->d_vecs);
   if (p->h_scal) (void)hipHostFree(p->h_scal);
@@ -249,14 +304,21 @@ wc_status run_minres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (code == ST_NONFINITE) return WC_E_NONFINITE;
     if (code == ST_BREAKDOWN) { st = WC_E_BREAKDOWN; break; }
     while (code == ST_RUNNING && iters < p->opts.maxit) {
-      WC_TRY(launch_matvec(*p, Z, AZ, p->d_partials, &np));
-      WC_TRY(launch_minres_scalar(*p, 1, np, tol));
-      WC_TRY(launch_lincomb3(*p, V0, AZ, V1, V0, S_CV0, 0, 0, 0));
-      WC_TRY(launch_pc_apply(*p, V0, ZN, true, &np));
-      WC_TRY(launch_minres_scalar(*p, 2, np, tol));
-      WC_TRY(launch_minres_update(*p, W0, W1, Z, x, R, V0));
-      WC_TRY(launch_minres_scalar(*p, 3, red_blocks(p->nvec), tol));
-      WC_TRY(sync_read(p, 0, 16));
+      auto body = [&]() -> hipError_t {
+        hipError_t e;
+        int nq = 0;
+        if ((e = launch_matvec(*p, Z, AZ, p->d_partials, &nq)) != hipSuccess) return e;
+        if ((e = launch_minres_scalar(*p, 1, nq, tol)) != hipSuccess) return e;
+        if ((e = launch_lincomb3(*p, V0, AZ, V1, V0, S_CV0, 0, 0, 0)) != hipSuccess) return e;
+        if ((e = launch_pc_apply(*p, V0, ZN, true, &nq)) != hipSuccess) return e;
+        if ((e = launch_minres_scalar(*p, 2, nq, tol)) != hipSuccess) return e;
+        if ((e = launch_minres_update(*p, W0, W1, Z, x, R, V0)) != hipSuccess) return e;
+        if ((e = launch_minres_scalar(*p, 3, red_blocks(p->nvec), tol)) != hipSuccess) return e;
+        return hipMemcpyAsync(p->h_scal, p->d_scal, 16 * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream);
+      };
+      WC_TRY(run_captured(p, wc_plan::kGraphSlots - 2 + (V0 == p->vec(1) ? 0 : 1), x, body));
+      WC_TRY(hipStreamSynchronize(p->stream));
       ++iters;
       std::swap(V0, V1);
       std::swap(W0, W1);
@@ -343,19 +405,28 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       double *Vn = V + (size_t)(j + 1) * nv;
       double *Zj = flex ? Zb + (size_t)j * nv : Zb;
       int np = 0;
-      WC_TRY(launch_pc_apply(*p, Vj, Zj, false, nullptr));
-      // Arnoldi on E = Ahat P^{-1} - I (same Krylov space, H = H_E + I): Ahat z - v is
-      // not dominated by v, so one classical Gram-Schmidt pass normally suffices
-      WC_TRY(launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj));
-      WC_TRY(launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np));
-      WC_TRY(launch_gs_finalize(*p, 1, j, np));
-      WC_TRY(launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np));
-      WC_TRY(launch_gs_finalize(*p, 2, j, np));
-      WC_TRY(launch_multidot(*p, V, j + 1, Vn, false, gate, &np));
-      WC_TRY(launch_gs_finalize(*p, 3, j, np));
-      WC_TRY(launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np));
-      WC_TRY(launch_gs_finalize(*p, 4, j, np));
-      WC_TRY(sync_read(p, S_WN2, S_D2 + j + 1 - S_WN2));
+      auto body = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = launch_pc_apply(*p, Vj, Zj, false, nullptr)) != hipSuccess) return e;
+        // Arnoldi on E = Ahat P^{-1} - I (same Krylov space, H = H_E + I): Ahat z - v is
+        // not dominated by v, so one classical Gram-Schmidt pass normally suffices
+        if ((e = launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj)) != hipSuccess) return e;
+        if ((e = launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np)) != hipSuccess) return e;
+        if ((e = launch_gs_finalize(*p, 1, j, np)) != hipSuccess) return e;
+        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np)) != hipSuccess)
+          return e;
+        if ((e = launch_gs_finalize(*p, 2, j, np)) != hipSuccess) return e;
+        if ((e = launch_multidot(*p, V, j + 1, Vn, false, gate, &np)) != hipSuccess) return e;
+        if ((e = launch_gs_finalize(*p, 3, j, np)) != hipSuccess) return e;
+        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np)) != hipSuccess)
+          return e;
+        if ((e = launch_gs_finalize(*p, 4, j, np)) != hipSuccess) return e;
+        return hipMemcpyAsync(p->h_scal + S_WN2, p->d_scal + S_WN2,
+                              (S_D2 + j + 1 - S_WN2) * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream);
+      };
+      WC_TRY(run_captured(p, j, nullptr, body));
+      WC_TRY(hipStreamSynchronize(p->stream));
       const bool two = p->h_scal[S_REORTH] != 0.0;
       reorth += two ? 1 : 0;
       if (!two && p->prof.on) {
@@ -661,6 +732,7 @@ void wc_opts_default(wc_opts *o) {
   o->flexible = 0;
   o->mg_max_cycles = 30;
   o->mg_tol = 1e-10;
+  o->graphs = 1;
 }
 
 size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts) {
@@ -763,11 +835,55 @@ wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *op
       opts->flexible != o.flexible)
     return WC_E_ARG;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return WC_E_HIP;
+  drop_graphs(p);  // captured launches hold the old scalars
   set_scalars(p, prob, opts);
   wc_status st = set_tables(p, prob);
   if (st == WC_OK && p->var_coeff && p->pc_ok) st = build_multigrid(p, prob->a_face_host);
   if (st != WC_OK) p->pc_ok = false;  // tables may be half written: refuse solves
   return st;
+}
+
+wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
+  if (!p || reps < 1) return WC_E_ARG;
+  if (!p->pc_ok) return WC_E_UNSUPPORTED;
+  double *v = p->vec(0), *w = p->vec(1);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return WC_E_HIP;
+  const bool prof = p->prof.on;
+  p->prof.on = false;
+  WC_TRY(launch_fill(*p, v, 1.0, p->nvec));
+  const int tss[3] = {4, 8, 16}, txs[3] = {4, 8, 16};
+  const int ntx = (p->dims == 2 && !p->var_coeff) ? 3 : 1;
+  float best = -1.f;
+  int bts = p->ts_time, btx = p->tx_cols;
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < 3 && e == hipSuccess; ++it)
+    for (int ix = 0; ix < ntx && e == hipSuccess; ++ix) {
+      p->ts_time = tss[it];
+      p->tx_cols = ntx > 1 ? txs[ix] : 0;
+      e = launch_pc_apply(*p, v, w, false, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pc_apply(*p, v, w, false, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess && (best < 0.f || ms < best)) {
+        best = ms;
+        bts = p->ts_time;
+        btx = p->tx_cols;
+      }
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  p->prof.on = prof;
+  p->ts_time = bts;
+  p->tx_cols = btx;
+  drop_graphs(p);  // captured launches hold the previous kernel choice
+  if (e != hipSuccess) return WC_E_HIP;
+  if (ts_out) *ts_out = bts;
+  if (tx_out) *tx_out = btx;
+  return WC_OK;
 }
 
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream) {
@@ -815,6 +931,7 @@ wc_status wc_krylov(wc_plan *plan, const double *b, double *x, wc_info *info) {
   const auto t1 = std::chrono::steady_clock::now();
   inf->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   inf->mg_cycles_max = plan->mg_cycles_max;
+  if (plan->var_coeff && plan->opts.mg_tol == 0.0) inf->mg_cycles_max = plan->opts.mg_max_cycles;
   inf->status = st;
   return st;
 }

@@ -144,6 +144,13 @@ struct wc_plan {
   mutable int mg_cycles_last = 0, mg_cycles_max = 0;
 
   mutable wc::Profiler prof;
+  // captured Krylov iterations: GMRES step j in slot j, the two MINRES buffer
+  // arrangements in the last two; key = the caller pointer the work also depends on
+  static constexpr int kGraphSlots = wc::kMaxRestart + 2;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[kGraphSlots] = {};
+  const void *gkey[kGraphSlots] = {};
+  bool graphs_failed = false;
 
   double *vec(int i) const { return d_vecs + (size_t)i * nvec; }
 };

@@ -46,7 +46,8 @@ class _Problem(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("restart", ctypes.c_int), ("flexible", ctypes.c_int),
-                ("mg_max_cycles", ctypes.c_int), ("mg_tol", ctypes.c_double)]
+                ("mg_max_cycles", ctypes.c_int), ("mg_tol", ctypes.c_double),
+                ("graphs", ctypes.c_int)]
 
 
 class _KStat(ctypes.Structure):
@@ -70,6 +71,8 @@ _lib.wc_plan_footprint_bytes.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTE
 _lib.wc_plan_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Opts), _vp, ctypes.POINTER(_vp)]
 _lib.wc_plan_destroy.argtypes = [_vp]
 _lib.wc_plan_retarget.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Opts)]
+_lib.wc_plan_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)]
 _lib.wc_plan_set_stream.argtypes = [_vp, _vp]
 _lib.wc_rhs.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.wc_matvec.argtypes = [_vp, _vp, _vp]
@@ -94,12 +97,12 @@ _lib.wc_server_bytes_in_use.restype = ctypes.c_size_t
 for _f in ("wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
            "wc_server_wait", "wc_server_cancel"):
     getattr(_lib, _f).restype = ctypes.c_int
-for _f in ("wc_plan_retarget", "wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
+for _f in ("wc_plan_retarget", "wc_plan_autotune", "wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
            "wc_pc_apply", "wc_recover", "wc_krylov", "wc_solve"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_plan_create",
-            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
+            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
             "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read",
             "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
             "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use"]
@@ -134,13 +137,14 @@ def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face):
     return pr, keep
 
 
-def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol):
+def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs=True):
     op = _Opts()
     _lib.wc_opts_default(ctypes.byref(op))
     op.method = METHODS[method] if isinstance(method, str) else int(method)
     op.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     op.tol, op.maxit, op.restart, op.flexible = tol, maxit, restart, int(flexible)
     op.mg_max_cycles, op.mg_tol = mg_max_cycles, mg_tol
+    op.graphs = int(bool(graphs))
     return op
 
 
@@ -168,10 +172,11 @@ class Plan:
 
     def __init__(self, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                  a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
-                 restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10, stream=None):
+                 restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10, stream=None,
+                 graphs=True):
         import torch
         pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
-        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol)
+        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs)
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
@@ -185,7 +190,7 @@ class Plan:
         self.m = M ** dims
         self.nvec = 2 * n * self.m
         self.method, self.precision = method, precision
-        self.restart, self.flexible = restart, flexible
+        self.restart, self.flexible, self.graphs = restart, flexible, graphs
         self.footprint = int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
     def close(self):
@@ -208,9 +213,16 @@ class Plan:
         """Same sizes and method/precision/restart: new problem data, no allocation."""
         pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face)
         op = _opts(self.method, self.precision, tol, maxit, self.restart, self.flexible,
-                   mg_max_cycles, mg_tol)
+                   mg_max_cycles, mg_tol, self.graphs)
         self._check(_lib.wc_plan_retarget(self._h, ctypes.byref(pr), ctypes.byref(op)),
                     "wc_plan_retarget")
+
+    def autotune(self, reps: int = 5):
+        """Pick the fastest preconditioner tile widths on this device; returns (ts, tx)."""
+        ts, tx = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(_lib.wc_plan_autotune(self._h, int(reps), ctypes.byref(ts), ctypes.byref(tx)),
+                    "wc_plan_autotune")
+        return ts.value, tx.value
 
     def set_stream(self, stream):
         self._stream = stream
@@ -291,10 +303,10 @@ class Server:
     def submit(self, f, g, y0, y, p, u=None, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4,
                zeta=np.pi, s2_remedy=1.0, a_face=None, method="gmres_ps", precision="fp64",
                tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
-               mg_tol=1e-10) -> int:
+               mg_tol=1e-10, graphs=True) -> int:
         """Queue one solve; the tensors must stay alive and untouched until it is done."""
         pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
-        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol)
+        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs)
         t = _u64()
         code = _lib.wc_server_submit(self._h, ctypes.byref(pr), ctypes.byref(op), _ptr(f), _ptr(g),
                                      _ptr(y0), _ptr(y), _ptr(p), _ptr(u), ctypes.byref(t))
