@@ -7,9 +7,14 @@ and p), inputs resident in HBM.  Prints one JSON line.
 Default workload: 2D heat tracking on the unit square, a = 1, M = 255
 (h = 1/256), n = 256 steps, T = 1, theta = 1/2 (Crank-Nicolson),
 gamma = 1e-4, seeded smooth modes + N(0, 1e-3) noise in f and g,
-GMRES(30) with the block omega-circulant preconditioner P_S (zeta = pi), FP64.
+GMRES(30) with the block omega-circulant preconditioner P_S (zeta = pi), FP64,
+in the low-rank form (the Arnoldi process in the compact coordinates that the GMRES
+proposition gives: same iterates, no full-length basis; --lowrank 0 for the
+standard form).  Only GMRES-P_S in FP64 with a = 1 has that form; other methods,
+precisions and coefficients run the standard form.
 
 Also measured in the same run:
+  * the standard form of the same solve (full-length basis, matvec each step);
   * per-kernel HIP-event timings over the timed region (library tracing);
     the roofline entry is the kernel family with the largest share of time,
     achieved = algorithmic bytes / duration, against the 8 TB/s HBM peak;
@@ -52,6 +57,10 @@ def parse():
                     help="pick the preconditioner tile widths by timing them first")
     ap.add_argument("--graphs", type=int, default=1,
                     help="replay captured Krylov iterations (not while tracing kernels)")
+    ap.add_argument("--lowrank", type=int, default=1,
+                    help="GMRES-P_S Arnoldi in the compact coordinates of the GMRES proposition")
+    ap.add_argument("--standard-steps", type=int, default=3,
+                    help="also time the standard GMRES form (full basis, matvec per step)")
     ap.add_argument("--flexible", type=int, default=1,
                     help="GMRES stores P^-1 v_j (same iterates; no final preconditioner apply)")
     ap.add_argument("--seed", type=int, default=0)
@@ -211,6 +220,8 @@ def serve(args):
 
 def main():
     args = parse()
+    if args.method != "gmres_ps" or args.precision != "fp64" or args.coeff != "const":
+        args.lowrank = 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no "
               "multi-GPU path in this build", file=sys.stderr)
@@ -236,7 +247,8 @@ def main():
     p = torch.empty_like(y)
     plan = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma, method=args.method,
                    precision=args.precision, restart=args.restart, tol=1e-8, maxit=500,
-                   a_face=d["a_face"], flexible=bool(args.flexible), graphs=bool(args.graphs))
+                   a_face=d["a_face"], flexible=bool(args.flexible) and not args.lowrank,
+                   graphs=bool(args.graphs), lowrank=bool(args.lowrank))
     log(f"plan footprint {plan.footprint / 2**30:.2f} GiB")
     tiles = plan.autotune(reps=3) if args.autotune else (0, 0)
     log(f"tile widths (time FFT, x2 pass): {tiles}")
@@ -258,6 +270,29 @@ def main():
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     iters = infos[-1].iters
     relres = max(i.relres for i in infos)
+
+    # ---- the standard form of the same solve (full-length basis, matvec each step) -----
+    standard = None
+    if args.lowrank and args.standard_steps > 0:
+        sp = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma,
+                     method=args.method, precision=args.precision, restart=args.restart,
+                     tol=1e-8, maxit=500, a_face=d["a_face"], flexible=bool(args.flexible),
+                     graphs=bool(args.graphs))
+        if args.autotune:
+            sp.autotune(reps=3)
+        sp.solve(f, g, y0, y, p)
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        for _ in range(args.standard_steps):
+            si = sp.solve(f, g, y0, y, p)
+        torch.cuda.synchronize()
+        standard = {"ms_per_solve": round((time.perf_counter() - ts0) * 1000.0 / args.standard_steps, 3),
+                    "iters": si.iters, "relres": si.relres, "steps": args.standard_steps,
+                    "flexible": bool(args.flexible)}
+        log(f"standard form: {standard}")
+        sp.close()
+        del sp
+        torch.cuda.empty_cache()
 
     # ---- preconditioner apply alone ------------------------------------------
     v = torch.randn(2 * n * m, dtype=torch.float64, device=dev)
@@ -328,11 +363,13 @@ def main():
                    "dims": args.dims, "M": args.M, "n": n, "theta": args.theta,
                    "gamma": args.gamma, "zeta": "pi", "method": args.method,
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
-                   "flexible": bool(args.flexible), "tiles_ts_tx": list(tiles),
+                   "flexible": bool(args.flexible) and not args.lowrank,
+                   "lowrank": bool(args.lowrank), "tiles_ts_tx": list(tiles),
                    "dof": 2 * n * m, "seed": args.seed},
         "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
         "mg_cycles_max": infos[-1].mg_cycles_max,
         "solves_per_s": round(1000.0 / ms_per_step, 3),
+        "standard_form": standard,
         "pc_apply": {"ms": round(pc_ms, 4), "model_bytes": pc_bytes,
                      "GBps": round(pc_gbs, 1) if pc_gbs else None,
                      "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4) if pc_gbs else None,

@@ -97,6 +97,14 @@ typedef struct {
   int graphs;         /* 1: replay each Krylov iteration's launches from a captured
                          hipGraph (cached per plan; not while profiling, and for
                          variable a only with mg_tol = 0) */
+  int lowrank;        /* GMRES-P_S with a = 1, FP64: run the Arnoldi process in the
+                         compact coordinates given by the GMRES proposition (Sec. 3):
+                         Ahat - P_S acts only in time and has rank one per block row,
+                         so every Krylov vector is c r0_perp + [g (x) s1; r (x) s2].
+                         Same iterates; the basis takes (restart+1)(1+2m) doubles and
+                         each step is one preconditioner apply whose last pass
+                         contracts over time.  WC_E_ARG with any other method,
+                         precision or a variable coefficient. */
 } wc_opts;
 
 typedef struct {
@@ -116,7 +124,7 @@ typedef struct wc_plan wc_plan;
 const char *wc_status_str(int status);
 
 /* Defaults: GMRES_PS, FP64, tol 1e-8, maxit 500, restart 30, flexible 0,
- * mg_max_cycles 30, mg_tol 1e-10, graphs 1. */
+ * mg_max_cycles 30, mg_tol 1e-10, graphs 1, lowrank 0. */
 void wc_opts_default(wc_opts *opts);
 
 /* Device bytes a plan for (problem, opts) allocates (tables, spectral
@@ -130,7 +138,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
                          wc_plan **out);
 wc_status wc_plan_destroy(wc_plan *plan);
 /* Re-point a plan at another problem of the same shape without allocating: same
- * dims, M, n, method, precision, restart and flexible, and a_face_host given iff
+ * dims, M, n, method, precision, restart, flexible and lowrank, and a_face_host given iff
  * it was at creation (WC_E_ARG otherwise).  theta, gamma, T, zeta, s2_remedy,
  * the coefficient values and the remaining options may change; every table is
  * rebuilt.  Synchronises the plan's stream first.  On an error other than

@@ -26,7 +26,7 @@ const char *kernel_name(int id) {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
       "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re", "mg_smooth", "mg_restrict",
-      "mg_lds", "mg_norm", "mg_mix"};
+      "mg_lds", "mg_norm", "mg_mix", "lr_setup"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -66,6 +66,8 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   if (!(op->tol > 0) || op->maxit < 1) return WC_E_ARG;
   if (op->method == WC_GMRES_PS && (op->restart < 1 || op->restart > kMaxRestart)) return WC_E_ARG;
   if (op->method == WC_MINRES_ABS_PS && pr->a_face_host) return WC_E_ARG;  // |P_S| needs a == 1
+  if (op->lowrank && (op->method != WC_GMRES_PS || op->precision != WC_FP64 || pr->a_face_host))
+    return WC_E_ARG;
   const double m = std::pow((double)pr->M, pr->dims);
   if (m * pr->n * 2.0 > 4.0e9) return WC_E_ARG;  // 32-bit spatial indexing inside kernels
   if (pr->a_face_host) {
@@ -87,6 +89,7 @@ bool pc_path_ok(const wc_problem *pr) {
 
 int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
   (void)pr;
+  if (op->lowrank) return 2 + 2;  // r0, P^{-1} update; B, X
   if (op->method == WC_GMRES_PS) {
     const bool flex = op->flexible || op->precision == WC_MIXED;
     return (op->restart + 1) + (flex ? op->restart : 1) + 1 + 2;  // V, Z, T, B, X
@@ -134,6 +137,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.partials = parts + 64;
   s.tables = 1 << 20;
   s.vecs = (size_t)krylov_vectors(pr, op) * s.nvec * sizeof(double);
+  if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g and r
+    s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 2 * (size_t)pr->n) * sizeof(double);
   s.mg = 0;
   if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
     const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
@@ -231,6 +236,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
+  dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat);
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_mg_fn2);
@@ -358,13 +364,28 @@ wc_status run_minres(wc_plan *p, const double *b, double *x, wc_info *info) {
 // kept as a device scalar): the matvec writes straight into the next basis slot and no
 // scaling pass is needed; all coefficients are rescaled on the host.
 // ---------------------------------------------------------------------------------
+//
+// Low-rank form (opts.lowrank): by the GMRES proposition Ahat = P_S + (Ahat - P_S) with
+// Ahat - P_S = omega diag(g r^T, r g^T) (x) I, so E v = (Ahat - P_S) P^{-1} v lies in
+// {[g (x) a; r (x) b]} and the Krylov space of r0 is span{r0_perp} + that range, r0_perp
+// being r0's part orthogonal to it (N0 = ||r0_perp||^2).  A basis vector
+// v = c r0_perp + [g (x) s1; r (x) s2] is kept as its coordinates [sqrt(N0) c; |g| s1; |r| s2],
+// whose Euclidean inner products equal those of the full vectors (the three parts are
+// mutually orthogonal), so the Gram-Schmidt kernels run unchanged on 1 + 2m numbers; E v_j is one preconditioner apply on the generated
+// v_j whose inverse time transform contracts over time.  The update x += P^{-1} sum y_j v_j
+// is one more apply.
+// ---------------------------------------------------------------------------------
 wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   const int k = p->opts.restart;
-  const bool flex = p->opts.flexible || p->opts.precision == WC_MIXED;
+  const bool lr = p->opts.lowrank != 0;
+  if (lr && !p->lr_ok) return WC_E_UNSUPPORTED;
+  const bool flex = !lr && (p->opts.flexible || p->opts.precision == WC_MIXED);
   const size_t nv = p->nvec;
-  double *V = p->vec(0);
-  double *Zb = p->vec(k + 1);
-  double *T = p->vec(k + 1 + (flex ? k : 1));
+  const size_t len = lr ? p->lr_len : nv;  // basis vector length (and stride)
+  double *V = lr ? p->d_lr_hat : p->vec(0);
+  double *R0 = lr ? p->vec(0) : nullptr;    // full residual of the cycle (low-rank form)
+  double *Zb = lr ? nullptr : p->vec(k + 1);
+  double *T = lr ? p->vec(1) : p->vec(k + 1 + (flex ? k : 1));
   const double tol = p->opts.tol;
   const double *gate = p->d_scal + S_REORTH;
   WC_TRY(launch_dot(*p, b, b, S_DOT));
@@ -382,16 +403,28 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   wc_status st = WC_E_MAXIT;
   double relres = 1.0, relres_est = 1.0;
   for (;;) {
+    double *Rf = lr ? R0 : V;  // the cycle's full residual
     if (first) {
-      WC_TRY(launch_lincomb3(*p, V, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
+      WC_TRY(launch_lincomb3(*p, Rf, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
     } else {
       WC_TRY(launch_matvec(*p, x, T, p->d_partials, nullptr));
-      WC_TRY(launch_lincomb3(*p, V, b, T, nullptr, -1, 1.0, -1.0, 0.0));
+      WC_TRY(launch_lincomb3(*p, Rf, b, T, nullptr, -1, 1.0, -1.0, 0.0));
     }
-    WC_TRY(launch_dot(*p, V, V, S_NU2));
-    WC_TRY(sync_read(p, S_NU2, 1));
-    const double beta = std::sqrt(p->h_scal[S_NU2]);
-    relres = beta / bnorm;
+    double beta;
+    if (lr) {
+      WC_TRY(launch_dot(*p, R0, R0, S_DOT));
+      WC_TRY(launch_lr_setup(*p, R0, V));
+      WC_TRY(launch_dot(*p, V, V, S_NU2, len));
+      WC_TRY(sync_read(p, S_DOT, 1));
+      WC_TRY(sync_read(p, S_NU2, 1));
+      relres = std::sqrt(p->h_scal[S_DOT]) / bnorm;
+      beta = std::sqrt(p->h_scal[S_NU2]);
+    } else {
+      WC_TRY(launch_dot(*p, V, V, S_NU2));
+      WC_TRY(sync_read(p, S_NU2, 1));
+      beta = std::sqrt(p->h_scal[S_NU2]);
+      relres = beta / bnorm;
+    }
     if (!std::isfinite(relres)) { st = WC_E_NONFINITE; break; }
     if (relres <= tol) { st = WC_OK; break; }
     if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
@@ -401,24 +434,32 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     int jd = 0;
     bool stop = false;
     for (int j = 0; j < k && !stop; ++j) {
-      double *Vj = V + (size_t)j * nv;
-      double *Vn = V + (size_t)(j + 1) * nv;
-      double *Zj = flex ? Zb + (size_t)j * nv : Zb;
+      double *Vj = V + (size_t)j * len;
+      double *Vn = V + (size_t)(j + 1) * len;
+      double *Zj = lr ? nullptr : (flex ? Zb + (size_t)j * nv : Zb);
       int np = 0;
       auto body = [&]() -> hipError_t {
         hipError_t e;
-        if ((e = launch_pc_apply(*p, Vj, Zj, false, nullptr)) != hipSuccess) return e;
-        // Arnoldi on E = Ahat P^{-1} - I (same Krylov space, H = H_E + I): Ahat z - v is
-        // not dominated by v, so one classical Gram-Schmidt pass normally suffices
-        if ((e = launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj)) != hipSuccess) return e;
-        if ((e = launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np)) != hipSuccess) return e;
+        if (lr) {  // E v_j in compact coordinates
+          if ((e = launch_pc_lowrank(*p, R0, Vj, Vn, nullptr)) != hipSuccess) return e;
+        } else {
+          if ((e = launch_pc_apply(*p, Vj, Zj, false, nullptr)) != hipSuccess) return e;
+          // Arnoldi on E = Ahat P^{-1} - I (same Krylov space, H = H_E + I): Ahat z - v is
+          // not dominated by v, so one classical Gram-Schmidt pass normally suffices
+          if ((e = launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj)) != hipSuccess) return e;
+        }
+        if ((e = launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np, len)) != hipSuccess)
+          return e;
         if ((e = launch_gs_finalize(*p, 1, j, np)) != hipSuccess) return e;
-        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np)) != hipSuccess)
+        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np, len)) !=
+            hipSuccess)
           return e;
         if ((e = launch_gs_finalize(*p, 2, j, np)) != hipSuccess) return e;
-        if ((e = launch_multidot(*p, V, j + 1, Vn, false, gate, &np)) != hipSuccess) return e;
+        if ((e = launch_multidot(*p, V, j + 1, Vn, false, gate, &np, len)) != hipSuccess)
+          return e;
         if ((e = launch_gs_finalize(*p, 3, j, np)) != hipSuccess) return e;
-        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np)) != hipSuccess)
+        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np, len)) !=
+            hipSuccess)
           return e;
         if ((e = launch_gs_finalize(*p, 4, j, np)) != hipSuccess) return e;
         return hipMemcpyAsync(p->h_scal + S_WN2, p->d_scal + S_WN2,
@@ -466,7 +507,13 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     }
     for (int i = 0; i < jd; ++i) y[i] /= nu[i];
     WC_TRY(write_scalar(p, S_Y, y.data(), jd));
-    if (flex) {
+    if (lr) {
+      double *U = V + (size_t)(k + 1) * len;
+      WC_TRY(launch_fill(*p, U, 0.0, len));
+      WC_TRY(launch_multiaxpy(*p, U, V, jd, S_Y, 1.0, false, nullptr, nullptr, len));
+      WC_TRY(launch_pc_lowrank(*p, R0, U, nullptr, T));
+      WC_TRY(launch_lincomb3(*p, x, x, T, nullptr, -1, 1.0, 1.0, 0.0));
+    } else if (flex) {
       WC_TRY(launch_multiaxpy(*p, x, Zb, jd, S_Y, 1.0, false, nullptr, nullptr));
     } else {
       WC_TRY(launch_fill(*p, T, 0.0, nv));
@@ -641,6 +688,33 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   WC_UP(d_lam32, lam32) WC_UP(d_twt32, twt32) WC_UP(d_tws32, tws32)
   WC_UP(d_sin32, sn32) WC_UP(d_mu32, mu32)
 #undef WC_UP
+  // low-rank GMRES: S_n - B_n = -omega g r^T with omega = e^{i zeta} = -1 (zeta = pi):
+  // g = e_1 + (1 - theta) B_n e_1, r_k = q^{n-k} / (theta + omega (1 - theta) q^{n-1}),
+  // q = -(1 - theta)/theta (k = 1..n; the wrap-around corners of S^(1), S^(2))
+  std::vector<double> gr;
+  p->lr_ok = false;
+  if (p->opts.lowrank) {
+    const double th = p->theta, q = -(1.0 - th) / th;
+    gr.assign(2 * (size_t)n, 0.0);
+    std::vector<double> z(n, 0.0);  // B_n e_1 = (B^(2))^{-1} (e_1 - e_2)
+    for (int k = 0; k < n; ++k) {
+      const double rhs = k == 0 ? 1.0 : (k == 1 ? -1.0 : 0.0);
+      z[k] = (rhs - (k > 0 ? (1.0 - th) * z[k - 1] : 0.0)) / th;
+    }
+    for (int k = 0; k < n; ++k) gr[k] = (k == 0 ? 1.0 : 0.0) + (1.0 - th) * z[k];
+    const double den = th - (1.0 - th) * std::pow(q, n - 1);
+    double g2 = 0.0, r2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      gr[n + k] = std::pow(q, n - 1 - k) / den;
+      g2 += gr[k] * gr[k];
+      r2 += gr[n + k] * gr[n + k];
+    }
+    // the remedied singular S^(2) (theta = 1/2, n odd) breaks the rank-one form
+    p->lr_ok = std::fabs(den) > 1e-12 && std::isfinite(g2) && std::isfinite(r2) && p->pc_ok;
+    p->lr_gn = std::sqrt(g2);
+    p->lr_rn = std::sqrt(r2);
+    if (e == hipSuccess) e = upload(p->stream, &p->d_lr_gr, gr);
+  }
   std::vector<double> af;
   if (e == hipSuccess && prob->a_face_host) {
     const size_t nf = p->dims == 1 ? (size_t)M + 1 : 2 * (size_t)M * (M + 1);
@@ -733,6 +807,7 @@ void wc_opts_default(wc_opts *o) {
   o->mg_max_cycles = 30;
   o->mg_tol = 1e-10;
   o->graphs = 1;
+  o->lowrank = 0;
 }
 
 size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts) {
@@ -787,7 +862,12 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
   p->nkvec = krylov_vectors(prob, opts);
-  alloc((void **)&p->d_vecs, sz.vecs);
+  alloc((void **)&p->d_vecs, (size_t)p->nkvec * p->nvec * sizeof(double));
+  if (opts->lowrank) {
+    p->lr_len = 1 + 2 * (size_t)p->m;
+    alloc((void **)&p->d_lr_s0, 2 * (size_t)p->m * sizeof(double));
+    alloc((void **)&p->d_lr_hat, (size_t)(opts->restart + 2) * p->lr_len * sizeof(double));
+  }
   if (!oom && hipHostMalloc((void **)&p->h_scal, S_COUNT * sizeof(double), 0) != hipSuccess)
     oom = true;
   if (oom) {
@@ -832,7 +912,7 @@ wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *op
   if (prob->dims != p->dims || prob->M != p->M || prob->n != p->n ||
       (prob->a_face_host != nullptr) != p->var_coeff || opts->method != o.method ||
       opts->precision != o.precision || opts->restart != o.restart ||
-      opts->flexible != o.flexible)
+      opts->flexible != o.flexible || opts->lowrank != o.lowrank)
     return WC_E_ARG;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return WC_E_HIP;
   drop_graphs(p);  // captured launches hold the old scalars

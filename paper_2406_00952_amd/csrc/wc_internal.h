@@ -56,6 +56,8 @@ enum ScalarSlot : int {
   S_Y = 224,     // kMaxRestart update coefficients
   S_DOT = 300,   // scratch dot results
   S_MG_RELRES = 310,  // largest relative residual over the multigrid systems
+  S_LR_N0 = 320,      // low-rank GMRES: squared norm of r0's part outside the correction's range
+  S_LR_SQN0,          //   its square root (0 when that part vanishes)
   S_COUNT = 512
 };
 
@@ -66,7 +68,7 @@ enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
   K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_MG_SMOOTH, K_MG_RESTRICT,
-  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_COUNT
+  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_COUNT
 };
 const char *kernel_name(int id);
 
@@ -142,6 +144,14 @@ struct wc_plan {
   double *d_mg_mix = nullptr;             // n/2 x 6: rotation of the two block rows (P_S)
   double *d_mg_fn2 = nullptr;             // n: squared right-hand side norms
   mutable int mg_cycles_last = 0, mg_cycles_max = 0;
+  // low-rank GMRES (a = 1, FP64, GMRES-P_S): Ahat - P_S = -diag(D, D^T) (x) I with
+  // D = S_n - B_n = -omega g r^T; the Krylov basis lives in compact coordinates
+  bool lr_ok = false;
+  double lr_gn = 0, lr_rn = 0;      // |g|, |r|
+  size_t lr_len = 0;                // 1 + 2m
+  double *d_lr_gr = nullptr;        // 2n: g then r
+  double *d_lr_s0 = nullptr;        // 2m
+  double *d_lr_hat = nullptr;       // (restart + 2) compact vectors of lr_len
 
   mutable wc::Profiler prof;
   // captured Krylov iterations: GMRES step j in slot j, the two MINRES buffer
@@ -180,6 +190,29 @@ struct ProfScope {
 
 namespace wc {
 
+// ---- low-rank GMRES ---------------------------------------------------------
+// Compact input (low-rank GMRES): the system vector is generated on the fly from the
+// compact coordinates h = [sqrt(N0) c; |g| s1; |r| s2] of c r0_perp + [g (x) s1; r (x) s2],
+// r0_perp = r0 - [g (x) s0_1; r (x) s0_2]:
+//   v1[k][s] = c r0_1[k][s] + g_k (s1[s] - c s0_1[s]),  v2 likewise with r_k and s2.
+struct GenIn {
+  const double *hat;    // compact coordinates (1 + 2m)
+  const double *s0;     // 2m: projection coefficients of r0 on the range of the correction
+  const double *gr;     // 2n: g_k then r_k
+  const double *sqn0;   // device scalar: sqrt(N0) (0 when r0 lies in that range)
+  double inv_gn, inv_rn;
+};
+
+// Contracted output (low-rank GMRES): instead of z, the compact coordinates of
+// (Ahat - P_S) z = omega [g (x) sum_k r_k z1_k; r (x) sum_k g_k z2_k]:
+//   hat[0] = 0, hat[1+s] = |g| omega sum_k r_k z1[k][s], hat[1+m+s] = |r| omega sum_k g_k z2[k][s].
+struct ContractOut {
+  double *hat;
+  const double *gr;  // 2n: g_k then r_k
+  double gn_omega, rn_omega;
+};
+
+
 // ---- launchers (wc_ops.hip) -------------------------------------------------
 // Step 2 for variable a: batched multigrid on d_specA (in/out), d_specB = fine solution.
 hipError_t mg_space_apply(const wc_plan &p);
@@ -197,7 +230,8 @@ int red_blocks(size_t n);
 hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,
                            const double *c, int slot, double h0, double h1, double h2);
 // partials of <a, b> (one per block) -> finalize into d_scal[slot]
-hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot);
+hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot,
+                      size_t len = 0);
 hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, int nsum,
                            int slot);
 hipError_t launch_minres_update(const wc_plan &p, double *w0, const double *w1,
@@ -205,21 +239,32 @@ hipError_t launch_minres_update(const wc_plan &p, double *w0, const double *w1,
 hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double tol);
 // <basis_i, w> for i < nb (plus <w, w> when self) -> partials [sum][block]; *nblocks out.
 // gate (device pointer or null): the launch does nothing when *gate == 0.
+// len: vector length and basis stride (0: a system vector)
 hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
-                           bool self, const double *gate, int *nblocks);
+                           bool self, const double *gate, int *nblocks, size_t len = 0);
 // w += sign * sum_i scal[slot+i] basis_i; partials of ||w||^2 when norm.
 hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb,
                             int slot, double sign, bool norm, const double *gate,
-                            int *nblocks);
+                            int *nblocks, size_t len = 0);
 // Gram-Schmidt bookkeeping of GMRES iteration j (one block): stage 1 first-pass dots,
 // 2 first-pass norm and DGKS test, 3 second-pass dots, 4 second-pass norm.
 hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count);
 hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count);
+hipError_t launch_copy(const wc_plan &p, double *dst, const double *src, size_t count);
 
 // ---- preconditioner (wc_pc.hip) --------------------------------------------
 // w = P^{-1} v.  With dot = true the last pass also writes per-block partial sums of
 // <w, v> to p.d_partials[0..*nparts) (v must then not alias w).
 hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool dot, int *nparts);
+// P^{-1} applied to the vector generated from compact coordinates hat_in (low-rank GMRES);
+// hat_out != nullptr: write the compact coordinates of (Ahat - P_S) P^{-1} v there,
+// else write P^{-1} v to w.
+hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *hat_in,
+                             double *hat_out, double *w);
+// s0 = projection coefficients of r0 on the correction's range; N0 = ||r0 - [g s0_1; r s0_2]||^2
+// and sqrt(N0) into the scalar slots; hat = [sqrt(N0), |g| s0_1, |r| s0_2].  Expects
+// ||r0||^2 in d_scal[S_DOT] (launch_dot before).
+hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
 bool pc_supported(int n, int N1);
 int pc_partials_needed(int n, int m, int precision);
 

@@ -466,6 +466,79 @@ __global__ __launch_bounds__(kThreads) void k_fill(double *__restrict__ dst, dou
     dst[i] = val;
 }
 
+
+// ---- low-rank GMRES setup -------------------------------------------------------
+// s0_1[s] = sum_k g_k r0_1[k][s] / |g|^2, s0_2[s] = sum_k r_k r0_2[k][s] / |r|^2: the
+// coefficients of the orthogonal projection of r0 on {[g (x) a; r (x) b]}.
+__global__ __launch_bounds__(kThreads) void k_lr_project(const double *__restrict__ r0,
+                                                         const double *__restrict__ gr,
+                                                         double *__restrict__ s0, int n, int m,
+                                                         double inv_g2, double inv_r2) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  const double *a = r0, *b = r0 + (size_t)n * m;
+  double sa = 0.0, sb = 0.0;
+  for (int k = 0; k < n; ++k) {
+    sa += gr[k] * a[(size_t)k * m + s];
+    sb += gr[n + k] * b[(size_t)k * m + s];
+  }
+  s0[s] = sa * inv_g2;
+  s0[m + s] = sb * inv_r2;
+}
+
+// partials of ||r0 - [g (x) s0_1; r (x) s0_2]||^2
+__global__ __launch_bounds__(kThreads) void k_lr_perp(const double *__restrict__ r0,
+                                                      const double *__restrict__ gr,
+                                                      const double *__restrict__ s0, int n,
+                                                      int m, double *__restrict__ partials) {
+  __shared__ double red[kThreads / 64];
+  const size_t nm = (size_t)n * m;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nm;
+       i += (size_t)gridDim.x * kThreads) {
+    const int k = (int)(i / m), s = (int)(i % m);
+    const double d1 = r0[i] - gr[k] * s0[s];
+    const double d2 = r0[nm + i] - gr[n + k] * s0[m + s];
+    acc += d1 * d1 + d2 * d2;
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// S[slot] = N0 (sum of the partials), S[slot + 1] = sqrt(N0) or 0 when N0 <= tiny * ||r0||^2;
+// hat = [S[slot + 1], |g| s0_1, |r| s0_2]
+__global__ __launch_bounds__(kThreads) void k_lr_hat0(const double *__restrict__ partials,
+                                                      int count, double *__restrict__ S,
+                                                      int slot,
+                                                      const double *__restrict__ r0n2p,
+                                                      const double *__restrict__ s0, int m,
+                                                      double gn, double rn,
+                                                      double *__restrict__ hat) {
+  __shared__ double red[kThreads / 64];
+  if (blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kThreads) acc += partials[i];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+      const double n0 = r > 1e-28 * *r0n2p ? r : 0.0;
+      S[slot] = n0;
+      S[slot + 1] = sqrt(n0);
+      hat[0] = sqrt(n0);
+    }
+  }
+  for (int s = blockIdx.x * kThreads + threadIdx.x; s < m; s += gridDim.x * kThreads) {
+    hat[1 + s] = gn * s0[s];
+    hat[1 + m + s] = rn * s0[m + s];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy(double *__restrict__ dst,
+                                                   const double *__restrict__ src, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
 }  // namespace
 
 int red_blocks(size_t n) {
@@ -521,12 +594,14 @@ hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, 
   return hipGetLastError();
 }
 
-hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot) {
-  const int nb = red_blocks(p.nvec);
+hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot,
+                      size_t len) {
+  const size_t nv = len ? len : p.nvec;
+  const int nb = red_blocks(nv);
   hipError_t e;
   {
-    ProfScope ps(p, K_DOT, 8.0 * p.nvec * (a == b ? 1 : 2));
-    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, p.stream, a, b, p.nvec, p.d_partials);
+    ProfScope ps(p, K_DOT, 8.0 * nv * (a == b ? 1 : 2));
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, p.stream, a, b, nv, p.d_partials);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
@@ -555,19 +630,20 @@ hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double 
   X(32)
 
 hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
-                           bool self, const double *gate, int *nblocks) {
-  const int g = red_blocks(p.nvec);
+                           bool self, const double *gate, int *nblocks, size_t len) {
+  const size_t nv = len ? len : p.nvec;
+  const int g = red_blocks(nv);
   if (nblocks) *nblocks = g;
-  ProfScope ps(p, gate ? K_MULTIDOT_RE : K_MULTIDOT, 8.0 * p.nvec * (nb + 1));
+  ProfScope ps(p, gate ? K_MULTIDOT_RE : K_MULTIDOT, 8.0 * nv * (nb + 1));
   switch (nb) {
 #define CASE_NB(K)                                                                           \
   case K:                                                                                    \
     if (self)                                                                                \
       hipLaunchKernelGGL((k_multidot<K, true>), dim3(g), dim3(kThreads), 0, p.stream, basis, \
-                         w, p.nvec, p.d_partials, gate);                                     \
+                         w, nv, p.d_partials, gate);                                         \
     else                                                                                     \
       hipLaunchKernelGGL((k_multidot<K, false>), dim3(g), dim3(kThreads), 0, p.stream,       \
-                         basis, w, p.nvec, p.d_partials, gate);                              \
+                         basis, w, nv, p.d_partials, gate);                                  \
     break;
     WC_NB_CASES(CASE_NB)
 #undef CASE_NB
@@ -577,15 +653,17 @@ hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const 
 }
 
 hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb, int slot,
-                            double sign, bool norm, const double *gate, int *nblocks) {
-  const int g = red_blocks(p.nvec);
+                            double sign, bool norm, const double *gate, int *nblocks,
+                            size_t len) {
+  const size_t nv = len ? len : p.nvec;
+  const int g = red_blocks(nv);
   if (nblocks) *nblocks = g;
   double *parts = norm ? p.d_partials : nullptr;
-  ProfScope ps(p, gate ? K_MULTIAXPY_RE : K_MULTIAXPY, 8.0 * p.nvec * (nb + 2));
+  ProfScope ps(p, gate ? K_MULTIAXPY_RE : K_MULTIAXPY, 8.0 * nv * (nb + 2));
   switch (nb) {
 #define CASE_NB(K)                                                                            \
   case K:                                                                                     \
-    hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, basis, p.nvec, \
+    hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, basis, nv,      \
                        p.d_scal, slot, sign, parts, gate);                                    \
     break;
     WC_NB_CASES(CASE_NB)
@@ -599,6 +677,38 @@ hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count) {
   ProfScope ps(p, K_FINALIZE, 8.0 * count * (j + 2));
   hipLaunchKernelGGL(k_gs_finalize, dim3(1), dim3(kThreads), 0, p.stream, p.d_partials, count,
                      p.d_scal, stage, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const wc_plan &p, double *dst, const double *src, size_t count) {
+  size_t b = (count + kThreads * 4 - 1) / (kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  ProfScope ps(p, K_FILL, 16.0 * count);
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)b), dim3(kThreads), 0, p.stream, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat) {
+  hipError_t e;
+  {
+    ProfScope ps(p, K_LR_SETUP, 8.0 * p.nvec + 16.0 * p.m);
+    hipLaunchKernelGGL(k_lr_project, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       p.stream, r0, p.d_lr_gr, p.d_lr_s0, p.n, p.m,
+                       1.0 / (p.lr_gn * p.lr_gn), 1.0 / (p.lr_rn * p.lr_rn));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int nb = red_blocks(p.nvec / 2);
+  {
+    ProfScope ps(p, K_LR_SETUP, 8.0 * p.nvec + 16.0 * p.m);
+    hipLaunchKernelGGL(k_lr_perp, dim3(nb), dim3(kThreads), 0, p.stream, r0, p.d_lr_gr,
+                       p.d_lr_s0, p.n, p.m, p.d_partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ProfScope ps(p, K_LR_SETUP, 8.0 * p.lr_len);
+  hipLaunchKernelGGL(k_lr_hat0, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     p.stream, p.d_partials, nb, p.d_scal, (int)S_LR_N0, p.d_scal + S_DOT,
+                     p.d_lr_s0, p.m, p.lr_gn, p.lr_rn, hat);
   return hipGetLastError();
 }
 

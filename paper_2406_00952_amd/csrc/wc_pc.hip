@@ -24,6 +24,8 @@
 // in LDS; waves synchronise only themselves, so the four waves of a workgroup never wait
 // on each other between stages.  The DST running sum is a segmented wave-shuffle scan.
 
+#include <type_traits>
+
 #include "wc_internal.h"
 
 namespace wc {
@@ -316,11 +318,12 @@ __device__ __forceinline__ void mode_op(cx<P> &a, cx<P> &b, cx<P> l, P musum, in
 
 // ---- step 1a: time transform of both block rows ------------------------------
 // v: 2 x (n, m) FP64.  W: [q][half][s] complex, q = 0..n/2-1 <-> frequency l = q+1.
-template <typename P, int N, int TS_>
+template <typename P, int N, int TS_, bool GEN>
 __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict__ v,
                                                        cx<P> *__restrict__ W,
                                                        const cx<double> *__restrict__ dtw,
-                                                       const cx<P> *__restrict__ twg, int m) {
+                                                       const cx<P> *__restrict__ twg, int m,
+                                                       GenIn gi) {
   using C = TimeCfg<P, N, TS_>;
   constexpr int TS = TS_, S = C::S, PS = C::PS;
   __shared__ cx<P> buf[C::PN * S];
@@ -332,6 +335,18 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
   // all global loads of the tile are issued before any is consumed
   constexpr int LIT = (N * TS + kThreads - 1) / kThreads;
   double ra[LIT], rb[LIT];
+  // generated input: this thread's column is fixed (kThreads is a multiple of TS), so its
+  // coefficients of the two range terms are formed once
+  double gc = 0.0, a1 = 0.0, a2 = 0.0;
+  if constexpr (GEN) {
+    static_assert(kThreads % TS == 0, "a thread's column must not change");
+    const int gs = s0 + tid % TS;
+    gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+    if (gs < m) {
+      a1 = gi.hat[1 + gs] * gi.inv_gn - gc * gi.s0[gs];
+      a2 = gi.hat[1 + m + gs] * gi.inv_rn - gc * gi.s0[m + gs];
+    }
+  }
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int idx = tid + it * kThreads;
@@ -341,6 +356,10 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     if ((N * TS % kThreads == 0 || idx < N * TS) && gs < m) {
       ra[it] = v1[(size_t)k * m + gs];
       rb[it] = v2[(size_t)k * m + gs];
+      if constexpr (GEN) {
+        ra[it] = gc * ra[it] + gi.gr[k] * a1;
+        rb[it] = gc * rb[it] + gi.gr[N + k] * a2;
+      }
     }
   }
   if constexpr (C::TW_LDS)
@@ -371,18 +390,20 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
 }
 
 // ---- step 3b: inverse time transform, real output, optional fused <w, dotv> ----
-template <typename P, int N, int TS_>
+template <typename P, int N, int TS_, bool CONTRACT>
 __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
                                                        double *__restrict__ out,
                                                        const cx<double> *__restrict__ dtw,
                                                        const cx<P> *__restrict__ twg, int m,
                                                        const double *__restrict__ dotv,
-                                                       double *__restrict__ partials) {
+                                                       double *__restrict__ partials,
+                                                       ContractOut co) {
   using C = TimeCfg<P, N, TS_>;
   constexpr int TS = TS_, S = C::S, PS = C::PS;
   __shared__ cx<P> buf[C::PN * S];
   __shared__ cx<P> stw[C::TW_LDS ? N : 1];
   __shared__ double red[kThreads / 64];
+  __shared__ double sums[CONTRACT ? 2 * kThreads : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = blockIdx.x * TS;
   constexpr int HT = (N / 2) * TS;
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   __syncthreads();
   wfft<P, N, 1, TS / 4, S, PS, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
   __syncthreads();
-  double acc = 0.0;
+  double acc = 0.0, c1 = 0.0, c2 = 0.0;
   double *o1 = out;
   double *o2 = out + (size_t)N * m;
   for (int idx = tid; idx < N * TS; idx += kThreads) {
@@ -425,10 +446,32 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
     const double zx = (double)z.x, zy = (double)z.y;
     const double r1 = zx * d.x + zy * d.y;
     const double r2 = zy * d.x - zx * d.y;
-    const size_t g = (size_t)k * m + gs;
-    o1[g] = r1;
-    o2[g] = r2;
-    if (dotv) acc += r1 * dotv[g] + r2 * dotv[(size_t)N * m + g];
+    if constexpr (CONTRACT) {  // kThreads is a multiple of TS: this thread's s is fixed
+      c1 += co.gr[N + k] * r1;
+      c2 += co.gr[k] * r2;
+    } else {
+      const size_t g = (size_t)k * m + gs;
+      o1[g] = r1;
+      o2[g] = r2;
+      if (dotv) acc += r1 * dotv[g] + r2 * dotv[(size_t)N * m + g];
+    }
+  }
+  if constexpr (CONTRACT) {
+    static_assert(kThreads % TS == 0, "a thread's column must not change");
+    sums[tid] = c1;
+    sums[kThreads + tid] = c2;
+    __syncthreads();
+    if (tid < TS && s0 + tid < m) {
+      double a1 = 0.0, a2 = 0.0;
+      for (int t = tid; t < kThreads; t += TS) {
+        a1 += sums[t];
+        a2 += sums[kThreads + t];
+      }
+      co.hat[1 + s0 + tid] = co.gn_omega * a1;
+      co.hat[1 + m + s0 + tid] = co.rn_omega * a2;
+    }
+    if (blockIdx.x == 0 && tid == 0) co.hat[0] = 0.0;
+    return;
   }
   if (dotv) {
     const double r = block_sum(acc, red);
@@ -647,48 +690,70 @@ template <typename P, int N1> constexpr int default_tx() {
 }
 
 template <typename P, int N, int TS>
-hipError_t tfft_fwd_ts(const wc_plan &p, const double *v) {
+hipError_t tfft_fwd_ts(const wc_plan &p, const double *v, const GenIn *gen) {
   if constexpr (!TimeCfg<P, N, TS>::FITS) {
-    return tfft_fwd_ts<P, N, 4>(p, v);
+    return tfft_fwd_ts<P, N, 4>(p, v, gen);
   } else {
     dim3 grid((p.m + TS - 1) / TS);
     ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
-    hipLaunchKernelGGL((k_tfft_fwd<P, N, TS>), grid, dim3(kThreads), 0, p.stream, v,
-                       (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m);
+    if constexpr (std::is_same<P, double>::value) {
+      if (gen) {
+        hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, true>), grid, dim3(kThreads), 0, p.stream, v,
+                           (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
+                           p.m, *gen);
+        return hipGetLastError();
+      }
+    }
+    if (gen) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, false>), grid, dim3(kThreads), 0, p.stream, v,
+                       (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m,
+                       GenIn{});
     return hipGetLastError();
   }
 }
 
 template <typename P, int N, int TS>
-hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *nparts) {
+hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *nparts,
+                       const ContractOut *co) {
   if constexpr (!TimeCfg<P, N, TS>::FITS) {
-    return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
+    return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts, co);
   } else {
     dim3 grid((p.m + TS - 1) / TS);
     *nparts = grid.x;
+    if constexpr (std::is_same<P, double>::value) {
+      if (co) {
+        ProfScope ps(p, K_TFFT_INV, (double)p.nvec * sizeof(P) + 16.0 * p.m);
+        hipLaunchKernelGGL((k_tfft_inv<P, N, TS, true>), grid, dim3(kThreads), 0, p.stream,
+                           (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw,
+                           Tabs<P>::twt(p), p.m, dotv, p.d_partials, *co);
+        return hipGetLastError();
+      }
+    }
+    if (co) return hipErrorInvalidValue;
     ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
-    hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(kThreads), 0, p.stream,
+    hipLaunchKernelGGL((k_tfft_inv<P, N, TS, false>), grid, dim3(kThreads), 0, p.stream,
                        (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
-                       p.m, dotv, p.d_partials);
+                       p.m, dotv, p.d_partials, ContractOut{});
     return hipGetLastError();
   }
 }
 
 template <typename P, int N>
-hipError_t run_tfft_fwd(const wc_plan &p, const double *v) {
+hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen) {
   switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
-    case 4: return tfft_fwd_ts<P, N, 4>(p, v);
-    case 8: return tfft_fwd_ts<P, N, 8>(p, v);
-    default: return tfft_fwd_ts<P, N, 16>(p, v);
+    case 4: return tfft_fwd_ts<P, N, 4>(p, v, gen);
+    case 8: return tfft_fwd_ts<P, N, 8>(p, v, gen);
+    default: return tfft_fwd_ts<P, N, 16>(p, v, gen);
   }
 }
 
 template <typename P, int N>
-hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts) {
+hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts,
+                        const ContractOut *co) {
   switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
-    case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
-    case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts);
-    default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts);
+    case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts, co);
+    case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts, co);
+    default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts, co);
   }
 }
 
@@ -751,10 +816,10 @@ hipError_t run_space(const wc_plan &p) {
 
 template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
-                      int *nparts) {
+                      int *nparts, const GenIn *gen, const ContractOut *co) {
   hipError_t e = hipErrorInvalidValue;
   switch (p.n) {
-#define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, v); break;
+#define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, v, gen); break;
     WC_POW2_CASES(CASE_N)
 #undef CASE_N
     default: return hipErrorInvalidValue;
@@ -772,7 +837,7 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   }
   if (e != hipSuccess) return e;
   switch (p.n) {
-#define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts); break;
+#define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts, co); break;
     WC_POW2_CASES(CASE_N)
 #undef CASE_N
     default: return hipErrorInvalidValue;
@@ -791,10 +856,20 @@ hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool do
                            int *nparts) {
   int np = 0;
   const double *dotv = dot ? v : nullptr;
-  hipError_t e = p.opts.precision == WC_MIXED ? pc_apply_t<float>(p, v, w, dotv, &np)
-                                              : pc_apply_t<double>(p, v, w, dotv, &np);
+  hipError_t e = p.opts.precision == WC_MIXED
+                    ? pc_apply_t<float>(p, v, w, dotv, &np, nullptr, nullptr)
+                    : pc_apply_t<double>(p, v, w, dotv, &np, nullptr, nullptr);
   if (nparts) *nparts = np;
   return e;
+}
+
+hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *hat_in,
+                             double *hat_out, double *w) {
+  if (p.opts.precision != WC_FP64) return hipErrorInvalidValue;
+  GenIn gen{hat_in, p.d_lr_s0, p.d_lr_gr, p.d_scal + S_LR_SQN0, 1.0 / p.lr_gn, 1.0 / p.lr_rn};
+  ContractOut co{hat_out, p.d_lr_gr, -p.lr_gn, -p.lr_rn};  // omega = e^{i pi} = -1
+  int np = 0;
+  return pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
 }
 
 int pc_partials_needed(int n, int m, int precision) {

@@ -44,7 +44,8 @@ struct Key {
     const wc_opts &c = opts, &d = o.opts;
     const bool oe = c.method == d.method && c.precision == d.precision && c.tol == d.tol &&
                     c.maxit == d.maxit && c.restart == d.restart && c.flexible == d.flexible &&
-                    c.mg_max_cycles == d.mg_max_cycles && c.mg_tol == d.mg_tol;
+                    c.mg_max_cycles == d.mg_max_cycles && c.mg_tol == d.mg_tol &&
+                    c.graphs == d.graphs && c.lowrank == d.lowrank;
     return pe && oe && aface == o.aface;
   }
 
@@ -53,7 +54,7 @@ struct Key {
     return prob.dims == o.prob.dims && prob.M == o.prob.M && prob.n == o.prob.n &&
            opts.method == o.opts.method && opts.precision == o.opts.precision &&
            opts.restart == o.opts.restart && opts.flexible == o.opts.flexible &&
-           aface.empty() == o.aface.empty();
+           opts.lowrank == o.opts.lowrank && aface.empty() == o.aface.empty();
   }
 };
 

@@ -47,7 +47,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("restart", ctypes.c_int), ("flexible", ctypes.c_int),
                 ("mg_max_cycles", ctypes.c_int), ("mg_tol", ctypes.c_double),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("lowrank", ctypes.c_int)]
 
 
 class _KStat(ctypes.Structure):
@@ -137,7 +137,8 @@ def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face):
     return pr, keep
 
 
-def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs=True):
+def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs=True,
+          lowrank=False):
     op = _Opts()
     _lib.wc_opts_default(ctypes.byref(op))
     op.method = METHODS[method] if isinstance(method, str) else int(method)
@@ -145,14 +146,17 @@ def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_to
     op.tol, op.maxit, op.restart, op.flexible = tol, maxit, restart, int(flexible)
     op.mg_max_cycles, op.mg_tol = mg_max_cycles, mg_tol
     op.graphs = int(bool(graphs))
+    op.lowrank = int(bool(lowrank))
     return op
 
 
 def footprint_bytes(dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                     a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
-                    restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10) -> int:
+                    restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10,
+                    lowrank=False) -> int:
     pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
-    op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol)
+    op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol,
+               lowrank=lowrank)
     return int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
 
@@ -173,10 +177,11 @@ class Plan:
     def __init__(self, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                  a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
                  restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10, stream=None,
-                 graphs=True):
+                 graphs=True, lowrank=False):
         import torch
         pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
-        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs)
+        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
+                   lowrank)
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
@@ -191,6 +196,7 @@ class Plan:
         self.nvec = 2 * n * self.m
         self.method, self.precision = method, precision
         self.restart, self.flexible, self.graphs = restart, flexible, graphs
+        self.lowrank = lowrank
         self.footprint = int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
     def close(self):
@@ -213,7 +219,7 @@ class Plan:
         """Same sizes and method/precision/restart: new problem data, no allocation."""
         pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face)
         op = _opts(self.method, self.precision, tol, maxit, self.restart, self.flexible,
-                   mg_max_cycles, mg_tol, self.graphs)
+                   mg_max_cycles, mg_tol, self.graphs, self.lowrank)
         self._check(_lib.wc_plan_retarget(self._h, ctypes.byref(pr), ctypes.byref(op)),
                     "wc_plan_retarget")
 
@@ -303,10 +309,11 @@ class Server:
     def submit(self, f, g, y0, y, p, u=None, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4,
                zeta=np.pi, s2_remedy=1.0, a_face=None, method="gmres_ps", precision="fp64",
                tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
-               mg_tol=1e-10, graphs=True) -> int:
+               mg_tol=1e-10, graphs=True, lowrank=False) -> int:
         """Queue one solve; the tensors must stay alive and untouched until it is done."""
         pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
-        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs)
+        op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
+                   lowrank)
         t = _u64()
         code = _lib.wc_server_submit(self._h, ctypes.byref(pr), ctypes.byref(op), _ptr(f), _ptr(g),
                                      _ptr(y0), _ptr(y), _ptr(p), _ptr(u), ctypes.byref(t))

@@ -105,3 +105,14 @@ def test_retarget_null_plan(wc):
     lib = ctypes.CDLL(LIB)
     lib.wc_plan_retarget.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.wc_plan_retarget(None, None, None) == wc.WC_E_ARG
+
+
+def test_lowrank_options_and_footprint(wc):
+    full = wc.footprint_bytes(2, 255, 256, method="gmres_ps", restart=30)
+    lr = wc.footprint_bytes(2, 255, 256, method="gmres_ps", restart=30, lowrank=True)
+    nvec = 2 * 256 * 255 * 255 * 8
+    assert 0 < lr < full - 25 * nvec  # the basis is compact: ~4 system vectors instead of ~35
+    assert wc.footprint_bytes(2, 31, 32, method="minres_abs_ps", lowrank=True) == 0
+    assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", precision="mixed", lowrank=True) == 0
+    a = np.ones(2 * 31 * 32)
+    assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", a_face=a, lowrank=True) == 0

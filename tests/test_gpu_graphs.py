@@ -27,6 +27,7 @@ CASES = [
     (1, 127, 64, 0.5, 1e-4, "minres_abs_ps", "fp64", "const", {}),
     (2, 31, 32, 0.5, 1e-2, "minres_pms", "fp64", "const", {}),
     (2, 63, 32, 0.5, 1e-4, "gmres_ps", "fp64", "sin", dict(mg_tol=0.0, mg_max_cycles=2)),
+    (2, 63, 64, 0.5, 1e-4, "gmres_ps", "fp64", "const", dict(lowrank=True, restart=4)),
 ]
 
 
