@@ -60,6 +60,15 @@ template <typename T> __device__ __forceinline__ cx<T> shfl_cx(cx<T> v, int src)
   return cx<T>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round robin by linear id.
+// Tiles adjacent in memory share cache lines, so give each XCD a contiguous run of
+// tiles: tile = first tile of XCD (b mod 8) + b div 8.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X, x = b % X;
+  return x * q + (x < r ? x : r) + b / X;
+}
+
 // ---- small DFTs in registers, natural order in and out ---------------------
 template <typename T, bool INV> __device__ __forceinline__ void dft2(cx<T> *v) {
   cx<T> a = v[0], b = v[1];
@@ -93,10 +102,45 @@ template <typename T, bool INV> __device__ __forceinline__ void dft8(cx<T> *v) {
   }
 }
 
+// 16 points as 4 x 4: index n = 4 n1 + n2, output k = k1 + 4 k2:
+//   A[n2][k1] = DFT4 over n1 of v[4 n1 + n2];  A[n2][k1] *= w16^(n2 k1);
+//   X[k1 + 4 k2] = DFT4 over n2 of A[n2][k1].
+template <typename T, bool INV> __device__ __forceinline__ void dft16(cx<T> *v) {
+  cx<T> a[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+    dft4<T, INV>(a[n2]);
+  }
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;  // cos, sin pi/8
+  const T h = (T)0.70710678118654752440;
+  const T sg = INV ? (T)1 : (T)-1;  // w16 = e^{sg i 2 pi / 16}
+  // w16^1, w16^2, w16^3 and w16^4, w16^6, w16^9
+  const cx<T> w1{c1, sg * s1}, w2{h, sg * h}, w3{s1, sg * c1};
+  a[1][1] = cmul(a[1][1], w1);
+  a[1][2] = cmul(a[1][2], w2);
+  a[1][3] = cmul(a[1][3], w3);
+  a[2][1] = cmul(a[2][1], w2);
+  a[2][2] = INV ? mul_i(a[2][2]) : mul_mi(a[2][2]);                 // w16^4
+  a[2][3] = cmul(a[2][3], cx<T>{-h, sg * h});                        // w16^6
+  a[3][1] = cmul(a[3][1], w3);
+  a[3][2] = cmul(a[3][2], cx<T>{-h, sg * h});                        // w16^6
+  a[3][3] = cmul(a[3][3], cx<T>{-c1, -sg * s1});                     // w16^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4<T, INV>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+  }
+}
+
 template <typename T, int R, bool INV> __device__ __forceinline__ void dftR(cx<T> *v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
-  else dft8<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
 }
 
 // One Stockham stage executed by one wave on B lines of length N stored at
@@ -129,6 +173,15 @@ __device__ __forceinline__ void wstage(cx<T> *buf, const cx<T> *__restrict__ tw,
           w[6] = cmul(w[2], w[4]);
           w[7] = cmul(w[3], w[4]);
         }
+        if constexpr (R == 16) {  // w^4 and w^8 looked up, the rest as short products
+          w[4] = tw[4 * k * STEP];
+          w[8] = tw[8 * k * STEP];
+          w[5] = cmul(w[1], w[4]);
+          w[6] = cmul(w[2], w[4]);
+          w[7] = cmul(w[3], w[4]);
+#pragma unroll
+          for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+        }
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> ww = w[r];
@@ -153,13 +206,16 @@ __device__ __forceinline__ void wstage(cx<T> *buf, const cx<T> *__restrict__ tw,
   wave_sync();
 }
 
-template <typename T, int N, int NS, int B, int S, int PS, bool INV>
+// Radix 16 (R16) when the remaining length allows it and its butterflies still fill the
+// wave (N/16 * B >= 64), else radix 8, 4, 2.
+template <typename T, int N, int NS, int B, int S, int PS, bool INV, bool R16 = false>
 __device__ __forceinline__ void wfft(cx<T> *buf, const cx<T> *__restrict__ tw, int lane) {
   if constexpr (NS < N) {
     constexpr int REM = N / NS;
-    constexpr int R = REM >= 8 ? 8 : REM;
+    constexpr bool use16 = R16 && REM >= 16 && (N / 16) * B >= 64;
+    constexpr int R = use16 ? 16 : (REM >= 8 ? 8 : REM);
     wstage<T, N, R, NS, B, S, PS, INV>(buf, tw, lane);
-    wfft<T, N, NS * R, B, S, PS, INV>(buf, tw, lane);
+    wfft<T, N, NS * R, B, S, PS, INV, R16>(buf, tw, lane);
   }
 }
 
@@ -329,7 +385,8 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
   __shared__ cx<P> buf[C::PN * S];
   __shared__ cx<P> stw[C::TW_LDS ? N : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int s0 = blockIdx.x * TS;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int s0 = tile * TS;
   const double *v1 = v;
   const double *v2 = v + (size_t)N * m;
   // all global loads of the tile are issued before any is consumed
@@ -375,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, false>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  wfft<P, N, 1, TS / 4, S, PS, false, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
   __syncthreads();
   for (int idx = tid; idx < (N / 2) * TS; idx += kThreads) {
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
@@ -405,7 +462,8 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   __shared__ double red[kThreads / 64];
   __shared__ double sums[CONTRACT ? 2 * kThreads : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int s0 = blockIdx.x * TS;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int s0 = tile * TS;
   constexpr int HT = (N / 2) * TS;
   constexpr int LIT = (HT + kThreads - 1) / kThreads;
   cx<P> ra[LIT], rb[LIT];
@@ -433,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  wfft<P, N, 1, TS / 4, S, PS, true, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
   __syncthreads();
   double acc = 0.0, c1 = 0.0, c2 = 0.0;
   double *o1 = out;
@@ -475,7 +533,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   }
   if (dotv) {
     const double r = block_sum(acc, red);
-    if (tid == 0) partials[blockIdx.x] = r;
+    if (tid == 0) partials[tile] = r;
   }
 }
 
@@ -600,8 +658,10 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
   __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
   __shared__ P ssin[C::TAB_LDS ? N1 : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int q = blockIdx.y;
-  const int c0 = blockIdx.x * TX;
+  const int ncx = (N1 - 2 + TX) / TX;  // column tiles per frequency, M = N1 - 1 columns
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int q = t / ncx;
+  const int c0 = (t % ncx) * TX;
   cx<P> *slab0 = W + ((size_t)q * 2 + 0) * M * M;
   cx<P> *slab1 = W + ((size_t)q * 2 + 1) * M * M;
   // tile column 2c+h holds (block row h, x1 column c0+c)
@@ -763,7 +823,7 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c) {
     return cols_tx<P, N1, 4>(p, kind, c);
   } else {
     constexpr int M = N1 - 1;
-    dim3 gc((M + TX - 1) / TX, p.n / 2);
+    dim3 gc(((M + TX - 1) / TX) * (p.n / 2));
     ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
     hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(kThreads), 0, p.stream,
                        (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
