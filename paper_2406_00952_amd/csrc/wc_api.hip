@@ -26,7 +26,7 @@ const char *kernel_name(int id) {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
       "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re", "mg_smooth", "mg_restrict",
-      "mg_lds", "mg_norm", "mg_mix", "lr_setup"};
+      "mg_lds", "mg_norm", "mg_mix", "lr_setup", "contract"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -137,8 +137,9 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.partials = parts + 64;
   s.tables = 1 << 20;
   s.vecs = (size_t)krylov_vectors(pr, op) * s.nvec * sizeof(double);
-  if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g and r
-    s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 2 * (size_t)pr->n) * sizeof(double);
+  if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g, r, rho, partials
+    s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 4 * (size_t)pr->n +
+               (size_t)kContractChunks * 2 * m) * sizeof(double);
   s.mg = 0;
   if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
     const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
@@ -236,7 +237,8 @@ void free_plan(wc_plan *p) {
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
-  dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat);
+  dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat); dfree(p->d_lr_rho);
+  dfree(p->d_lr_part);
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_mg_fn2);
@@ -691,7 +693,7 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   // low-rank GMRES: S_n - B_n = -omega g r^T with omega = e^{i zeta} = -1 (zeta = pi):
   // g = e_1 + (1 - theta) B_n e_1, r_k = q^{n-k} / (theta + omega (1 - theta) q^{n-1}),
   // q = -(1 - theta)/theta (k = 1..n; the wrap-around corners of S^(1), S^(2))
-  std::vector<double> gr;
+  std::vector<double> gr, rho;
   p->lr_ok = false;
   if (p->opts.lowrank) {
     const double th = p->theta, q = -(1.0 - th) / th;
@@ -714,6 +716,23 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
     p->lr_gn = std::sqrt(g2);
     p->lr_rn = std::sqrt(r2);
     if (e == hipSuccess) e = upload(p->stream, &p->d_lr_gr, gr);
+    // contraction weights on the kept frequencies l = q + 1:
+    //   rho_r[q] = sum_k r_k e^{-i zeta k/n} e^{2 pi i k l/n}, rho_g likewise with g
+    rho.assign(2 * (size_t)n, 0.0);
+    for (int q = 0; q < n / 2; ++q) {
+      std::complex<double> ar = 0.0, ag = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const std::complex<double> ph =
+            std::polar(1.0, -p->zeta * k / n + 2.0 * M_PI * k * (q + 1) / n);
+        ar += gr[n + k] * ph;
+        ag += gr[k] * ph;
+      }
+      rho[2 * q] = ar.real();
+      rho[2 * q + 1] = ar.imag();
+      rho[n + 2 * q] = ag.real();
+      rho[n + 2 * q + 1] = ag.imag();
+    }
+    if (e == hipSuccess) e = upload(p->stream, &p->d_lr_rho, rho);
   }
   std::vector<double> af;
   if (e == hipSuccess && prob->a_face_host) {
@@ -867,6 +886,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     p->lr_len = 1 + 2 * (size_t)p->m;
     alloc((void **)&p->d_lr_s0, 2 * (size_t)p->m * sizeof(double));
     alloc((void **)&p->d_lr_hat, (size_t)(opts->restart + 2) * p->lr_len * sizeof(double));
+    alloc((void **)&p->d_lr_part, (size_t)kContractChunks * 2 * p->m * sizeof(double));
   }
   if (!oom && hipHostMalloc((void **)&p->h_scal, S_COUNT * sizeof(double), 0) != hipSuccess)
     oom = true;

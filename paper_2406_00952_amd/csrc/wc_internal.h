@@ -68,7 +68,7 @@ enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
   K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_MG_SMOOTH, K_MG_RESTRICT,
-  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_COUNT
+  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_CONTRACT, K_COUNT
 };
 const char *kernel_name(int id);
 
@@ -152,6 +152,8 @@ struct wc_plan {
   double *d_lr_gr = nullptr;        // 2n: g then r
   double *d_lr_s0 = nullptr;        // 2m
   double *d_lr_hat = nullptr;       // (restart + 2) compact vectors of lr_len
+  double *d_lr_rho = nullptr;       // n complex: contraction weights per kept frequency
+  double *d_lr_part = nullptr;      // kContractChunks x 2m
 
   mutable wc::Profiler prof;
   // captured Krylov iterations: GMRES step j in slot j, the two MINRES buffer
@@ -206,11 +208,17 @@ struct GenIn {
 // Contracted output (low-rank GMRES): instead of z, the compact coordinates of
 // (Ahat - P_S) z = omega [g (x) sum_k r_k z1_k; r (x) sum_k g_k z2_k]:
 //   hat[0] = 0, hat[1+s] = |g| omega sum_k r_k z1[k][s], hat[1+m+s] = |r| omega sum_k g_k z2[k][s].
+// The time sums are taken on the spectrum, before the inverse time transform: for real z
+// with the half spectrum Z_q (frequency l = q + 1; its partner 1 - l carries conj(Z_q)),
+//   sum_k r_k z_k = sum_q 2 Re(rho_q Z_q),  rho_q = sum_k r_k conj(omega^{k/n}) e^{2 pi i k (q+1)/n}.
 struct ContractOut {
   double *hat;
-  const double *gr;  // 2n: g_k then r_k
   double gn_omega, rn_omega;
+  const double *rho;   // n complex: rho_r[q] then rho_g[q], q < n/2 (frequency l = q + 1)
+  double *part;        // kContractChunks x 2m partial sums
 };
+// frequency chunks of the contraction kernel (deterministic two-stage sum)
+constexpr int kContractChunks = 8;
 
 
 // ---- launchers (wc_ops.hip) -------------------------------------------------

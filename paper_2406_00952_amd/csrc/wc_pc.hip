@@ -447,20 +447,18 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
 }
 
 // ---- step 3b: inverse time transform, real output, optional fused <w, dotv> ----
-template <typename P, int N, int TS_, bool CONTRACT>
+template <typename P, int N, int TS_>
 __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
                                                        double *__restrict__ out,
                                                        const cx<double> *__restrict__ dtw,
                                                        const cx<P> *__restrict__ twg, int m,
                                                        const double *__restrict__ dotv,
-                                                       double *__restrict__ partials,
-                                                       ContractOut co) {
+                                                       double *__restrict__ partials) {
   using C = TimeCfg<P, N, TS_>;
   constexpr int TS = TS_, S = C::S, PS = C::PS;
   __shared__ cx<P> buf[C::PN * S];
   __shared__ cx<P> stw[C::TW_LDS ? N : 1];
   __shared__ double red[kThreads / 64];
-  __shared__ double sums[CONTRACT ? 2 * kThreads : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int s0 = tile * TS;
@@ -493,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   __syncthreads();
   wfft<P, N, 1, TS / 4, S, PS, true, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
   __syncthreads();
-  double acc = 0.0, c1 = 0.0, c2 = 0.0;
+  double acc = 0.0;
   double *o1 = out;
   double *o2 = out + (size_t)N * m;
   for (int idx = tid; idx < N * TS; idx += kThreads) {
@@ -504,32 +502,10 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
     const double zx = (double)z.x, zy = (double)z.y;
     const double r1 = zx * d.x + zy * d.y;
     const double r2 = zy * d.x - zx * d.y;
-    if constexpr (CONTRACT) {  // kThreads is a multiple of TS: this thread's s is fixed
-      c1 += co.gr[N + k] * r1;
-      c2 += co.gr[k] * r2;
-    } else {
-      const size_t g = (size_t)k * m + gs;
-      o1[g] = r1;
-      o2[g] = r2;
-      if (dotv) acc += r1 * dotv[g] + r2 * dotv[(size_t)N * m + g];
-    }
-  }
-  if constexpr (CONTRACT) {
-    static_assert(kThreads % TS == 0, "a thread's column must not change");
-    sums[tid] = c1;
-    sums[kThreads + tid] = c2;
-    __syncthreads();
-    if (tid < TS && s0 + tid < m) {
-      double a1 = 0.0, a2 = 0.0;
-      for (int t = tid; t < kThreads; t += TS) {
-        a1 += sums[t];
-        a2 += sums[kThreads + t];
-      }
-      co.hat[1 + s0 + tid] = co.gn_omega * a1;
-      co.hat[1 + m + s0 + tid] = co.rn_omega * a2;
-    }
-    if (blockIdx.x == 0 && tid == 0) co.hat[0] = 0.0;
-    return;
+    const size_t g = (size_t)k * m + gs;
+    o1[g] = r1;
+    o2[g] = r2;
+    if (dotv) acc += r1 * dotv[g] + r2 * dotv[(size_t)N * m + g];
   }
   if (dotv) {
     const double r = block_sum(acc, red);
@@ -715,6 +691,43 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
   }
 }
 
+
+// ---- low-rank GMRES: time contraction on the spectrum (replaces the inverse FFT) ----
+// part[c][s] = sum over the frequencies q of chunk c of 2 Re(rho_r[q] A_q[s]), and
+// part[c][m + s] likewise with rho_g and B_q[s] (A = block row 1, B = block row 2).
+__global__ __launch_bounds__(kThreads) void k_contract_freq(const cx<double> *__restrict__ W,
+                                                            ContractOut co, int m, int nq) {
+  const int s = blockIdx.x * kThreads + threadIdx.x, c = blockIdx.y;
+  if (s >= m) return;
+  const int per = (nq + kContractChunks - 1) / kContractChunks;
+  const int q0 = c * per, q1 = q0 + per < nq ? q0 + per : nq;
+  const cx<double> *rr = reinterpret_cast<const cx<double> *>(co.rho);
+  const cx<double> *rg = rr + nq;
+  double a1 = 0.0, a2 = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    const cx<double> A = W[((size_t)q * 2 + 0) * m + s], B = W[((size_t)q * 2 + 1) * m + s];
+    const cx<double> u = rr[q], w = rg[q];
+    a1 += u.x * A.x - u.y * A.y;
+    a2 += w.x * B.x - w.y * B.y;
+  }
+  co.part[(size_t)c * 2 * m + s] = 2.0 * a1;
+  co.part[(size_t)c * 2 * m + m + s] = 2.0 * a2;
+}
+
+__global__ __launch_bounds__(kThreads) void k_contract_final(ContractOut co, int m) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) co.hat[0] = 0.0;
+  if (s >= m) return;
+  double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < kContractChunks; ++c) {
+    a1 += co.part[(size_t)c * 2 * m + s];
+    a2 += co.part[(size_t)c * 2 * m + m + s];
+  }
+  co.hat[1 + s] = co.gn_omega * a1;
+  co.hat[1 + m + s] = co.rn_omega * a2;
+}
+
 // ---- host dispatch -------------------------------------------------------------
 template <typename P> struct Tabs;
 template <> struct Tabs<double> {
@@ -773,27 +786,16 @@ hipError_t tfft_fwd_ts(const wc_plan &p, const double *v, const GenIn *gen) {
 }
 
 template <typename P, int N, int TS>
-hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *nparts,
-                       const ContractOut *co) {
+hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *nparts) {
   if constexpr (!TimeCfg<P, N, TS>::FITS) {
-    return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts, co);
+    return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
   } else {
     dim3 grid((p.m + TS - 1) / TS);
     *nparts = grid.x;
-    if constexpr (std::is_same<P, double>::value) {
-      if (co) {
-        ProfScope ps(p, K_TFFT_INV, (double)p.nvec * sizeof(P) + 16.0 * p.m);
-        hipLaunchKernelGGL((k_tfft_inv<P, N, TS, true>), grid, dim3(kThreads), 0, p.stream,
-                           (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw,
-                           Tabs<P>::twt(p), p.m, dotv, p.d_partials, *co);
-        return hipGetLastError();
-      }
-    }
-    if (co) return hipErrorInvalidValue;
     ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
-    hipLaunchKernelGGL((k_tfft_inv<P, N, TS, false>), grid, dim3(kThreads), 0, p.stream,
+    hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(kThreads), 0, p.stream,
                        (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
-                       p.m, dotv, p.d_partials, ContractOut{});
+                       p.m, dotv, p.d_partials);
     return hipGetLastError();
   }
 }
@@ -808,12 +810,11 @@ hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen) {
 }
 
 template <typename P, int N>
-hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts,
-                        const ContractOut *co) {
+hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts) {
   switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
-    case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts, co);
-    case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts, co);
-    default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts, co);
+    case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
+    case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts);
+    default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts);
   }
 }
 
@@ -896,8 +897,26 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
     }
   }
   if (e != hipSuccess) return e;
+  if constexpr (std::is_same<P, double>::value) {
+    if (co) {  // low-rank GMRES: contract over time on the spectrum
+      const int nq = p.n / 2;
+      {
+        ProfScope ps(p, K_CONTRACT, (double)p.n * p.m * sizeof(cx<double>) +
+                                        16.0 * kContractChunks * p.m);
+        hipLaunchKernelGGL(k_contract_freq, dim3((p.m + kThreads - 1) / kThreads, kContractChunks),
+                           dim3(kThreads), 0, p.stream, (const cx<double> *)p.d_specA, *co, p.m,
+                           nq);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
+      hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                         p.stream, *co, p.m);
+      *nparts = 0;
+      return hipGetLastError();
+    }
+  }
   switch (p.n) {
-#define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts, co); break;
+#define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts); break;
     WC_POW2_CASES(CASE_N)
 #undef CASE_N
     default: return hipErrorInvalidValue;
@@ -927,7 +946,7 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
                              double *hat_out, double *w) {
   if (p.opts.precision != WC_FP64) return hipErrorInvalidValue;
   GenIn gen{hat_in, p.d_lr_s0, p.d_lr_gr, p.d_scal + S_LR_SQN0, 1.0 / p.lr_gn, 1.0 / p.lr_rn};
-  ContractOut co{hat_out, p.d_lr_gr, -p.lr_gn, -p.lr_rn};  // omega = e^{i pi} = -1
+  ContractOut co{hat_out, -p.lr_gn, -p.lr_rn, p.d_lr_rho, p.d_lr_part};  // omega = e^{i pi} = -1
   int np = 0;
   return pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
 }
