@@ -385,7 +385,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   const size_t nv = p->nvec;
   const size_t len = lr ? p->lr_len : nv;  // basis vector length (and stride)
   double *V = lr ? p->d_lr_hat : p->vec(0);
-  double *R0 = lr ? p->vec(0) : nullptr;    // full residual of the cycle (low-rank form)
+  double *const R0buf = lr ? p->vec(0) : nullptr;  // full residual of later cycles (low-rank)
   double *Zb = lr ? nullptr : p->vec(k + 1);
   double *T = lr ? p->vec(1) : p->vec(k + 1 + (flex ? k : 1));
   const double tol = p->opts.tol;
@@ -393,7 +393,8 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   WC_TRY(launch_dot(*p, b, b, S_DOT));
   WC_TRY(sync_read(p, S_DOT, 1));
   const double bnorm = std::sqrt(p->h_scal[S_DOT]);
-  WC_TRY(launch_fill(*p, x, 0.0, nv));
+  // x0 = 0 (the low-rank form writes its first update straight into x instead)
+  if (!lr || bnorm == 0.0 || !std::isfinite(bnorm)) WC_TRY(launch_fill(*p, x, 0.0, nv));
   if (!std::isfinite(bnorm)) return WC_E_NONFINITE;
   if (bnorm == 0.0) {
     if (info) { info->status = WC_OK; info->relres = 0; info->relres_est = 0; }
@@ -405,22 +406,19 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
   wc_status st = WC_E_MAXIT;
   double relres = 1.0, relres_est = 1.0;
   for (;;) {
-    double *Rf = lr ? R0 : V;  // the cycle's full residual
+    // the cycle's full residual r0 = b - Ahat x (x = 0 in the first cycle: b itself)
+    const double *R0 = lr ? (first ? b : R0buf) : nullptr;
+    double *Rf = lr ? R0buf : V;
     if (first) {
-      WC_TRY(launch_lincomb3(*p, Rf, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
+      if (!lr) WC_TRY(launch_lincomb3(*p, Rf, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
     } else {
-      WC_TRY(launch_matvec(*p, x, T, p->d_partials, nullptr));
-      WC_TRY(launch_lincomb3(*p, Rf, b, T, nullptr, -1, 1.0, -1.0, 0.0));
+      WC_TRY(launch_matvec(*p, x, Rf, p->d_partials, nullptr, b, true));
     }
     double beta;
     if (lr) {
       WC_TRY(launch_dot(*p, R0, R0, S_DOT));
-      WC_TRY(launch_lr_setup(*p, R0, V));
-      WC_TRY(launch_dot(*p, V, V, S_NU2, len));
       WC_TRY(sync_read(p, S_DOT, 1));
-      WC_TRY(sync_read(p, S_NU2, 1));
       relres = std::sqrt(p->h_scal[S_DOT]) / bnorm;
-      beta = std::sqrt(p->h_scal[S_NU2]);
     } else {
       WC_TRY(launch_dot(*p, V, V, S_NU2));
       WC_TRY(sync_read(p, S_NU2, 1));
@@ -430,6 +428,12 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (!std::isfinite(relres)) { st = WC_E_NONFINITE; break; }
     if (relres <= tol) { st = WC_OK; break; }
     if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
+    if (lr) {  // compact coordinates of r0 (its range part and the rest)
+      WC_TRY(launch_lr_setup(*p, R0, V));
+      WC_TRY(launch_dot(*p, V, V, S_NU2, len));
+      WC_TRY(sync_read(p, S_NU2, 1));
+      beta = std::sqrt(p->h_scal[S_NU2]);
+    }
     nu[0] = beta;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -468,7 +472,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
                               (S_D2 + j + 1 - S_WN2) * sizeof(double), hipMemcpyDeviceToHost,
                               p->stream);
       };
-      WC_TRY(run_captured(p, j, nullptr, body));
+      WC_TRY(run_captured(p, first ? j : kMaxRestart + j, R0, body));
       WC_TRY(hipStreamSynchronize(p->stream));
       const bool two = p->h_scal[S_REORTH] != 0.0;
       reorth += two ? 1 : 0;
@@ -513,8 +517,12 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       double *U = V + (size_t)(k + 1) * len;
       WC_TRY(launch_fill(*p, U, 0.0, len));
       WC_TRY(launch_multiaxpy(*p, U, V, jd, S_Y, 1.0, false, nullptr, nullptr, len));
-      WC_TRY(launch_pc_lowrank(*p, R0, U, nullptr, T));
-      WC_TRY(launch_lincomb3(*p, x, x, T, nullptr, -1, 1.0, 1.0, 0.0));
+      if (first) {  // x is still zero
+        WC_TRY(launch_pc_lowrank(*p, R0, U, nullptr, x));
+      } else {
+        WC_TRY(launch_pc_lowrank(*p, R0, U, nullptr, T));
+        WC_TRY(launch_lincomb3(*p, x, x, T, nullptr, -1, 1.0, 1.0, 0.0));
+      }
     } else if (flex) {
       WC_TRY(launch_multiaxpy(*p, x, Zb, jd, S_Y, 1.0, false, nullptr, nullptr));
     } else {

@@ -156,9 +156,10 @@ struct wc_plan {
   double *d_lr_part = nullptr;      // kContractChunks x 2m
 
   mutable wc::Profiler prof;
-  // captured Krylov iterations: GMRES step j in slot j, the two MINRES buffer
-  // arrangements in the last two; key = the caller pointer the work also depends on
-  static constexpr int kGraphSlots = wc::kMaxRestart + 2;
+  // captured Krylov iterations: GMRES step j in slot j (first restart cycle) or
+  // kMaxRestart + j (later cycles), the two MINRES buffer arrangements in the last two;
+  // key = the caller pointer the work also depends on
+  static constexpr int kGraphSlots = 2 * wc::kMaxRestart + 2;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[kGraphSlots] = {};
   const void *gkey[kGraphSlots] = {};
@@ -226,9 +227,10 @@ constexpr int kContractChunks = 8;
 hipError_t mg_space_apply(const wc_plan &p);
 // LDS bytes of a cycle over the pyramid from an M-point level down to M = 1
 size_t mg_lds_bytes(int dims, int M, int precision);
-// y = Ahat x (GMRES layout) or A x (MINRES layout); with sub, y = (.) x - sub.
+// y = Ahat x (GMRES layout) or A x (MINRES layout); with sub, y = (.) x - sub, or
+// sub - (.) x with negate (a residual in one pass).
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
-                         int *nblocks_out, const double *sub = nullptr);
+                         int *nblocks_out, const double *sub = nullptr, bool negate = false);
 hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
                       double *b);
 hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u);

@@ -83,13 +83,14 @@ struct MvArgs {
   int n, M, dims, m, sym;
   double theta, tau, alpha, inv_h2;
   const double *aface;
+  double ssign;  // with sub: y = ssign * (A x - sub)
 };
 
 // blockIdx.y == 0: T x1 - alpha x2 (forward in time); 1: T^T x2 + alpha x1 (backward).
 // Output block rows: A (sym) = [alpha x1 + T^T x2; T x1 - alpha x2],
 //                    A_hat   = [T x1 - alpha x2; alpha x1 + T^T x2].
 // partials[dir*gridDim.x + block] = this block's share of <y, x>.
-// With sub != nullptr the kernel writes y - sub (same layout as y) and the
+// With sub != nullptr the kernel writes ssign * (y - sub) (same layout as y) and the
 // partial sums are not meaningful.
 __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ x,
                                                      double *__restrict__ y,
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
           out = (uu - zprev) + a.tau * kx[u] + a.alpha * xok[u];
           zprev = uu;
         }
-        yo[(size_t)k * a.m + s] = out - sk[u];
+        yo[(size_t)k * a.m + s] = so ? a.ssign * (out - sk[u]) : out;
         acc += out * (a.sym ? xok[u] : xc[u]);
       }
     }
@@ -549,9 +550,9 @@ int red_blocks(size_t n) {
 }
 
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
-                         int *nblocks_out, const double *sub) {
+                         int *nblocks_out, const double *sub, bool negate) {
   MvArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
-           p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface};
+           p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface, negate ? -1.0 : 1.0};
   dim3 grid((p.m + kThreads - 1) / kThreads, 2);
   ProfScope ps(p, K_MATVEC, (sub ? 24.0 : 16.0) * p.nvec);
   hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, sub, a, partials);

@@ -558,6 +558,78 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
   }
 }
 
+
+// ---- 2D low-rank GMRES: inverse x1 sine transform fused with the time contraction ----
+// Each wave owns (frequency chunk c, block row h, row x2); it transforms the B lines of
+// consecutive frequencies at a time and accumulates sum_q 2 Re(rho_h[q] Y_q[x1]) for its
+// x1 positions, so the spectrum is not written back: part[c][h m + x2 M + x1].
+template <int N1>
+__global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double> *__restrict__ W,
+                                                                int nq, ContractOut co,
+                                                                const cx<double> *__restrict__ twg,
+                                                                const double *__restrict__ sing) {
+  using R = RowCfg<double, N1>;
+  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  constexpr int XPL = (M + 63) / 64;  // x1 positions per lane
+  __shared__ cx<double> lds[R::WPB][R::PN * S];
+  __shared__ cx<double> stw[N1];
+  __shared__ double ssin[N1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    stw[i] = twg[i];
+    ssin[i] = sing[i];
+  }
+  __syncthreads();
+  cx<double> *buf = lds[wv];
+  const size_t m = (size_t)M * M;
+  const int per = (nq + kContractChunks - 1) / kContractChunks;
+  const int ntasks = kContractChunks * 2 * M;
+  const cx<double> *rho = reinterpret_cast<const cx<double> *>(co.rho);
+  for (int task = blockIdx.x * R::WPB + wv; task < ntasks; task += gridDim.x * R::WPB) {
+    const int c = task / (2 * M), rem = task % (2 * M), h = rem / M, x2 = rem % M;
+    const int q0 = c * per, q1 = q0 + per < nq ? q0 + per : nq;
+    const cx<double> *rh = rho + (size_t)h * nq;
+    double acc[XPL];
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) acc[j] = 0.0;
+    for (int qb = q0; qb < q1; qb += B) {
+      constexpr int LIT = (B * M + 63) / 64;
+      cx<double> r[LIT];
+#pragma unroll
+      for (int it = 0; it < LIT; ++it) {
+        const int idx = lane + 64 * it, b = idx / M, x = idx % M;
+        r[it] = cx<double>{0.0, 0.0};
+        if (idx < B * M && qb + b < q1)
+          r[it] = W[((size_t)(qb + b) * 2 + h) * m + (size_t)x2 * M + x];
+      }
+#pragma unroll
+      for (int it = 0; it < LIT; ++it) {
+        const int idx = lane + 64 * it;
+        if (idx < B * M) buf[pk<PS>(idx % M + 1) * S + idx / M] = r[it];
+      }
+      wave_sync();
+      wdst<double, N1, B, S, PS>(buf, stw, ssin, lane);
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const int x = lane + 64 * j;
+        if (x >= M) continue;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          if (qb + b >= q1) continue;
+          const cx<double> y = buf[pk<PS>(x + 1) * S + b], u = rh[qb + b];
+          acc[j] += 2.0 * (u.x * y.x - u.y * y.y);
+        }
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) {
+      const int x = lane + 64 * j;
+      if (x < M) co.part[(size_t)c * 2 * m + (size_t)h * m + (size_t)x2 * M + x] = acc[j];
+    }
+  }
+}
+
 // ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
 // W layout [q][half][x]; every wave owns UNITS frequencies (2*UNITS lines) at a time.
 template <typename P, int N1>
@@ -834,7 +906,7 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c) {
 }
 
 template <typename P, int N1>
-hipError_t run_space(const wc_plan &p) {
+hipError_t run_space(const wc_plan &p, const ContractOut *co) {
   using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
@@ -867,6 +939,16 @@ hipError_t run_space(const wc_plan &p) {
     default: e = cols_tx<P, N1, 8>(p, kind, c); break;
   }
   if (e != hipSuccess) return e;
+  if constexpr (std::is_same<P, double>::value) {
+    if (co) {  // low-rank GMRES: the last pass contracts over time instead of writing back
+      const int ntasks = kContractChunks * 2 * M;
+      dim3 gt(row_grid(ntasks, R::WPB));
+      ProfScope ps(p, K_DST_X1_INV, bytes / 2 + 16.0 * kContractChunks * p.m);
+      hipLaunchKernelGGL((k_dst_rows_contract<N1>), gt, dim3(64 * R::WPB), 0, p.stream,
+                         (const cx<double> *)W, p.n / 2, *co, Tabs<P>::tws(p), Tabs<P>::sin(p));
+      return hipGetLastError();
+    }
+  }
   ProfScope ps(p, K_DST_X1_INV, bytes);
   hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
                      W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
@@ -890,7 +972,7 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
     e = mg_space_apply(p);
   } else {
     switch (p.N1) {
-#define CASE_S(NN) case NN: e = run_space<P, NN>(p); break;
+#define CASE_S(NN) case NN: e = run_space<P, NN>(p, co); break;
       WC_POW2_CASES(CASE_S)
 #undef CASE_S
       default: return hipErrorInvalidValue;
@@ -900,7 +982,7 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   if constexpr (std::is_same<P, double>::value) {
     if (co) {  // low-rank GMRES: contract over time on the spectrum
       const int nq = p.n / 2;
-      {
+      if (p.dims == 1) {  // 2D: the inverse x1 pass already contracted
         ProfScope ps(p, K_CONTRACT, (double)p.n * p.m * sizeof(cx<double>) +
                                         16.0 * kContractChunks * p.m);
         hipLaunchKernelGGL(k_contract_freq, dim3((p.m + kThreads - 1) / kThreads, kContractChunks),
