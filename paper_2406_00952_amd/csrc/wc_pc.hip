@@ -225,6 +225,9 @@ __device__ __forceinline__ void wfft(cx<T> *buf, const cx<T> *__restrict__ tw, i
 //   C_k = (F_k + F_{N1-k})/2,  S_k = i (F_k - F_{N1-k})/2
 //   Y_{2k} = S_k,  Y_{2k+1} = C_0/2 + C_1 + ... + C_k
 template <typename T, int N1, int B, int S, int PS>
+__device__ __forceinline__ void wdst_core(cx<T> *buf, const cx<T> *__restrict__ tw, int lane);
+
+template <typename T, int N1, int B, int S, int PS>
 __device__ __forceinline__ void wdst(cx<T> *buf, const cx<T> *__restrict__ tw,
                                      const T *__restrict__ sintab, int lane) {
   constexpr int H = N1 / 2;
@@ -241,6 +244,14 @@ __device__ __forceinline__ void wdst(cx<T> *buf, const cx<T> *__restrict__ tw,
     if (i == 1) buf[b] = cx<T>{(T)0, (T)0};
   }
   wave_sync();
+  wdst_core<T, N1, B, S, PS>(buf, tw, lane);
+}
+
+// FFT and post-processing of wdst, on the pre-processed sequence already in buf.
+template <typename T, int N1, int B, int S, int PS>
+__device__ __forceinline__ void wdst_core(cx<T> *buf, const cx<T> *__restrict__ tw, int lane) {
+  constexpr int H = N1 / 2;
+  constexpr int ITEMS = H * B;
   wfft<T, N1, 1, B, S, PS, false>(buf, tw, lane);
   // post-processing: every lane owns CH consecutive k of one line; the running sum is a
   // sequential scan inside the chunk plus a shuffle scan of the chunk totals.
@@ -283,6 +294,85 @@ __device__ __forceinline__ void wdst(cx<T> *buf, const cx<T> *__restrict__ tw,
     }
   }
   wave_sync();
+}
+
+// The DST of B lines as above, for callers that write the pre-processed sequence
+// (y_i, slot 0 = 0) themselves and take the outputs from registers: lane (b, g) gets
+// k = k0 + c, c < CH, with odd[c] = Y_{2k+1} and even[c] = Y_{2k} (k >= 1); valid is false
+// for lanes without a line.  buf may be rewritten once the wave has synchronised.
+template <typename T, int N1, int B> struct DstLanes {
+  static constexpr int H = N1 / 2, ITEMS = H * B;
+  static constexpr int CH = ITEMS >= 64 ? ITEMS / 64 : 1;
+  static constexpr int G = H / CH;  // lanes per line
+};
+
+template <typename T, int N1, int B, int S, int PS>
+__device__ __forceinline__ void wdst_regs(cx<T> *buf, const cx<T> *__restrict__ tw, int lane,
+                                          cx<T> *odd, cx<T> *even, int &b, int &k0,
+                                          bool &valid) {
+  using L = DstLanes<T, N1, B>;
+  constexpr int CH = L::CH, G = L::G;
+  wfft<T, N1, 1, B, S, PS, false>(buf, tw, lane);
+  b = lane / G;
+  const int g = lane % G;
+  k0 = g * CH;
+  valid = b < B;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    odd[c] = cx<T>{(T)0, (T)0};
+    even[c] = cx<T>{(T)0, (T)0};
+    if (valid) {
+      const int k = k0 + c;
+      const cx<T> Fk = buf[pk<PS>(k) * S + b];
+      const cx<T> Fm = buf[pk<PS>((N1 - k) & (N1 - 1)) * S + b];
+      cx<T> C = cscale(cadd(Fk, Fm), (T)0.5);
+      if (k == 0) C = cscale(C, (T)0.5);
+      odd[c] = C;
+      even[c] = mul_i(cscale(csub(Fk, Fm), (T)0.5));
+    }
+  }
+#pragma unroll
+  for (int c = 1; c < CH; ++c) odd[c] = cadd(odd[c], odd[c - 1]);
+  const cx<T> tot = odd[CH - 1];
+  cx<T> inc = tot;
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const cx<T> y = shfl_up_cx(inc, off);
+    if (g >= off) inc = cadd(inc, y);
+  }
+  const cx<T> excl = csub(inc, tot);
+#pragma unroll
+  for (int c = 0; c < CH; ++c) odd[c] = cadd(odd[c], excl);
+}
+
+// Pre-processing straight from global memory: line b's x_i (i = 1..N1-1) is src(b, i-1);
+// writes y_i = sin(pi i/N1)(x_i + x_{N1-i}) + (x_i - x_{N1-i})/2 and y_0 = 0 into buf.
+template <typename T, int N1, int B, int S, int PS, typename Src>
+__device__ __forceinline__ void dst_pre_global(cx<T> *buf, const T *__restrict__ sintab,
+                                               int lane, Src src) {
+  constexpr int H = N1 / 2, IT = (H * B + 63) / 64;
+  cx<T> xa[IT], xb[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {  // every load is issued before any is consumed
+    const int idx = lane + 64 * it, i = 1 + idx % H, b = idx / H;
+    xa[it] = cx<T>{(T)0, (T)0};
+    xb[it] = cx<T>{(T)0, (T)0};
+    if ((H * B) % 64 == 0 || idx < H * B) {
+      xa[it] = src(b, i - 1);
+      xb[it] = src(b, N1 - i - 1);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int idx = lane + 64 * it, i = 1 + idx % H, b = idx / H;
+    if ((H * B) % 64 != 0 && idx >= H * B) continue;
+    const T s = sintab[i];
+    const cx<T> sum = cadd(xa[it], xb[it]);
+    const cx<T> dif = cscale(csub(xa[it], xb[it]), (T)0.5);
+    buf[pk<PS>(i) * S + b] = cadd(cscale(sum, s), dif);
+    if (i != H) buf[pk<PS>(N1 - i) * S + b] = csub(cscale(sum, s), dif);
+    if (i == 1) buf[b] = cx<T>{(T)0, (T)0};
+  }
 }
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -534,23 +624,12 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
   const int ngroups = (nlines + B - 1) / B;
   for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
     const int l0 = grp * B;
-    constexpr int LIT = (B * M + 63) / 64;
-    cx<P> r[LIT];
-#pragma unroll
-    for (int it = 0; it < LIT; ++it) {
-      const int idx = lane + 64 * it;
-      const int b = idx / M, x = idx % M;
-      r[it] = cx<P>{(P)0, (P)0};
-      if (idx < B * M && l0 + b < nlines) r[it] = W[(size_t)(l0 + b) * M + x];
-    }
-#pragma unroll
-    for (int it = 0; it < LIT; ++it) {
-      const int idx = lane + 64 * it;
-      if (idx < B * M) buf[pk<PS>(idx % M + 1) * S + idx / M] = r[it];
-    }
+    dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
+      return l0 + b < nlines ? W[(size_t)(l0 + b) * M + x] : cx<P>{(P)0, (P)0};
+    });
     wave_sync();
-    wdst<P, N1, B, S, PS>(buf, stw, ssin, lane);
-    for (int idx = lane; idx < B * M; idx += 64) {
+    wdst_core<P, N1, B, S, PS>(buf, stw, lane);
+    for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
       const int b = idx / M, x = idx % M;
       if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
     }
@@ -558,11 +637,11 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
   }
 }
 
-
 // ---- 2D low-rank GMRES: inverse x1 sine transform fused with the time contraction ----
 // Each wave owns (frequency chunk c, block row h, row x2); it transforms the B lines of
-// consecutive frequencies at a time and accumulates sum_q 2 Re(rho_h[q] Y_q[x1]) for its
-// x1 positions, so the spectrum is not written back: part[c][h m + x2 M + x1].
+// consecutive frequencies at a time and accumulates sum_q 2 Re(rho_h[q] Y_q[x1]) in the
+// registers that hold its outputs, so the spectrum is not written back:
+// part[c][h m + x2 M + x1].
 template <int N1>
 __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double> *__restrict__ W,
                                                                 int nq, ContractOut co,
@@ -570,7 +649,6 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
                                                                 const double *__restrict__ sing) {
   using R = RowCfg<double, N1>;
   constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
-  constexpr int XPL = (M + 63) / 64;  // x1 positions per lane
   __shared__ cx<double> lds[R::WPB][R::PN * S];
   __shared__ cx<double> stw[N1];
   __shared__ double ssin[N1];
@@ -585,47 +663,58 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
   const int per = (nq + kContractChunks - 1) / kContractChunks;
   const int ntasks = kContractChunks * 2 * M;
   const cx<double> *rho = reinterpret_cast<const cx<double> *>(co.rho);
+  using L = DstLanes<double, N1, B>;
   for (int task = blockIdx.x * R::WPB + wv; task < ntasks; task += gridDim.x * R::WPB) {
     const int c = task / (2 * M), rem = task % (2 * M), h = rem / M, x2 = rem % M;
     const int q0 = c * per, q1 = q0 + per < nq ? q0 + per : nq;
     const cx<double> *rh = rho + (size_t)h * nq;
-    double acc[XPL];
+    // this lane's outputs: Y_{2k+1} at x = 2k and Y_{2k} at x = 2k - 1, k = k0 + cc
+    double aodd[L::CH], aeven[L::CH];
 #pragma unroll
-    for (int j = 0; j < XPL; ++j) acc[j] = 0.0;
+    for (int cc = 0; cc < L::CH; ++cc) aodd[cc] = aeven[cc] = 0.0;
+    int b = 0, k0 = 0;
+    bool valid = false;
     for (int qb = q0; qb < q1; qb += B) {
-      constexpr int LIT = (B * M + 63) / 64;
-      cx<double> r[LIT];
-#pragma unroll
-      for (int it = 0; it < LIT; ++it) {
-        const int idx = lane + 64 * it, b = idx / M, x = idx % M;
-        r[it] = cx<double>{0.0, 0.0};
-        if (idx < B * M && qb + b < q1)
-          r[it] = W[((size_t)(qb + b) * 2 + h) * m + (size_t)x2 * M + x];
-      }
-#pragma unroll
-      for (int it = 0; it < LIT; ++it) {
-        const int idx = lane + 64 * it;
-        if (idx < B * M) buf[pk<PS>(idx % M + 1) * S + idx / M] = r[it];
-      }
+      dst_pre_global<double, N1, B, S, PS>(buf, ssin, lane, [&](int bb, int x) {
+        return qb + bb < q1 ? W[((size_t)(qb + bb) * 2 + h) * m + (size_t)x2 * M + x]
+                            : cx<double>{0.0, 0.0};
+      });
       wave_sync();
-      wdst<double, N1, B, S, PS>(buf, stw, ssin, lane);
+      cx<double> odd[L::CH], even[L::CH];
+      wdst_regs<double, N1, B, S, PS>(buf, stw, lane, odd, even, b, k0, valid);
+      if (valid && qb + b < q1) {
+        const cx<double> u = rh[qb + b];
 #pragma unroll
-      for (int j = 0; j < XPL; ++j) {
-        const int x = lane + 64 * j;
-        if (x >= M) continue;
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-          if (qb + b >= q1) continue;
-          const cx<double> y = buf[pk<PS>(x + 1) * S + b], u = rh[qb + b];
-          acc[j] += 2.0 * (u.x * y.x - u.y * y.y);
+        for (int cc = 0; cc < L::CH; ++cc) {
+          aodd[cc] += 2.0 * (u.x * odd[cc].x - u.y * odd[cc].y);
+          aeven[cc] += 2.0 * (u.x * even[cc].x - u.y * even[cc].y);
         }
       }
       wave_sync();
     }
+    // the B lines of a group are different frequencies of the same row: add the lanes
+    // that hold the same k for other b (lanes b*G + g), then lane b = 0 writes
+    constexpr int G = L::G;
 #pragma unroll
-    for (int j = 0; j < XPL; ++j) {
-      const int x = lane + 64 * j;
-      if (x < M) co.part[(size_t)c * 2 * m + (size_t)h * m + (size_t)x2 * M + x] = acc[j];
+    for (int cc = 0; cc < L::CH; ++cc) {
+      double so = aodd[cc], se = aeven[cc];
+#pragma unroll
+      for (int bb = 1; bb < B; ++bb) {
+        so += __shfl(aodd[cc], (lane + bb * G) & 63, 64);
+        se += __shfl(aeven[cc], (lane + bb * G) & 63, 64);
+      }
+      aodd[cc] = so;
+      aeven[cc] = se;
+    }
+    if (lane < G) {
+      double *dst = co.part + (size_t)c * 2 * m + (size_t)h * m + (size_t)x2 * M;
+      const int kk0 = lane * L::CH;
+#pragma unroll
+      for (int cc = 0; cc < L::CH; ++cc) {
+        const int k = kk0 + cc;
+        if (k > 0) dst[2 * k - 1] = aeven[cc];
+        if (2 * k < M) dst[2 * k] = aodd[cc];
+      }
     }
   }
 }
