@@ -801,16 +801,24 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
   const int c0 = (t % ncx) * TX;
   cx<P> *slab0 = W + ((size_t)q * 2 + 0) * M * M;
   cx<P> *slab1 = W + ((size_t)q * 2 + 1) * M * M;
-  // tile column 2c+h holds (block row h, x1 column c0+c)
+  // tile column 2c+h holds (block row h, x1 column c0+c).  The first sine transform's
+  // pre-processing is done on the loads: item (c, h, i) reads rows i-1 and N1-i-1 and
+  // writes y_i, y_{N1-i} (all loads issued first).
   constexpr int TT = 2 * TX * M;
-  constexpr int LIT = (TT + kThreads - 1) / kThreads;
-  cx<P> r[LIT];
+  constexpr int H = N1 / 2, TP = H * 2 * TX;
+  constexpr int LIT = (TP + kThreads - 1) / kThreads;
+  cx<P> ra[LIT], rb[LIT];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int idx = tid + it * kThreads;
-    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
-    r[it] = cx<P>{(P)0, (P)0};
-    if (idx < TT && c0 + c < M) r[it] = (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c];
+    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX);
+    ra[it] = cx<P>{(P)0, (P)0};
+    rb[it] = cx<P>{(P)0, (P)0};
+    if (idx < TP && c0 + c < M) {
+      const cx<P> *src = (h ? slab1 : slab0) + c0 + c;
+      ra[it] = src[(size_t)(i - 1) * M];
+      rb[it] = src[(size_t)(N1 - i - 1) * M];
+    }
   }
   if constexpr (C::TAB_LDS) {
     for (int i = tid; i < N1; i += kThreads) {
@@ -818,19 +826,24 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
       ssin[i] = sing[i];
     }
   }
+  __syncthreads();  // the sine table is read below
+  const P *sn = C::TAB_LDS ? ssin : sing;
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int idx = tid + it * kThreads;
-    if (idx < TT) {
-      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
-      buf[pk<PS>(x2 + 1) * S + 2 * c + h] = r[it];
-    }
+    if (idx >= TP) continue;
+    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX), col = 2 * c + h;
+    const P sv = sn[i];
+    const cx<P> sum = cadd(ra[it], rb[it]);
+    const cx<P> dif = cscale(csub(ra[it], rb[it]), (P)0.5);
+    buf[pk<PS>(i) * S + col] = cadd(cscale(sum, sv), dif);
+    if (i != H) buf[pk<PS>(N1 - i) * S + col] = csub(cscale(sum, sv), dif);
+    if (i == 1) buf[col] = cx<P>{(P)0, (P)0};
   }
   __syncthreads();
   const cx<P> *tw = C::TAB_LDS ? stw : twg;
-  const P *sn = C::TAB_LDS ? ssin : sing;
   cx<P> *wb = buf + wv * 2 * CPW;
-  wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
+  wdst_core<P, N1, 2 * CPW, S, PS>(wb, tw, lane);
   const cx<P> l = lam[q];
   for (int idx = lane; idx < CPW * M; idx += 64) {
     const int c = idx / M, j2 = idx % M;
