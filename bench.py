@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--flexible", type=int, default=1,
                     help="GMRES stores P^-1 v_j (same iterates; no final preconditioner apply)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mg-tol", type=float, default=1e-10,
+                    help="multigrid cycle tolerance (variable a); 0 = exactly --mg-cycles cycles")
+    ap.add_argument("--mg-cycles", type=int, default=30, help="multigrid cycle cap (variable a)")
     ap.add_argument("--coeff", choices=["const", "sin"], default="const",
                     help="a = 1, or a = 1 + 0.5 sin(2 pi x1) sin(2 pi x2) (multigrid)")
     ap.add_argument("--pc-reps", type=int, default=20)
@@ -248,7 +251,8 @@ def main():
     plan = wc.Plan(args.dims, args.M, n, theta=args.theta, gamma=args.gamma, method=args.method,
                    precision=args.precision, restart=args.restart, tol=1e-8, maxit=500,
                    a_face=d["a_face"], flexible=bool(args.flexible) and not args.lowrank,
-                   graphs=bool(args.graphs), lowrank=bool(args.lowrank))
+                   graphs=bool(args.graphs), lowrank=bool(args.lowrank),
+                   mg_tol=args.mg_tol, mg_max_cycles=args.mg_cycles)
     log(f"plan footprint {plan.footprint / 2**30:.2f} GiB")
     tiles = plan.autotune(reps=3) if args.autotune else (0, 0)
     log(f"tile widths (time FFT, x2 pass): {tiles}")
@@ -365,6 +369,8 @@ def main():
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
                    "flexible": bool(args.flexible) and not args.lowrank,
                    "lowrank": bool(args.lowrank), "tiles_ts_tx": list(tiles),
+                   "mg_tol": args.mg_tol if args.coeff == "sin" else None,
+                   "mg_cycles": args.mg_cycles if args.coeff == "sin" else None,
                    "dof": 2 * n * m, "seed": args.seed},
         "iters": iters, "relres": relres, "reorth": infos[-1].reorth,
         "mg_cycles_max": infos[-1].mg_cycles_max,
