@@ -503,12 +503,9 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     if ((N * TS % kThreads == 0 || idx < N * TS) && gs < m) {
       ra[it] = v1[(size_t)k * m + gs];
       rb[it] = v2[(size_t)k * m + gs];
-      if constexpr (GEN) {
-        ra[it] = gc * ra[it] + gi.gr[k] * a1;
-        rb[it] = gc * rb[it] + gi.gr[N + k] * a2;
-      }
     }
   }
+  // twiddles are staged while the tile's loads are in flight
   if constexpr (C::TW_LDS)
     for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
 #pragma unroll
@@ -517,7 +514,12 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     if (N * TS % kThreads == 0 || idx < N * TS) {
       const int k = idx / TS, s = idx % TS;
       const cx<double> d = dtw[k];
-      const double a = ra[it], b = rb[it];
+      double a = ra[it], b = rb[it];
+      if constexpr (GEN) {
+        // columns past m hold zeros there and get zero coefficients a1 = a2 = 0
+        a = gc * a + gi.gr[k] * a1;
+        b = gc * b + gi.gr[N + k] * a2;
+      }
       buf[pk<PS>(k) * S + s] = cx<P>{(P)(a * d.x - b * d.y), (P)(a * d.y + b * d.x)};
     }
   }
