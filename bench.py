@@ -77,7 +77,68 @@ def parse():
     ap.add_argument("--rates", default="5,20,60,150", help="arrival rates (requests/s), --serve")
     ap.add_argument("--requests", type=int, default=60, help="requests per rate, --serve")
     ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="instances of the small serving shape (2D, M=63, n=64) solved one by "
+                         "one and as one batch (0 = skip)")
     return ap.parse_args()
+
+
+def batch_bench(args):
+    """Many instances of a small problem: sequential wc_solve (captured iterations) against
+    one lockstep batch (one launch per preconditioner pass for all instances)."""
+    import numpy as np
+    import torch
+    import datagen
+    from paper_2406_00952_amd import wc
+    M, n, k = 63, 64, args.batch
+    plans = [wc.Plan(2, M, n, theta=0.5, gamma=1e-4, method="gmres_ps", tol=1e-8, maxit=500)
+             for _ in range(k)]
+    data = []
+    for i in range(k):
+        d = datagen.config_problem(2, M, n, seed=args.seed + 10 + i, noise_sigma=1e-3)
+        data.append([torch.from_numpy(np.ascontiguousarray(d[x])).cuda() for x in ("f", "g", "y0")])
+    ys = [torch.empty(n * M * M, dtype=torch.float64, device="cuda") for _ in range(k)]
+    ps = [torch.empty_like(y) for y in ys]
+    reps = 5
+
+    def seq():
+        return [pl.solve(*dd, y, p) for pl, dd, y, p in zip(plans, data, ys, ps)]
+
+    batch = wc.Batch(plans)
+    cols = [[dd[j] for dd in data] for j in range(3)]
+
+    def bat():
+        return batch.solve(cols[0], cols[1], cols[2], ys, ps)
+
+    out = {"instances": k, "shape": "2D M=63 n=64 fp64 GMRES(30)-P_S"}
+    for name, fn in (("sequential", seq), ("batch", bat)):
+        infos = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            infos = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        out[name] = {"ms": round(ms, 3), "solves_per_s": round(1000.0 * k / ms, 1),
+                     "iters": [i.iters for i in infos],
+                     "max_relres": max(i.relres for i in infos)}
+    vs = [torch.randn(2 * n * M * M, dtype=torch.float64, device="cuda") for _ in range(k)]
+    ws = [torch.empty_like(v) for v in vs]
+    for name, fn in (("pc_sequential_ms", lambda: [pl.pc_apply(v, w) for pl, v, w in zip(plans, vs, ws)]),
+                     ("pc_batch_ms", lambda: batch.pc_apply(vs, ws))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = round((time.perf_counter() - t0) * 1000.0 / 20, 4)
+    out["speedup"] = round(out["sequential"]["ms"] / out["batch"]["ms"], 3)
+    batch.close()
+    for pl in plans:
+        pl.close()
+    log(f"batch: {out}")
+    return out
 
 
 def log(*a):
@@ -298,6 +359,8 @@ def main():
         del sp
         torch.cuda.empty_cache()
 
+    batch = batch_bench(args) if args.batch > 0 else None
+
     # ---- preconditioner apply alone ------------------------------------------
     v = torch.randn(2 * n * m, dtype=torch.float64, device=dev)
     w = torch.empty_like(v)
@@ -376,6 +439,7 @@ def main():
         "mg_cycles_max": infos[-1].mg_cycles_max,
         "solves_per_s": round(1000.0 / ms_per_step, 3),
         "standard_form": standard,
+        "batch": batch,
         "pc_apply": {"ms": round(pc_ms, 4), "model_bytes": pc_bytes,
                      "GBps": round(pc_gbs, 1) if pc_gbs else None,
                      "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4) if pc_gbs else None,

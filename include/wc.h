@@ -249,6 +249,43 @@ wc_status wc_server_cancel(wc_server *srv, uint64_t ticket);
 /* Device bytes the server holds in plans (running plus idle). */
 size_t wc_server_bytes_in_use(wc_server *srv);
 
+/* ---- batches: many right-hand sides and instances in one launch per pass ---------
+ * The preconditioner apply of the three-step decomposition (time transform, spatial
+ * sine transforms with the per-mode 2x2 solves, inverse transforms; Section 3 and the
+ * P_S / |P_S| / P_MS applies of Section 4) for up to 32 instances at once: each pass
+ * is one kernel launch over the work units of every instance (per precision class,
+ * FP64 or mixed), whatever their grid M and steps n.  Many right-hand sides of one
+ * problem are several plans of that problem.
+ *
+ * wc_batch_create: plans[0..count) (1 <= count <= 32), distinct plans, each 2D with
+ * a == 1 (a_face NULL), n and M+1 in {64, 128, 256, 512}; otherwise WC_E_ARG (null,
+ * repeated plan, count out of range) or WC_E_UNSUPPORTED.  The batch borrows the plans
+ * (their spectral workspaces and tables): they must outlive it and must not be
+ * retargeted while it exists.  Every call runs on the plans' stream, which must be the
+ * same for all of them at the time of the call (else WC_E_ARG).
+ *
+ * wc_batch_pc_apply: w[i] = P_i^{-1} v[i] (device pointers, 2*n_i*m_i doubles each,
+ * v[i] != w[i]); stream-ordered and asynchronous, results equal to wc_pc_apply's for
+ * each plan.
+ *
+ * wc_batch_solve: wc_solve for every instance (f, g, y0, y, p arrays of device
+ * pointers, one per plan, sizes as for wc_solve) by GMRES(k)-P_S in the standard
+ * form (each plan's method must be WC_GMRES_PS and lowrank 0, else WC_E_UNSUPPORTED),
+ * advanced in lockstep: each round applies the preconditioner of every instance still
+ * iterating in one batched apply and synchronises the host once.  Each instance keeps
+ * its own tolerance, restart length, precision and iteration count, and stops on its
+ * own true residual.  infos[count] (may be NULL) receives each instance's wc_info;
+ * ms is the wall time of the whole batch.  Synchronous.  Returns WC_OK when every
+ * instance converged, else the first failure (WC_E_MAXIT if that is the only one);
+ * WC_E_MAXIT still writes y, p. */
+typedef struct wc_batch wc_batch;
+wc_status wc_batch_create(wc_plan *const *plans, int count, wc_batch **out);
+wc_status wc_batch_destroy(wc_batch *batch);
+wc_status wc_batch_pc_apply(wc_batch *batch, const double *const *v, double *const *w);
+wc_status wc_batch_solve(wc_batch *batch, const double *const *f, const double *const *g,
+                         const double *const *y0, double *const *y, double *const *p,
+                         wc_info *infos);
+
 /* Library build identification (static string). */
 const char *wc_version(void);
 

@@ -45,12 +45,6 @@ hipEvent_t Profiler::get() {
 
 namespace {
 
-#define WC_TRY(expr)                                          \
-  do {                                                        \
-    hipError_t _e = (expr);                                   \
-    if (_e != hipSuccess) return WC_E_HIP;                    \
-  } while (0)
-
 bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
 
 wc_status validate(const wc_problem *pr, const wc_opts *op) {

@@ -9,6 +9,13 @@
 
 #include "../../include/wc.h"
 
+// in a function returning wc_status: a failed HIP call returns WC_E_HIP
+#define WC_TRY(expr)                                          \
+  do {                                                        \
+    hipError_t _e = (expr);                                   \
+    if (_e != hipSuccess) return WC_E_HIP;                    \
+  } while (0)
+
 namespace wc {
 
 constexpr int kThreads = 256;        // threads per workgroup for every kernel
@@ -276,6 +283,23 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
 // ||r0||^2 in d_scal[S_DOT] (launch_dot before).
 hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
 bool pc_supported(int n, int N1);
+
+// ---- many instances in one launch per pass (2D, a = 1) ------------------------------
+// Per-instance data that stays fixed for the life of a batch (device resident): sizes,
+// step-2 parameters, the instance's spectral workspace and its tables in its precision.
+constexpr int kBatchMax = 32;
+struct BatchInst {
+  int n, N1, m, kind;
+  double tau, alpha, cnorm;
+  void *W;
+  const void *dtw, *twt, *tws, *sin, *lam, *mu;
+};
+bool batch_sizes_ok(int n, int N1);
+// P^{-1} v_i -> w_i for the instances idx[0..cnt) of the table, all of one precision
+// (FP64 or FP32 transforms): five launches, each over every instance's work units.
+hipError_t launch_pc_batch(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_tab,
+                           int cnt, const int *idx, const double *const *v, double *const *w,
+                           bool fp32);
 int pc_partials_needed(int n, int m, int precision);
 
 }  // namespace wc

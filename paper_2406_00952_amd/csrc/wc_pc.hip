@@ -24,7 +24,10 @@
 // in LDS; waves synchronise only themselves, so the four waves of a workgroup never wait
 // on each other between stages.  The DST running sum is a segmented wave-shuffle scan.
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "wc_internal.h"
 
@@ -464,18 +467,14 @@ __device__ __forceinline__ void mode_op(cx<P> &a, cx<P> &b, cx<P> l, P musum, in
 
 // ---- step 1a: time transform of both block rows ------------------------------
 // v: 2 x (n, m) FP64.  W: [q][half][s] complex, q = 0..n/2-1 <-> frequency l = q+1.
-template <typename P, int N, int TS_, bool GEN>
-__global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict__ v,
-                                                       cx<P> *__restrict__ W,
-                                                       const cx<double> *__restrict__ dtw,
-                                                       const cx<P> *__restrict__ twg, int m,
-                                                       GenIn gi) {
-  using C = TimeCfg<P, N, TS_>;
-  constexpr int TS = TS_, S = C::S, PS = C::PS;
-  __shared__ cx<P> buf[C::PN * S];
-  __shared__ cx<P> stw[C::TW_LDS ? N : 1];
+template <typename P, int N, int TS, bool GEN, bool TWL>
+__device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P> *__restrict__ W,
+                                              const cx<double> *__restrict__ dtw,
+                                              const cx<P> *__restrict__ twg, int m, GenIn gi,
+                                              int tile, cx<P> *buf, cx<P> *stw) {
+  using C = TimeCfg<P, N, TS>;
+  constexpr int S = C::S, PS = C::PS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int s0 = tile * TS;
   const double *v1 = v;
   const double *v2 = v + (size_t)N * m;
@@ -506,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     }
   }
   // twiddles are staged while the tile's loads are in flight
-  if constexpr (C::TW_LDS)
+  if constexpr (TWL)
     for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
@@ -524,7 +523,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, false, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  wfft<P, N, 1, TS / 4, S, PS, false, true>(buf + wv * (TS / 4), TWL ? stw : twg, lane);
   __syncthreads();
   for (int idx = tid; idx < (N / 2) * TS; idx += kThreads) {
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
@@ -537,22 +536,30 @@ __global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict_
     W[((size_t)q * 2 + 1) * m + gs] = mul_mi(D);
   }
 }
-
-// ---- step 3b: inverse time transform, real output, optional fused <w, dotv> ----
-template <typename P, int N, int TS_>
-__global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
-                                                       double *__restrict__ out,
+template <typename P, int N, int TS, bool GEN>
+__global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict__ v,
+                                                       cx<P> *__restrict__ W,
                                                        const cx<double> *__restrict__ dtw,
                                                        const cx<P> *__restrict__ twg, int m,
-                                                       const double *__restrict__ dotv,
-                                                       double *__restrict__ partials) {
-  using C = TimeCfg<P, N, TS_>;
-  constexpr int TS = TS_, S = C::S, PS = C::PS;
-  __shared__ cx<P> buf[C::PN * S];
+                                                       GenIn gi) {
+  using C = TimeCfg<P, N, TS>;
+  __shared__ cx<P> buf[C::PN * C::S];
   __shared__ cx<P> stw[C::TW_LDS ? N : 1];
-  __shared__ double red[kThreads / 64];
+  tfft_fwd_tile<P, N, TS, GEN, C::TW_LDS>(v, W, dtw, twg, m, gi, xcd_tile(blockIdx.x, gridDim.x),
+                                          buf, stw);
+}
+
+// ---- step 3b: inverse time transform, real output, optional fused <w, dotv> ----
+template <typename P, int N, int TS, bool TWL>
+__device__ __forceinline__ void tfft_inv_tile(const cx<P> *__restrict__ W, double *__restrict__ out,
+                                              const cx<double> *__restrict__ dtw,
+                                              const cx<P> *__restrict__ twg, int m,
+                                              const double *__restrict__ dotv,
+                                              double *__restrict__ partials, int tile, cx<P> *buf,
+                                              cx<P> *stw, double *red) {
+  using C = TimeCfg<P, N, TS>;
+  constexpr int S = C::S, PS = C::PS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int s0 = tile * TS;
   constexpr int HT = (N / 2) * TS;
   constexpr int LIT = (HT + kThreads - 1) / kThreads;
@@ -568,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
       rb[it] = W[((size_t)q * 2 + 1) * m + gs];
     }
   }
-  if constexpr (C::TW_LDS)
+  if constexpr (TWL)
     for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
@@ -581,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, true, true>(buf + wv * (TS / 4), C::TW_LDS ? stw : twg, lane);
+  wfft<P, N, 1, TS / 4, S, PS, true, true>(buf + wv * (TS / 4), TWL ? stw : twg, lane);
   __syncthreads();
   double acc = 0.0;
   double *o1 = out;
@@ -605,14 +612,48 @@ __global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__
   }
 }
 
+template <typename P, int N, int TS>
+__global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
+                                                       double *__restrict__ out,
+                                                       const cx<double> *__restrict__ dtw,
+                                                       const cx<P> *__restrict__ twg, int m,
+                                                       const double *__restrict__ dotv,
+                                                       double *__restrict__ partials) {
+  using C = TimeCfg<P, N, TS>;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TW_LDS ? N : 1];
+  __shared__ double red[kThreads / 64];
+  tfft_inv_tile<P, N, TS, C::TW_LDS>(W, out, dtw, twg, m, dotv, partials,
+                                     xcd_tile(blockIdx.x, gridDim.x), buf, stw, red);
+}
+
 // ---- sine transform of contiguous rows, in place (2D x1 passes) ------------------
 // nlines rows of M complex each; every wave owns B rows at a time.
+template <typename P, int N1>
+__device__ __forceinline__ void dst_rows_group(cx<P> *__restrict__ W, int nlines, int grp,
+                                               const cx<P> *tw, const P *sn, cx<P> *buf,
+                                               int lane) {
+  using R = RowCfg<P, N1>;
+  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  const int l0 = grp * B;
+  dst_pre_global<P, N1, B, S, PS>(buf, sn, lane, [&](int b, int x) {
+    return l0 + b < nlines ? W[(size_t)(l0 + b) * M + x] : cx<P>{(P)0, (P)0};
+  });
+  wave_sync();
+  wdst_core<P, N1, B, S, PS>(buf, tw, lane);
+  for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
+    const int b = idx / M, x = idx % M;
+    if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
+  }
+  wave_sync();
+}
+
 template <typename P, int N1>
 __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, int nlines,
                                                        const cx<P> *__restrict__ twg,
                                                        const P *__restrict__ sing) {
   using R = RowCfg<P, N1>;
-  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  constexpr int B = R::B, S = R::S;
   __shared__ cx<P> lds[R::WPB][R::PN * S];
   __shared__ cx<P> stw[N1];
   __shared__ P ssin[N1];
@@ -622,21 +663,9 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
     ssin[i] = sing[i];
   }
   __syncthreads();
-  cx<P> *buf = lds[wv];
   const int ngroups = (nlines + B - 1) / B;
-  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
-    const int l0 = grp * B;
-    dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
-      return l0 + b < nlines ? W[(size_t)(l0 + b) * M + x] : cx<P>{(P)0, (P)0};
-    });
-    wave_sync();
-    wdst_core<P, N1, B, S, PS>(buf, stw, lane);
-    for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
-      const int b = idx / M, x = idx % M;
-      if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
-    }
-    wave_sync();
-  }
+  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB)
+    dst_rows_group<P, N1>(W, nlines, grp, stw, ssin, lds[wv], lane);
 }
 
 // ---- 2D low-rank GMRES: inverse x1 sine transform fused with the time contraction ----
@@ -783,22 +812,17 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
 
 // ---- 2D: x2-DST, step 2, x2-iDST on tiles of TX x1-columns (both block rows) -------
 // W layout [q][half][x2][x1], x1 already sine transformed (index j1).
-template <typename P, int N1, int TX_>
-__global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
-                                                        const cx<P> *__restrict__ twg,
-                                                        const P *__restrict__ sing,
-                                                        const cx<P> *__restrict__ lam,
-                                                        const P *__restrict__ mu, int kind,
-                                                        P tau, P alpha, P cnorm) {
-  using C = ColCfg<P, N1, TX_>;
-  constexpr int M = N1 - 1, TX = TX_, S = C::S, PS = C::PS;
+template <typename P, int N1, int TX, bool TABL>
+__device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
+                                               const P *__restrict__ sing,
+                                               const cx<P> *__restrict__ lam,
+                                               const P *__restrict__ mu, int kind, P tau, P alpha,
+                                               P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / 4;  // columns per wave
-  __shared__ cx<P> buf[C::PN * S];
-  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
-  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ncx = (N1 - 2 + TX) / TX;  // column tiles per frequency, M = N1 - 1 columns
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int q = t / ncx;
   const int c0 = (t % ncx) * TX;
   cx<P> *slab0 = W + ((size_t)q * 2 + 0) * M * M;
@@ -822,14 +846,14 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
       rb[it] = src[(size_t)(N1 - i - 1) * M];
     }
   }
-  if constexpr (C::TAB_LDS) {
+  if constexpr (TABL) {
     for (int i = tid; i < N1; i += kThreads) {
       stw[i] = twg[i];
       ssin[i] = sing[i];
     }
   }
   __syncthreads();  // the sine table is read below
-  const P *sn = C::TAB_LDS ? ssin : sing;
+  const P *sn = TABL ? ssin : sing;
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int idx = tid + it * kThreads;
@@ -843,7 +867,7 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
     if (i == 1) buf[col] = cx<P>{(P)0, (P)0};
   }
   __syncthreads();
-  const cx<P> *tw = C::TAB_LDS ? stw : twg;
+  const cx<P> *tw = TABL ? stw : twg;
   cx<P> *wb = buf + wv * 2 * CPW;
   wdst_core<P, N1, 2 * CPW, S, PS>(wb, tw, lane);
   const cx<P> l = lam[q];
@@ -865,6 +889,21 @@ __global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
     if (c0 + c < M)
       (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
   }
+}
+
+template <typename P, int N1, int TX>
+__global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
+                                                        const cx<P> *__restrict__ twg,
+                                                        const P *__restrict__ sing,
+                                                        const cx<P> *__restrict__ lam,
+                                                        const P *__restrict__ mu, int kind,
+                                                        P tau, P alpha, P cnorm) {
+  using C = ColCfg<P, N1, TX>;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  cols_mode_tile<P, N1, TX, C::TAB_LDS>(W, twg, sing, lam, mu, kind, tau, alpha, cnorm,
+                                        xcd_tile(blockIdx.x, gridDim.x), buf, stw, ssin);
 }
 
 
@@ -1110,11 +1149,332 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   return e;
 }
 
+
+// ---- many instances of uneven (n, M) in one persistent launch per pass ------------
+// A pass lists the work units of the instances back to back (time tiles, x1 row groups,
+// x2 column tiles) and launches one workgroup per unit; each finds its instance from the
+// prefix counts and runs the tile body of the single-instance kernels at that instance's
+// sizes.  Instances of every grid M share a time-pass launch when their n is the same,
+// and instances of every n share a sine-pass launch when their M is the same: a launch
+// whose LDS is sized for the largest tile runs the small tiles at the large tile's
+// occupancy, so a pass launches once per tile shape present (at most four).  (A grid-stride loop over the units
+// keeps loop-invariant addressing live across units: about 60 more VGPRs, one workgroup
+// per CU.)  The dynamic LDS holds the largest tile of the batch and, behind it, the
+// unit's own twiddle and sine tables, staged like the single kernels do; units are
+// spread over the XCDs like the single kernels' tiles.
+struct BatchArgs {
+  int count;
+  int inst[kBatchMax];
+  const double *v[kBatchMax];
+  double *w[kBatchMax];
+  int t0[kBatchMax + 1];  // first work unit of each instance in this pass
+  int aux;                // byte offset of the per-unit tables in the dynamic LDS
+};
+
+#define WC_BATCH_CASES(X) X(64) X(128) X(256) X(512)
+
+__device__ __forceinline__ int batch_find(const BatchArgs &a, int t) {
+  int i = 0;
+  while (i + 1 < a.count && t >= a.t0[i + 1]) ++i;
+  return i;
+}
+
+template <typename P, bool TBL>
+__global__ __launch_bounds__(kThreads) void k_batch_tfft_fwd(const BatchInst *__restrict__ tab,
+                                                             BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
+  cx<P> *stw = reinterpret_cast<cx<P> *>(dyn_lds + a.aux);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= a.t0[a.count]) return;
+  const int i = batch_find(a, t);
+  const BatchInst &I = tab[a.inst[i]];
+  cx<P> *W = static_cast<cx<P> *>(I.W);
+  const auto *dtw = static_cast<const cx<double> *>(I.dtw);
+  const auto *tw = static_cast<const cx<P> *>(I.twt);
+  switch (I.n) {
+#define CASE_B(NN)                                                                             \
+  case NN:                                                                                     \
+    tfft_fwd_tile<P, NN, default_ts<P, NN>(), false, TBL>(a.v[i], W, dtw, tw, I.m, GenIn{},   \
+                                                         t - a.t0[i], buf, stw);               \
+    break;
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+}
+
+template <typename P, bool TBL>
+__global__ __launch_bounds__(kThreads) void k_batch_tfft_inv(const BatchInst *__restrict__ tab,
+                                                             BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
+  cx<P> *stw = reinterpret_cast<cx<P> *>(dyn_lds + a.aux);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= a.t0[a.count]) return;
+  const int i = batch_find(a, t);
+  const BatchInst &I = tab[a.inst[i]];
+  const cx<P> *W = static_cast<const cx<P> *>(I.W);
+  const auto *dtw = static_cast<const cx<double> *>(I.dtw);
+  const auto *tw = static_cast<const cx<P> *>(I.twt);
+  switch (I.n) {
+#define CASE_B(NN)                                                                             \
+  case NN:                                                                                     \
+    tfft_inv_tile<P, NN, default_ts<P, NN>(), TBL>(W, a.w[i], dtw, tw, I.m, nullptr,         \
+                                                   nullptr, t - a.t0[i], buf, stw,         \
+                                                   nullptr);                                   \
+    break;
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+}
+
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_batch_rows(const BatchInst *__restrict__ tab,
+                                                         BatchArgs a, int slice) {
+  // a unit is kThreads/64 consecutive line groups of one instance, one per wave
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int WPB = kThreads / 64;
+  const int t = blockIdx.x;
+  if (t >= a.t0[a.count]) return;
+  const int i = batch_find(a, t);
+  const BatchInst &I = tab[a.inst[i]];
+  cx<P> *W = static_cast<cx<P> *>(I.W);
+  cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds + (size_t)wv * slice);
+  cx<P> *stw = reinterpret_cast<cx<P> *>(dyn_lds + a.aux);
+  P *ssin = reinterpret_cast<P *>(stw + I.N1);
+  const auto *tw = static_cast<const cx<P> *>(I.tws);
+  const auto *sn = static_cast<const P *>(I.sin);
+  for (int k = threadIdx.x; k < I.N1; k += kThreads) {
+    stw[k] = tw[k];
+    ssin[k] = sn[k];
+  }
+  __syncthreads();
+  const int grp = (t - a.t0[i]) * WPB + wv;
+  switch (I.N1) {
+#define CASE_B(NN)                                                                             \
+  case NN:                                                                                     \
+    if (grp < (I.n * (NN - 1) + RowCfg<P, NN>::B - 1) / RowCfg<P, NN>::B)                      \
+      dst_rows_group<P, NN>(W, I.n * (NN - 1), grp, stw, ssin, buf, lane);                     \
+    break;
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+}
+
+template <typename P, bool TBL>
+__global__ __launch_bounds__(kThreads) void k_batch_cols(const BatchInst *__restrict__ tab,
+                                                         BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
+  cx<P> *stw = reinterpret_cast<cx<P> *>(dyn_lds + a.aux);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= a.t0[a.count]) return;
+  const int i = batch_find(a, t);
+  const BatchInst &I = tab[a.inst[i]];
+  cx<P> *W = static_cast<cx<P> *>(I.W);
+  const auto *tw = static_cast<const cx<P> *>(I.tws);
+  const auto *sn = static_cast<const P *>(I.sin);
+  P *ssin = reinterpret_cast<P *>(stw + I.N1);
+  const auto *lam = static_cast<const cx<P> *>(I.lam);
+  const auto *mu = static_cast<const P *>(I.mu);
+  switch (I.N1) {
+#define CASE_B(NN)                                                                             \
+  case NN:                                                                                     \
+    cols_mode_tile<P, NN, default_tx<P, NN>(), TBL>(W, tw, sn, lam, mu, I.kind, (P)I.tau,    \
+                                                    (P)I.alpha, (P)I.cnorm, t - a.t0[i],       \
+                                                    buf, stw, ssin);                    \
+    break;
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+}
+
+// work units and LDS bytes of one instance in each pass
+template <typename P> struct BatchShape {
+  int time_units, time_lds, time_tab, row_units, row_slice, col_units, col_lds, space_tab;
+};
+template <typename P> BatchShape<P> batch_shape(int n, int N1, int m) {
+  BatchShape<P> b{};
+  switch (n) {
+#define CASE_B(NN)                                                                             \
+  case NN: {                                                                                   \
+    constexpr int TS = default_ts<P, NN>();                                                    \
+    b.time_units = (m + TS - 1) / TS;                                                          \
+    b.time_lds = TimeCfg<P, NN, TS>::TILE;                                                     \
+    b.time_tab = NN * TimeCfg<P, NN, TS>::CXB;                                                 \
+    break;                                                                                     \
+  }
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+  switch (N1) {
+#define CASE_B(NN)                                                                             \
+  case NN: {                                                                                   \
+    using R = RowCfg<P, NN>;                                                                   \
+    constexpr int TX = default_tx<P, NN>();                                                    \
+    b.row_units = ((n * (NN - 1) + R::B - 1) / R::B + kThreads / 64 - 1) / (kThreads / 64);    \
+    b.row_slice = R::PN * R::S * R::CXB;                                                       \
+    b.col_units = ((NN - 1 + TX - 1) / TX) * (n / 2);                                          \
+    b.col_lds = ColCfg<P, NN, TX>::TILE;                                                       \
+    b.space_tab = ColCfg<P, NN, TX>::TAB;                                                      \
+    break;                                                                                     \
+  }
+    WC_BATCH_CASES(CASE_B)
+#undef CASE_B
+    default: break;
+  }
+  return b;
+}
+
+// Dynamic LDS above 64 KiB must be allowed per kernel; done once per kernel, for the
+// whole CU budget.
+hipError_t allow_lds(const void *kernel, int lds) {
+  static std::mutex mu;
+  static std::vector<const void *> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), kernel) != done.end()) return hipSuccess;
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kCuLds) ==
+      hipSuccess) {
+    done.push_back(kernel);
+    return hipSuccess;
+  }
+  (void)hipGetLastError();  // the whole budget refused: allow this launch's size only
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+template <typename K>
+hipError_t batch_launch(K kernel, int units, int lds, hipStream_t st, const BatchInst *tab,
+                        const BatchArgs &a) {
+  if (lds > 65536 && allow_lds((const void *)kernel, lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kernel, dim3(std::max(1, units)), dim3(kThreads), (size_t)lds, st, tab, a);
+  return hipGetLastError();
+}
+
+// tables behind the largest tile when that keeps the same number of resident workgroups
+int with_tables(int tile, int tab, BatchArgs &a) {
+  a.aux = (tile + 15) & ~15;
+  return blocks_per_cu(a.aux + tab) == blocks_per_cu(tile) ? a.aux + tab : 0;
+}
+
+// One pass over the instances whose tile shape matches `key` (n for the time passes, M+1
+// for the sine passes): their work units back to back in one launch.
+template <typename P>
+BatchArgs batch_args(const BatchInst *h_tab, int cnt, const int *idx, const double *const *v,
+                     double *const *w, bool time, int key, int *lds, int *tab, int *slice) {
+  BatchArgs a{};
+  *lds = *tab = *slice = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const BatchInst &I = h_tab[idx[i]];
+    if ((time ? I.n : I.N1) != key) continue;
+    const BatchShape<P> b = batch_shape<P>(I.n, I.N1, I.m);
+    const int k = a.count++;
+    a.inst[k] = idx[i];
+    a.v[k] = v ? v[i] : nullptr;
+    a.w[k] = w ? w[i] : nullptr;
+    a.t0[k + 1] = a.t0[k] + (time ? b.time_units : b.row_units);
+    *lds = time ? b.time_lds : b.col_lds;
+    *tab = time ? b.time_tab : b.space_tab;
+    *slice = b.row_slice;
+  }
+  return a;
+}
+
+// the distinct values of n (time) or M+1 (sine passes) among the instances
+std::vector<int> batch_keys(const BatchInst *h_tab, int cnt, const int *idx, bool time) {
+  std::vector<int> k;
+  for (int i = 0; i < cnt; ++i) {
+    const int x = time ? h_tab[idx[i]].n : h_tab[idx[i]].N1;
+    if (std::find(k.begin(), k.end(), x) == k.end()) k.push_back(x);
+  }
+  return k;
+}
+
+template <typename P>
+hipError_t time_pass(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_tab, int cnt,
+                     const int *idx, const double *const *v, double *const *w, bool inverse) {
+  for (int key : batch_keys(h_tab, cnt, idx, true)) {
+    int tl, tt, unused;
+    BatchArgs a = batch_args<P>(h_tab, cnt, idx, v, w, true, key, &tl, &tt, &unused);
+    const int tlt = with_tables(tl, tt, a);
+    hipError_t e;
+    if (inverse)
+      e = tlt ? batch_launch(k_batch_tfft_inv<P, true>, a.t0[a.count], tlt, st, d_tab, a)
+              : batch_launch(k_batch_tfft_inv<P, false>, a.t0[a.count], tl, st, d_tab, a);
+    else
+      e = tlt ? batch_launch(k_batch_tfft_fwd<P, true>, a.t0[a.count], tlt, st, d_tab, a)
+              : batch_launch(k_batch_tfft_fwd<P, false>, a.t0[a.count], tl, st, d_tab, a);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename P>
+hipError_t space_pass(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_tab, int cnt,
+                      const int *idx, bool cols) {
+  for (int key : batch_keys(h_tab, cnt, idx, false)) {
+    int cl, ct, rs;
+    BatchArgs a = batch_args<P>(h_tab, cnt, idx, nullptr, nullptr, false, key, &cl, &ct, &rs);
+    hipError_t e;
+    if (cols) {
+      // column tiles: recount the units (the list above holds the row units)
+      for (int k = 0; k < a.count; ++k) {
+        const BatchInst &I = h_tab[a.inst[k]];
+        a.t0[k + 1] = a.t0[k] + batch_shape<P>(I.n, I.N1, I.m).col_units;
+      }
+      const int clt = with_tables(cl, ct, a);
+      e = clt ? batch_launch(k_batch_cols<P, true>, a.t0[a.count], clt, st, d_tab, a)
+              : batch_launch(k_batch_cols<P, false>, a.t0[a.count], cl, st, d_tab, a);
+    } else {
+      a.aux = rs * (kThreads / 64);  // the row passes always stage their tables
+      const int rl = a.aux + ct;
+      if (rl > 65536) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_batch_rows<P>, dim3(std::max(1, a.t0[a.count])), dim3(kThreads),
+                         (size_t)rl, st, d_tab, a, rs);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename P>
+hipError_t pc_batch_t(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_tab, int cnt,
+                      const int *idx, const double *const *v, double *const *w) {
+  hipError_t e;
+  if ((e = time_pass<P>(st, d_tab, h_tab, cnt, idx, v, w, false)) != hipSuccess) return e;
+  if ((e = space_pass<P>(st, d_tab, h_tab, cnt, idx, false)) != hipSuccess) return e;
+  if ((e = space_pass<P>(st, d_tab, h_tab, cnt, idx, true)) != hipSuccess) return e;
+  if ((e = space_pass<P>(st, d_tab, h_tab, cnt, idx, false)) != hipSuccess) return e;
+  return time_pass<P>(st, d_tab, h_tab, cnt, idx, v, w, true);
+}
+
 }  // namespace
 
 bool pc_supported(int n, int N1) {
   auto pow2 = [](int x) { return x >= 4 && x <= 1024 && (x & (x - 1)) == 0; };
   return pow2(n) && pow2(N1);
+}
+
+bool batch_sizes_ok(int n, int N1) {
+  auto ok = [](int x) { return x == 64 || x == 128 || x == 256 || x == 512; };
+  return ok(n) && ok(N1);
+}
+
+hipError_t launch_pc_batch(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_tab,
+                           int cnt, const int *idx, const double *const *v, double *const *w,
+                           bool fp32) {
+  if (cnt < 1 || cnt > kBatchMax) return hipErrorInvalidValue;
+  for (int i = 0; i < cnt; ++i)
+    if (!batch_sizes_ok(h_tab[idx[i]].n, h_tab[idx[i]].N1)) return hipErrorInvalidValue;
+  return fp32 ? pc_batch_t<float>(st, d_tab, h_tab, cnt, idx, v, w)
+              : pc_batch_t<double>(st, d_tab, h_tab, cnt, idx, v, w);
 }
 
 hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool dot,

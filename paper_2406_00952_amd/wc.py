@@ -94,6 +94,13 @@ _lib.wc_server_wait.argtypes = [_vp, _u64, ctypes.POINTER(_Info), ctypes.POINTER
 _lib.wc_server_cancel.argtypes = [_vp, _u64]
 _lib.wc_server_bytes_in_use.argtypes = [_vp]
 _lib.wc_server_bytes_in_use.restype = ctypes.c_size_t
+_vpp = ctypes.POINTER(_vp)
+_lib.wc_batch_create.argtypes = [_vpp, ctypes.c_int, ctypes.POINTER(_vp)]
+_lib.wc_batch_destroy.argtypes = [_vp]
+_lib.wc_batch_pc_apply.argtypes = [_vp, _vpp, _vpp]
+_lib.wc_batch_solve.argtypes = [_vp, _vpp, _vpp, _vpp, _vpp, _vpp, ctypes.POINTER(_Info)]
+for _f in ("wc_batch_create", "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve"):
+    getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
            "wc_server_wait", "wc_server_cancel"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -105,7 +112,8 @@ EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_p
             "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
             "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read",
             "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
-            "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use"]
+            "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use", "wc_batch_create",
+            "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve"]
 
 
 def status_str(code: int) -> str:
@@ -279,6 +287,50 @@ class Plan:
 def _info(inf) -> Info:
     return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
                 inf.mg_cycles_max, inf.reorth)
+
+
+def _ptrs(ts):
+    return (_vp * len(ts))(*[_ptr(t) for t in ts])
+
+
+class Batch:
+    """Several plans whose preconditioner passes run as one launch per pass (include/wc.h,
+    batches).  The plans must stay open, share one stream and not be retargeted while the
+    batch exists."""
+
+    def __init__(self, plans):
+        self._plans = list(plans)
+        arr = (_vp * len(self._plans))(*[p._h for p in self._plans])
+        h = _vp()
+        code = _lib.wc_batch_create(arr, len(self._plans), ctypes.byref(h))
+        if code != WC_OK:
+            raise WcError(code, "wc_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.wc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pc_apply(self, vs, ws):
+        code = _lib.wc_batch_pc_apply(self._h, _ptrs(vs), _ptrs(ws))
+        if code != WC_OK:
+            raise WcError(code, "wc_batch_pc_apply")
+
+    def solve(self, fs, gs, y0s, ys, ps, allow_maxit=False):
+        """GMRES(k)-P_S of every instance in lockstep; one Info per instance."""
+        infs = (_Info * len(self._plans))()
+        code = _lib.wc_batch_solve(self._h, _ptrs(fs), _ptrs(gs), _ptrs(y0s), _ptrs(ys),
+                                   _ptrs(ps), infs)
+        if not (code == WC_OK or (allow_maxit and code == WC_E_MAXIT)):
+            raise WcError(code, "wc_batch_solve")
+        return [_info(i) for i in infs]
 
 
 class Server:

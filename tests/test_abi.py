@@ -116,3 +116,22 @@ def test_lowrank_options_and_footprint(wc):
     assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", precision="mixed", lowrank=True) == 0
     a = np.ones(2 * 31 * 32)
     assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", a_face=a, lowrank=True) == 0
+
+
+def test_batch_null_arguments(wc):
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.wc_batch_create.argtypes = [vp, ctypes.c_int, vp]
+    lib.wc_batch_destroy.argtypes = [vp]
+    lib.wc_batch_pc_apply.argtypes = [vp, vp, vp]
+    lib.wc_batch_solve.argtypes = [vp] * 7
+    h = vp()
+    assert lib.wc_batch_create(None, 1, ctypes.byref(h)) == wc.WC_E_ARG
+    plans = (vp * 2)(None, None)
+    assert lib.wc_batch_create(plans, 0, ctypes.byref(h)) == wc.WC_E_ARG   # empty batch
+    assert lib.wc_batch_create(plans, 33, ctypes.byref(h)) == wc.WC_E_ARG  # above 32
+    assert lib.wc_batch_create(plans, 2, ctypes.byref(h)) == wc.WC_E_ARG   # null plans
+    assert lib.wc_batch_create(plans, 1, None) == wc.WC_E_ARG
+    assert lib.wc_batch_destroy(None) == wc.WC_E_ARG
+    assert lib.wc_batch_pc_apply(None, None, None) == wc.WC_E_ARG
+    assert lib.wc_batch_solve(None, None, None, None, None, None, None) == wc.WC_E_ARG
