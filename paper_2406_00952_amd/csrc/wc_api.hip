@@ -448,20 +448,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
           // not dominated by v, so one classical Gram-Schmidt pass normally suffices
           if ((e = launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj)) != hipSuccess) return e;
         }
-        if ((e = launch_multidot(*p, V, j + 1, Vn, true, nullptr, &np, len)) != hipSuccess)
-          return e;
-        if ((e = launch_gs_finalize(*p, 1, j, np)) != hipSuccess) return e;
-        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, &np, len)) !=
-            hipSuccess)
-          return e;
-        if ((e = launch_gs_finalize(*p, 2, j, np)) != hipSuccess) return e;
-        if ((e = launch_multidot(*p, V, j + 1, Vn, false, gate, &np, len)) != hipSuccess)
-          return e;
-        if ((e = launch_gs_finalize(*p, 3, j, np)) != hipSuccess) return e;
-        if ((e = launch_multiaxpy(*p, Vn, V, j + 1, S_GSC, -1.0, true, gate, &np, len)) !=
-            hipSuccess)
-          return e;
-        if ((e = launch_gs_finalize(*p, 4, j, np)) != hipSuccess) return e;
+        if ((e = launch_gram_schmidt(*p, V, j, Vn, len)) != hipSuccess) return e;
         return hipMemcpyAsync(p->h_scal + S_WN2, p->d_scal + S_WN2,
                               (S_D2 + j + 1 - S_WN2) * sizeof(double), hipMemcpyDeviceToHost,
                               p->stream);

@@ -94,21 +94,9 @@ hipError_t arnoldi_tail(Lane &L) {
   wc_plan &p = *L.p;
   const size_t nv = p.nvec;
   double *Vj = L.V + (size_t)L.j * nv, *Vn = L.V + (size_t)(L.j + 1) * nv;
-  const double *gate = p.d_scal + S_REORTH;
-  int np = 0;
   hipError_t e;
   if ((e = launch_matvec(p, L.Zj(), Vn, p.d_partials, nullptr, Vj)) != hipSuccess) return e;
-  if ((e = launch_multidot(p, L.V, L.j + 1, Vn, true, nullptr, &np)) != hipSuccess) return e;
-  if ((e = launch_gs_finalize(p, 1, L.j, np)) != hipSuccess) return e;
-  if ((e = launch_multiaxpy(p, Vn, L.V, L.j + 1, S_GSC, -1.0, true, nullptr, &np)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_gs_finalize(p, 2, L.j, np)) != hipSuccess) return e;
-  if ((e = launch_multidot(p, L.V, L.j + 1, Vn, false, gate, &np)) != hipSuccess) return e;
-  if ((e = launch_gs_finalize(p, 3, L.j, np)) != hipSuccess) return e;
-  if ((e = launch_multiaxpy(p, Vn, L.V, L.j + 1, S_GSC, -1.0, true, gate, &np)) != hipSuccess)
-    return e;
-  if ((e = launch_gs_finalize(p, 4, L.j, np)) != hipSuccess) return e;
+  if ((e = launch_gram_schmidt(p, L.V, L.j, Vn)) != hipSuccess) return e;
   return read_async(L.p, S_WN2, S_D2 + L.j + 1 - S_WN2);
 }
 

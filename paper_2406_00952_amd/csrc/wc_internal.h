@@ -65,6 +65,7 @@ enum ScalarSlot : int {
   S_MG_RELRES = 310,  // largest relative residual over the multigrid systems
   S_LR_N0 = 320,      // low-rank GMRES: squared norm of r0's part outside the correction's range
   S_LR_SQN0,          //   its square root (0 when that part vanishes)
+  S_GS_COUNT = 330,   // Gram-Schmidt reductions: workgroups done (an unsigned counter, 0 at rest)
   S_COUNT = 512
 };
 
@@ -266,6 +267,12 @@ hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, in
 // Gram-Schmidt bookkeeping of GMRES iteration j (one block): stage 1 first-pass dots,
 // 2 first-pass norm and DGKS test, 3 second-pass dots, 4 second-pass norm.
 hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count);
+// Both classical Gram-Schmidt passes of GMRES iteration j on Vn against V_0..V_j (vectors of
+// length len, 0: a system vector), the second gated on the device by the DGKS test; the
+// bookkeeping of each reduction (the four gs_finalize stages) is done by the last
+// workgroup of that reduction, so the passes are four launches.
+hipError_t launch_gram_schmidt(const wc_plan &p, const double *V, int j, double *Vn,
+                               size_t len = 0);
 hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count);
 hipError_t launch_copy(const wc_plan &p, double *dst, const double *src, size_t count);
 

@@ -365,70 +365,14 @@ __global__ __launch_bounds__(kThreads) void k_minres_scalar(const double *__rest
   }
 }
 
-// <basis_i, w> for i < NB (and <w, w> when SELF), basis vectors contiguous with stride nv.
-// partials[j * gridDim.x + block].  Does nothing when gate && *gate == 0.
-template <int NB, bool SELF>
-__global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict__ basis,
-                                                       const double *__restrict__ w, size_t nv,
-                                                       double *__restrict__ partials,
-                                                       const double *__restrict__ gate) {
-  if (gate && *gate == 0.0) return;
-  __shared__ double red[kThreads / 64];
-  constexpr int NS = NB + (SELF ? 1 : 0);
-  double acc[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j) acc[j] = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads) {
-    const double wi = w[i];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
-    if (SELF) acc[NS - 1] += wi * wi;
-  }
-  for (int j = 0; j < NS; ++j) {
-    const double r = block_sum(acc[j], red);
-    if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = r;
-  }
-}
-
-// w += sign * sum_i scal[slot+i] basis_i  (optional partials of ||w||^2); gated like above
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
-                                                        const double *__restrict__ basis,
-                                                        size_t nv, const double *__restrict__ scal,
-                                                        int slot, double sign,
-                                                        double *__restrict__ partials,
-                                                        const double *__restrict__ gate) {
-  if (gate && *gate == 0.0) return;
-  __shared__ double red[kThreads / 64];
-  double c[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) c[j] = sign * scal[slot + j];
-  double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads) {
-    double v = w[i];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) v += c[j] * basis[(size_t)j * nv + i];
-    w[i] = v;
-    acc += v * v;
-  }
-  if (partials) {
-    const double r = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = r;
-  }
-}
-
 // Gram-Schmidt bookkeeping for GMRES iteration j (basis V_0..V_j, new vector w).
 //  stage 1: D1_i = <V_i, w>, WN2 = ||w||^2, GSC_i = D1_i / NU2_i
 //  stage 2: WP2 = ||w'||^2; REORTH = WP2 < kReorthEta2 * WN2 (the projection cancelled
 //           most of the norm: orthogonality may be lost, project again); else NU2_{j+1} = WP2
 //  stage 3 (when REORTH): D2_i = <V_i, w'>, GSC_i = D2_i / NU2_i
 //  stage 4 (when REORTH): WPP2 = ||w''||^2, NU2_{j+1} = WPP2
-__global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restrict__ partials,
-                                                          int count, double *__restrict__ S,
-                                                          int stage, int j) {
-  __shared__ double red[kThreads / 64];
+__device__ void gs_finalize_block(const double *__restrict__ partials, int count,
+                                  double *__restrict__ S, int stage, int j, double *red) {
   if ((stage == 3 || stage == 4) && S[S_REORTH] == 0.0) return;
   const int nsum = stage == 1 ? j + 2 : (stage == 3 ? j + 1 : 1);
   for (int t = 0; t < nsum; ++t) {
@@ -458,6 +402,90 @@ __global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restri
       }
     }
   }
+}
+
+// End of a reduction kernel whose thread 0 has written this workgroup's partials: the
+// workgroup that finishes last (device-scope counter in the scalar array) folds all
+// partials into the Gram-Schmidt scalars and resets the counter for the next launch.
+__device__ void finalize_if_last(const double *__restrict__ partials, double *__restrict__ S,
+                                 int stage, int j, double *red) {
+  __shared__ bool last;
+  unsigned int *cnt = reinterpret_cast<unsigned int *>(S + S_GS_COUNT);
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's partials before its count
+    last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // every other workgroup's partials are visible after its count
+  gs_finalize_block(partials, gridDim.x, S, stage, j, red);
+  if (threadIdx.x == 0) atomicExch(cnt, 0u);
+}
+
+// <basis_i, w> for i < NB (and <w, w> when SELF), basis vectors contiguous with stride nv.
+// partials[j * gridDim.x + block].  Does nothing when gate && *gate == 0.
+template <int NB, bool SELF>
+__global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict__ basis,
+                                                       const double *__restrict__ w, size_t nv,
+                                                       double *__restrict__ partials,
+                                                       const double *__restrict__ gate,
+                                                       double *__restrict__ S, int stage, int jj) {
+  if (gate && *gate == 0.0) return;
+  __shared__ double red[kThreads / 64];
+  constexpr int NS = NB + (SELF ? 1 : 0);
+  double acc[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) acc[j] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
+    if (SELF) acc[NS - 1] += wi * wi;
+  }
+  for (int j = 0; j < NS; ++j) {
+    const double r = block_sum(acc[j], red);
+    if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = r;
+  }
+  if (stage) finalize_if_last(partials, S, stage, jj, red);
+}
+
+// w += sign * sum_i scal[slot+i] basis_i  (optional partials of ||w||^2); gated like above
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
+                                                        const double *__restrict__ basis,
+                                                        size_t nv, const double *__restrict__ scal,
+                                                        int slot, double sign,
+                                                        double *__restrict__ partials,
+                                                        const double *__restrict__ gate,
+                                                        double *__restrict__ S, int stage,
+                                                        int jj) {
+  if (gate && *gate == 0.0) return;
+  __shared__ double red[kThreads / 64];
+  double c[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) c[j] = sign * scal[slot + j];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (size_t)gridDim.x * kThreads) {
+    double v = w[i];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v += c[j] * basis[(size_t)j * nv + i];
+    w[i] = v;
+    acc += v * v;
+  }
+  if (partials) {
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+    if (stage) finalize_if_last(partials, S, stage, jj, red);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gs_finalize(const double *__restrict__ partials,
+                                                          int count, double *__restrict__ S,
+                                                          int stage, int j) {
+  __shared__ double red[kThreads / 64];
+  gs_finalize_block(partials, count, S, stage, j, red);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(double *__restrict__ dst, double val,
@@ -630,8 +658,10 @@ hipError_t launch_minres_scalar(const wc_plan &p, int stage, int nparts, double 
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)  \
   X(32)
 
-hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
-                           bool self, const double *gate, int *nblocks, size_t len) {
+namespace {
+hipError_t multidot_fin(const wc_plan &p, const double *basis, int nb, const double *w,
+                        bool self, const double *gate, int *nblocks, size_t len, int stage,
+                        int jj) {
   const size_t nv = len ? len : p.nvec;
   const int g = red_blocks(nv);
   if (nblocks) *nblocks = g;
@@ -641,10 +671,10 @@ hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const 
   case K:                                                                                    \
     if (self)                                                                                \
       hipLaunchKernelGGL((k_multidot<K, true>), dim3(g), dim3(kThreads), 0, p.stream, basis, \
-                         w, nv, p.d_partials, gate);                                         \
+                         w, nv, p.d_partials, gate, p.d_scal, stage, jj);                    \
     else                                                                                     \
       hipLaunchKernelGGL((k_multidot<K, false>), dim3(g), dim3(kThreads), 0, p.stream,       \
-                         basis, w, nv, p.d_partials, gate);                                  \
+                         basis, w, nv, p.d_partials, gate, p.d_scal, stage, jj);             \
     break;
     WC_NB_CASES(CASE_NB)
 #undef CASE_NB
@@ -653,9 +683,9 @@ hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const 
   return hipGetLastError();
 }
 
-hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb, int slot,
-                            double sign, bool norm, const double *gate, int *nblocks,
-                            size_t len) {
+hipError_t multiaxpy_fin(const wc_plan &p, double *w, const double *basis, int nb, int slot,
+                         double sign, bool norm, const double *gate, int *nblocks, size_t len,
+                         int stage, int jj) {
   const size_t nv = len ? len : p.nvec;
   const int g = red_blocks(nv);
   if (nblocks) *nblocks = g;
@@ -665,13 +695,40 @@ hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, in
 #define CASE_NB(K)                                                                            \
   case K:                                                                                     \
     hipLaunchKernelGGL(k_multiaxpy<K>, dim3(g), dim3(kThreads), 0, p.stream, w, basis, nv,      \
-                       p.d_scal, slot, sign, parts, gate);                                    \
+                       p.d_scal, slot, sign, parts, gate, p.d_scal, stage, jj);               \
     break;
     WC_NB_CASES(CASE_NB)
 #undef CASE_NB
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_multidot(const wc_plan &p, const double *basis, int nb, const double *w,
+                           bool self, const double *gate, int *nblocks, size_t len) {
+  return multidot_fin(p, basis, nb, w, self, gate, nblocks, len, 0, 0);
+}
+
+hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, int nb, int slot,
+                            double sign, bool norm, const double *gate, int *nblocks,
+                            size_t len) {
+  return multiaxpy_fin(p, w, basis, nb, slot, sign, norm, gate, nblocks, len, 0, 0);
+}
+
+hipError_t launch_gram_schmidt(const wc_plan &p, const double *V, int j, double *Vn,
+                               size_t len) {
+  const double *gate = p.d_scal + S_REORTH;
+  hipError_t e;
+  if ((e = multidot_fin(p, V, j + 1, Vn, true, nullptr, nullptr, len, 1, j)) != hipSuccess)
+    return e;
+  if ((e = multiaxpy_fin(p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, nullptr, len, 2, j)) !=
+      hipSuccess)
+    return e;
+  if ((e = multidot_fin(p, V, j + 1, Vn, false, gate, nullptr, len, 3, j)) != hipSuccess)
+    return e;
+  return multiaxpy_fin(p, Vn, V, j + 1, S_GSC, -1.0, true, gate, nullptr, len, 4, j);
 }
 
 hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count) {

@@ -387,7 +387,13 @@ constexpr int kCuLds = 163840;
 constexpr int blocks_per_cu(int lds) { return lds > 0 ? kCuLds / lds : 0; }
 
 // Time FFT tile: TS spatial columns x N time levels (4 waves, TS/4 columns each).
-template <typename P, int N, int TS> struct TimeCfg {
+// Waves per workgroup (TS / WAVES columns each): the inverse transform runs 8 (its input
+// loads are complex, half as many per column; measured 12% faster than 4 at n = 256),
+// the forward transform 4 (8 gave no gain there).
+constexpr int kTimeWavesFwd = 4, kTimeWavesInv = 8;
+template <typename P, int N, int TS, int WV = kTimeWavesFwd> struct TimeCfg {
+  static constexpr int WAVES = TS < WV ? TS : WV;
+  static constexpr int NT = 64 * WAVES;
   static constexpr int CXB = 2 * (int)sizeof(P);
   static constexpr int PS = 4;
   static constexpr int PN = padded<PS>(N);
@@ -412,7 +418,12 @@ template <typename P, int N1> struct RowCfg {
 };
 
 // x2 pass tile: TX x1-columns of both block rows (4 waves, TX/4 columns each).
+// x2 pass: 4 waves per workgroup, TX / 4 columns (both block rows) each (8 waves measured
+// no faster in FP64 and 20% slower in FP32)
+constexpr int kColWaves = 4;
 template <typename P, int N1, int TX> struct ColCfg {
+  static constexpr int WAVES = TX < kColWaves ? TX : kColWaves;
+  static constexpr int NT = 64 * WAVES;
   static constexpr int CXB = 2 * (int)sizeof(P);
   static constexpr int PS = 4;
   static constexpr int PN = padded<PS>(N1);
@@ -423,6 +434,7 @@ template <typename P, int N1, int TX> struct ColCfg {
   static constexpr bool TAB_LDS = blocks_per_cu(TILE + TAB) == blocks_per_cu(TILE);
 };
 
+template <int NT = kThreads>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -432,7 +444,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   double r = 0.0;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < kThreads / 64; ++i) r += sh[i];
+    for (int i = 0; i < NT / 64; ++i) r += sh[i];
   }
   return r;
 }
@@ -473,19 +485,19 @@ __device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P
                                               const cx<P> *__restrict__ twg, int m, GenIn gi,
                                               int tile, cx<P> *buf, cx<P> *stw) {
   using C = TimeCfg<P, N, TS>;
-  constexpr int S = C::S, PS = C::PS;
+  constexpr int S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = tile * TS;
   const double *v1 = v;
   const double *v2 = v + (size_t)N * m;
   // all global loads of the tile are issued before any is consumed
-  constexpr int LIT = (N * TS + kThreads - 1) / kThreads;
+  constexpr int LIT = (N * TS + NT - 1) / NT;
   double ra[LIT], rb[LIT];
-  // generated input: this thread's column is fixed (kThreads is a multiple of TS), so its
+  // generated input: this thread's column is fixed (NT is a multiple of TS), so its
   // coefficients of the two range terms are formed once
   double gc = 0.0, a1 = 0.0, a2 = 0.0;
   if constexpr (GEN) {
-    static_assert(kThreads % TS == 0, "a thread's column must not change");
+    static_assert(NT % TS == 0, "a thread's column must not change");
     const int gs = s0 + tid % TS;
     gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
     if (gs < m) {
@@ -495,22 +507,22 @@ __device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P
   }
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
+    const int idx = tid + it * NT;
     const int k = idx / TS, s = idx % TS, gs = s0 + s;
     ra[it] = 0.0;
     rb[it] = 0.0;
-    if ((N * TS % kThreads == 0 || idx < N * TS) && gs < m) {
+    if ((N * TS % NT == 0 || idx < N * TS) && gs < m) {
       ra[it] = v1[(size_t)k * m + gs];
       rb[it] = v2[(size_t)k * m + gs];
     }
   }
   // twiddles are staged while the tile's loads are in flight
   if constexpr (TWL)
-    for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
+    for (int i = tid; i < N; i += NT) stw[i] = twg[i];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (N * TS % kThreads == 0 || idx < N * TS) {
+    const int idx = tid + it * NT;
+    if (N * TS % NT == 0 || idx < N * TS) {
       const int k = idx / TS, s = idx % TS;
       const cx<double> d = dtw[k];
       double a = ra[it], b = rb[it];
@@ -523,9 +535,9 @@ __device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, false, true>(buf + wv * (TS / 4), TWL ? stw : twg, lane);
+  wfft<P, N, 1, CPW, S, PS, false, true>(buf + wv * CPW, TWL ? stw : twg, lane);
   __syncthreads();
-  for (int idx = tid; idx < (N / 2) * TS; idx += kThreads) {
+  for (int idx = tid; idx < (N / 2) * TS; idx += NT) {
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
     if (gs >= m) continue;
     const cx<P> Zl = buf[pk<PS>(q + 1) * S + s];
@@ -537,7 +549,7 @@ __device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P
   }
 }
 template <typename P, int N, int TS, bool GEN>
-__global__ __launch_bounds__(kThreads) void k_tfft_fwd(const double *__restrict__ v,
+__global__ __launch_bounds__((TimeCfg<P, N, TS>::NT)) void k_tfft_fwd(const double *__restrict__ v,
                                                        cx<P> *__restrict__ W,
                                                        const cx<double> *__restrict__ dtw,
                                                        const cx<P> *__restrict__ twg, int m,
@@ -557,30 +569,30 @@ __device__ __forceinline__ void tfft_inv_tile(const cx<P> *__restrict__ W, doubl
                                               const double *__restrict__ dotv,
                                               double *__restrict__ partials, int tile, cx<P> *buf,
                                               cx<P> *stw, double *red) {
-  using C = TimeCfg<P, N, TS>;
-  constexpr int S = C::S, PS = C::PS;
+  using C = TimeCfg<P, N, TS, kTimeWavesInv>;
+  constexpr int S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int s0 = tile * TS;
   constexpr int HT = (N / 2) * TS;
-  constexpr int LIT = (HT + kThreads - 1) / kThreads;
+  constexpr int LIT = (HT + NT - 1) / NT;
   cx<P> ra[LIT], rb[LIT];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
+    const int idx = tid + it * NT;
     const int q = idx / TS, s = idx % TS, gs = s0 + s;
     ra[it] = cx<P>{(P)0, (P)0};
     rb[it] = cx<P>{(P)0, (P)0};
-    if ((HT % kThreads == 0 || idx < HT) && gs < m) {
+    if ((HT % NT == 0 || idx < HT) && gs < m) {
       ra[it] = W[((size_t)q * 2 + 0) * m + gs];
       rb[it] = W[((size_t)q * 2 + 1) * m + gs];
     }
   }
   if constexpr (TWL)
-    for (int i = tid; i < N; i += kThreads) stw[i] = twg[i];
+    for (int i = tid; i < N; i += NT) stw[i] = twg[i];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
-    if (HT % kThreads == 0 || idx < HT) {
+    const int idx = tid + it * NT;
+    if (HT % NT == 0 || idx < HT) {
       const int q = idx / TS, s = idx % TS;
       const cx<P> A = ra[it], Bv = rb[it];
       buf[pk<PS>(q + 1) * S + s] = cx<P>{A.x - Bv.y, A.y + Bv.x};              // A + iB
@@ -588,12 +600,12 @@ __device__ __forceinline__ void tfft_inv_tile(const cx<P> *__restrict__ W, doubl
     }
   }
   __syncthreads();
-  wfft<P, N, 1, TS / 4, S, PS, true, true>(buf + wv * (TS / 4), TWL ? stw : twg, lane);
+  wfft<P, N, 1, CPW, S, PS, true, true>(buf + wv * CPW, TWL ? stw : twg, lane);
   __syncthreads();
   double acc = 0.0;
   double *o1 = out;
   double *o2 = out + (size_t)N * m;
-  for (int idx = tid; idx < N * TS; idx += kThreads) {
+  for (int idx = tid; idx < N * TS; idx += NT) {
     const int k = idx / TS, s = idx % TS, gs = s0 + s;
     if (gs >= m) continue;
     const cx<P> z = buf[pk<PS>(k) * S + s];
@@ -607,22 +619,22 @@ __device__ __forceinline__ void tfft_inv_tile(const cx<P> *__restrict__ W, doubl
     if (dotv) acc += r1 * dotv[g] + r2 * dotv[(size_t)N * m + g];
   }
   if (dotv) {
-    const double r = block_sum(acc, red);
+    const double r = block_sum<NT>(acc, red);
     if (tid == 0) partials[tile] = r;
   }
 }
 
 template <typename P, int N, int TS>
-__global__ __launch_bounds__(kThreads) void k_tfft_inv(const cx<P> *__restrict__ W,
+__global__ __launch_bounds__((TimeCfg<P, N, TS, kTimeWavesInv>::NT)) void k_tfft_inv(const cx<P> *__restrict__ W,
                                                        double *__restrict__ out,
                                                        const cx<double> *__restrict__ dtw,
                                                        const cx<P> *__restrict__ twg, int m,
                                                        const double *__restrict__ dotv,
                                                        double *__restrict__ partials) {
-  using C = TimeCfg<P, N, TS>;
+  using C = TimeCfg<P, N, TS, kTimeWavesInv>;
   __shared__ cx<P> buf[C::PN * C::S];
   __shared__ cx<P> stw[C::TW_LDS ? N : 1];
-  __shared__ double red[kThreads / 64];
+  __shared__ double red[C::NT / 64];
   tfft_inv_tile<P, N, TS, C::TW_LDS>(W, out, dtw, twg, m, dotv, partials,
                                      xcd_tile(blockIdx.x, gridDim.x), buf, stw, red);
 }
@@ -820,7 +832,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
                                                P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
-  constexpr int CPW = TX / 4;  // columns per wave
+  constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ncx = (N1 - 2 + TX) / TX;  // column tiles per frequency, M = N1 - 1 columns
   const int q = t / ncx;
@@ -832,11 +844,11 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   // writes y_i, y_{N1-i} (all loads issued first).
   constexpr int TT = 2 * TX * M;
   constexpr int H = N1 / 2, TP = H * 2 * TX;
-  constexpr int LIT = (TP + kThreads - 1) / kThreads;
+  constexpr int LIT = (TP + NT - 1) / NT;
   cx<P> ra[LIT], rb[LIT];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
+    const int idx = tid + it * NT;
     const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX);
     ra[it] = cx<P>{(P)0, (P)0};
     rb[it] = cx<P>{(P)0, (P)0};
@@ -847,7 +859,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
     }
   }
   if constexpr (TABL) {
-    for (int i = tid; i < N1; i += kThreads) {
+    for (int i = tid; i < N1; i += NT) {
       stw[i] = twg[i];
       ssin[i] = sing[i];
     }
@@ -856,7 +868,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   const P *sn = TABL ? ssin : sing;
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * kThreads;
+    const int idx = tid + it * NT;
     if (idx >= TP) continue;
     const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX), col = 2 * c + h;
     const P sv = sn[i];
@@ -884,7 +896,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   wave_sync();
   wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
   __syncthreads();
-  for (int idx = tid; idx < TT; idx += kThreads) {
+  for (int idx = tid; idx < TT; idx += NT) {
     const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
     if (c0 + c < M)
       (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
@@ -892,7 +904,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
 }
 
 template <typename P, int N1, int TX>
-__global__ __launch_bounds__(kThreads) void k_cols_mode(cx<P> *__restrict__ W,
+__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode(cx<P> *__restrict__ W,
                                                         const cx<P> *__restrict__ twg,
                                                         const P *__restrict__ sing,
                                                         const cx<P> *__restrict__ lam,
@@ -986,14 +998,14 @@ hipError_t tfft_fwd_ts(const wc_plan &p, const double *v, const GenIn *gen) {
     ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
     if constexpr (std::is_same<P, double>::value) {
       if (gen) {
-        hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, true>), grid, dim3(kThreads), 0, p.stream, v,
+        hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, true>), grid, dim3(TimeCfg<P, N, TS>::NT), 0, p.stream, v,
                            (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
                            p.m, *gen);
         return hipGetLastError();
       }
     }
     if (gen) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, false>), grid, dim3(kThreads), 0, p.stream, v,
+    hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, false>), grid, dim3(TimeCfg<P, N, TS>::NT), 0, p.stream, v,
                        (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m,
                        GenIn{});
     return hipGetLastError();
@@ -1008,7 +1020,8 @@ hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *npa
     dim3 grid((p.m + TS - 1) / TS);
     *nparts = grid.x;
     ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
-    hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(kThreads), 0, p.stream,
+    hipLaunchKernelGGL((k_tfft_inv<P, N, TS>), grid, dim3(TimeCfg<P, N, TS, kTimeWavesInv>::NT), 0,
+                       p.stream,
                        (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
                        p.m, dotv, p.d_partials);
     return hipGetLastError();
@@ -1041,7 +1054,7 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c) {
     constexpr int M = N1 - 1;
     dim3 gc(((M + TX - 1) / TX) * (p.n / 2));
     ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(kThreads), 0, p.stream,
+    hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0, p.stream,
                        (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
                        Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
     return hipGetLastError();
@@ -1180,7 +1193,7 @@ __device__ __forceinline__ int batch_find(const BatchArgs &a, int t) {
 }
 
 template <typename P, bool TBL>
-__global__ __launch_bounds__(kThreads) void k_batch_tfft_fwd(const BatchInst *__restrict__ tab,
+__global__ __launch_bounds__(64 * kTimeWavesFwd) void k_batch_tfft_fwd(const BatchInst *__restrict__ tab,
                                                              BatchArgs a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
@@ -1205,7 +1218,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_tfft_fwd(const BatchInst *__
 }
 
 template <typename P, bool TBL>
-__global__ __launch_bounds__(kThreads) void k_batch_tfft_inv(const BatchInst *__restrict__ tab,
+__global__ __launch_bounds__(64 * kTimeWavesInv) void k_batch_tfft_inv(const BatchInst *__restrict__ tab,
                                                              BatchArgs a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
@@ -1220,6 +1233,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_tfft_inv(const BatchInst *__
   switch (I.n) {
 #define CASE_B(NN)                                                                             \
   case NN:                                                                                     \
+    static_assert(TimeCfg<P, NN, default_ts<P, NN>(), kTimeWavesInv>::NT ==                    \
+                  64 * kTimeWavesInv, "the launch has 64 * kTimeWavesInv threads");            \
     tfft_inv_tile<P, NN, default_ts<P, NN>(), TBL>(W, a.w[i], dtw, tw, I.m, nullptr,         \
                                                    nullptr, t - a.t0[i], buf, stw,         \
                                                    nullptr);                                   \
@@ -1266,7 +1281,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_rows(const BatchInst *__rest
 }
 
 template <typename P, bool TBL>
-__global__ __launch_bounds__(kThreads) void k_batch_cols(const BatchInst *__restrict__ tab,
+__global__ __launch_bounds__(64 * kColWaves) void k_batch_cols(const BatchInst *__restrict__ tab,
                                                          BatchArgs a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   cx<P> *buf = reinterpret_cast<cx<P> *>(dyn_lds);
@@ -1296,7 +1311,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_cols(const BatchInst *__rest
 
 // work units and LDS bytes of one instance in each pass
 template <typename P> struct BatchShape {
-  int time_units, time_lds, time_tab, row_units, row_slice, col_units, col_lds, space_tab;
+  int time_units, time_lds, time_tab, row_units, row_slice, col_units, col_lds, space_tab,
+      col_threads;
 };
 template <typename P> BatchShape<P> batch_shape(int n, int N1, int m) {
   BatchShape<P> b{};
@@ -1323,6 +1339,7 @@ template <typename P> BatchShape<P> batch_shape(int n, int N1, int m) {
     b.col_units = ((NN - 1 + TX - 1) / TX) * (n / 2);                                          \
     b.col_lds = ColCfg<P, NN, TX>::TILE;                                                       \
     b.space_tab = ColCfg<P, NN, TX>::TAB;                                                      \
+    b.col_threads = ColCfg<P, NN, TX>::NT;                                                     \
     break;                                                                                     \
   }
     WC_BATCH_CASES(CASE_B)
@@ -1350,10 +1367,10 @@ hipError_t allow_lds(const void *kernel, int lds) {
 
 template <typename K>
 hipError_t batch_launch(K kernel, int units, int lds, hipStream_t st, const BatchInst *tab,
-                        const BatchArgs &a) {
+                        const BatchArgs &a, int threads = kThreads) {
   if (lds > 65536 && allow_lds((const void *)kernel, lds) != hipSuccess)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kernel, dim3(std::max(1, units)), dim3(kThreads), (size_t)lds, st, tab, a);
+  hipLaunchKernelGGL(kernel, dim3(std::max(1, units)), dim3(threads), (size_t)lds, st, tab, a);
   return hipGetLastError();
 }
 
@@ -1404,12 +1421,13 @@ hipError_t time_pass(hipStream_t st, const BatchInst *d_tab, const BatchInst *h_
     BatchArgs a = batch_args<P>(h_tab, cnt, idx, v, w, true, key, &tl, &tt, &unused);
     const int tlt = with_tables(tl, tt, a);
     hipError_t e;
+    constexpr int NF = 64 * kTimeWavesFwd, NI = 64 * kTimeWavesInv;
     if (inverse)
-      e = tlt ? batch_launch(k_batch_tfft_inv<P, true>, a.t0[a.count], tlt, st, d_tab, a)
-              : batch_launch(k_batch_tfft_inv<P, false>, a.t0[a.count], tl, st, d_tab, a);
+      e = tlt ? batch_launch(k_batch_tfft_inv<P, true>, a.t0[a.count], tlt, st, d_tab, a, NI)
+              : batch_launch(k_batch_tfft_inv<P, false>, a.t0[a.count], tl, st, d_tab, a, NI);
     else
-      e = tlt ? batch_launch(k_batch_tfft_fwd<P, true>, a.t0[a.count], tlt, st, d_tab, a)
-              : batch_launch(k_batch_tfft_fwd<P, false>, a.t0[a.count], tl, st, d_tab, a);
+      e = tlt ? batch_launch(k_batch_tfft_fwd<P, true>, a.t0[a.count], tlt, st, d_tab, a, NF)
+              : batch_launch(k_batch_tfft_fwd<P, false>, a.t0[a.count], tl, st, d_tab, a, NF);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1424,13 +1442,16 @@ hipError_t space_pass(hipStream_t st, const BatchInst *d_tab, const BatchInst *h
     hipError_t e;
     if (cols) {
       // column tiles: recount the units (the list above holds the row units)
+      int NC = kThreads;  // the tile body's width for this M
       for (int k = 0; k < a.count; ++k) {
         const BatchInst &I = h_tab[a.inst[k]];
-        a.t0[k + 1] = a.t0[k] + batch_shape<P>(I.n, I.N1, I.m).col_units;
+        const BatchShape<P> b = batch_shape<P>(I.n, I.N1, I.m);
+        a.t0[k + 1] = a.t0[k] + b.col_units;
+        NC = b.col_threads;
       }
       const int clt = with_tables(cl, ct, a);
-      e = clt ? batch_launch(k_batch_cols<P, true>, a.t0[a.count], clt, st, d_tab, a)
-              : batch_launch(k_batch_cols<P, false>, a.t0[a.count], cl, st, d_tab, a);
+      e = clt ? batch_launch(k_batch_cols<P, true>, a.t0[a.count], clt, st, d_tab, a, NC)
+              : batch_launch(k_batch_cols<P, false>, a.t0[a.count], cl, st, d_tab, a, NC);
     } else {
       a.aux = rs * (kThreads / 64);  // the row passes always stage their tables
       const int rl = a.aux + ct;
