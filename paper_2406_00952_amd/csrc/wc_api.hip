@@ -134,6 +134,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g, r, rho, partials
     s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 4 * (size_t)pr->n +
                (size_t)kContractChunks * 2 * m) * sizeof(double);
+  if (op->lowrank && pr->dims == 2)  // spectrum of r0, rank-term spectra, a1 and a2
+    s.vecs += s.spec_bytes + (4 * (size_t)pr->n + 2 * m) * sizeof(double);
   s.mg = 0;
   if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
     const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
@@ -233,6 +235,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_mg_u2);
   dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat); dfree(p->d_lr_rho);
   dfree(p->d_lr_part);
+  dfree(p->d_lr_spec); dfree(p->d_lr_rank); dfree(p->d_lr_a);
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_mg_fn2);
@@ -424,6 +427,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
     if (lr) {  // compact coordinates of r0 (its range part and the rest)
       WC_TRY(launch_lr_setup(*p, R0, V));
+      if (p->d_lr_spec) WC_TRY(launch_lr_spectrum(*p, R0));
       WC_TRY(launch_dot(*p, V, V, S_NU2, len));
       WC_TRY(sync_read(p, S_NU2, 1));
       beta = std::sqrt(p->h_scal[S_NU2]);
@@ -682,7 +686,7 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   // low-rank GMRES: S_n - B_n = -omega g r^T with omega = e^{i zeta} = -1 (zeta = pi):
   // g = e_1 + (1 - theta) B_n e_1, r_k = q^{n-k} / (theta + omega (1 - theta) q^{n-1}),
   // q = -(1 - theta)/theta (k = 1..n; the wrap-around corners of S^(1), S^(2))
-  std::vector<double> gr, rho;
+  std::vector<double> gr, rho, rk;  // alive until the uploads below are synchronised
   p->lr_ok = false;
   if (p->opts.lowrank) {
     const double th = p->theta, q = -(1.0 - th) / th;
@@ -722,6 +726,40 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
       rho[n + 2 * q + 1] = ag.imag();
     }
     if (e == hipSuccess) e = upload(p->stream, &p->d_lr_rho, rho);
+    if (p->dims == 2) {
+      // spectra of the rank-one terms as the time transform stores them: with
+      // G_l = sum_k e^{i zeta k/n} g_k e^{-2 pi i k l/n} (R_l likewise with r), the input
+      // [g (x) a1; r (x) a2] packs to Z_l = G_l a1 + i R_l a2, and the kept frequency
+      // l = q + 1 with its partner -q stores A = (Z_{q+1} + conj Z_{-q})/2 and
+      // -i D, D = (Z_{q+1} - conj Z_{-q})/2; a1, a2 are real, so per half two complex
+      // factors multiply a1 and a2
+      using C = std::complex<double>;
+      std::vector<C> G(n), R(n);
+      for (int l = 0; l < n; ++l) {
+        C sg = 0.0, sr = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const C ph = std::polar(1.0, p->zeta * k / n - 2.0 * M_PI * (double)((long)k * l % n) / n);
+          sg += gr[k] * ph;
+          sr += gr[n + k] * ph;
+        }
+        G[l] = sg;
+        R[l] = sr;
+      }
+      const C I(0.0, 1.0);
+      rk.assign(4 * (size_t)n, 0.0);
+      for (int q = 0; q < n / 2; ++q) {
+        const int lp = q + 1, lm = (n - q) % n;
+        const C f[4] = {(G[lp] + std::conj(G[lm])) * 0.5,        // half A, times a1
+                        I * (R[lp] - std::conj(R[lm])) * 0.5,     // half A, times a2
+                        -I * (G[lp] - std::conj(G[lm])) * 0.5,    // half -iD, times a1
+                        (R[lp] + std::conj(R[lm])) * 0.5};        // half -iD, times a2
+        for (int t = 0; t < 4; ++t) {
+          rk[8 * (size_t)q + 2 * t] = f[t].real();
+          rk[8 * (size_t)q + 2 * t + 1] = f[t].imag();
+        }
+      }
+      if (e == hipSuccess) e = upload(p->stream, &p->d_lr_rank, rk);
+    }
   }
   std::vector<double> af;
   if (e == hipSuccess && prob->a_face_host) {
@@ -876,6 +914,10 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     alloc((void **)&p->d_lr_s0, 2 * (size_t)p->m * sizeof(double));
     alloc((void **)&p->d_lr_hat, (size_t)(opts->restart + 2) * p->lr_len * sizeof(double));
     alloc((void **)&p->d_lr_part, (size_t)kContractChunks * 2 * p->m * sizeof(double));
+    if (p->dims == 2) {  // (the rank-term spectra were uploaded with the tables)
+      alloc((void **)&p->d_lr_spec, sz.spec_bytes);
+      alloc((void **)&p->d_lr_a, 2 * (size_t)p->m * sizeof(double));
+    }
   }
   if (!oom && hipHostMalloc((void **)&p->h_scal, S_COUNT * sizeof(double), 0) != hipSuccess)
     oom = true;

@@ -762,6 +762,60 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
   }
 }
 
+// ---- 2D low-rank GMRES: the first x1 pass reads the spectrum of v = c r0 + [g (x) a1;
+// r (x) a2] without a time transform: the transform is linear and r0 fixed within a cycle,
+// so Vhat[q][h][s] = c R0hat[q][h][s] + F[q][h][0] a1[s] + F[q][h][1] a2[s] with F the
+// stored spectra of g and r (complex) and a1, a2 real.
+__global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, double *__restrict__ a, int m) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+  a[s] = gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s];
+  a[m + s] = gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s];
+}
+
+template <int N1>
+__global__ __launch_bounds__(kThreads) void k_dst_rows_lrgen(
+    const cx<double> *__restrict__ R0hat, cx<double> *__restrict__ W, int nlines,
+    const double *__restrict__ a, const cx<double> *__restrict__ F, GenIn gi,
+    const cx<double> *__restrict__ twg, const double *__restrict__ sing) {
+  using R = RowCfg<double, N1>;
+  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  __shared__ cx<double> lds[R::WPB][R::PN * S];
+  __shared__ cx<double> stw[N1];
+  __shared__ double ssin[N1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    stw[i] = twg[i];
+    ssin[i] = sing[i];
+  }
+  __syncthreads();
+  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+  const size_t m = (size_t)M * M;
+  cx<double> *buf = lds[wv];
+  const int ngroups = (nlines + B - 1) / B;
+  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
+    const int l0 = grp * B;
+    dst_pre_global<double, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
+      const int l = l0 + b;  // line (q, h, x2): l = (2q + h) M + x2
+      if (l >= nlines) return cx<double>{0.0, 0.0};
+      const int qh = l / M;
+      const size_t s = (size_t)(l - qh * M) * M + x;
+      const cx<double> r = R0hat[(size_t)l * M + x];
+      const cx<double> f1 = F[2 * qh], f2 = F[2 * qh + 1];
+      const double a1 = a[s], a2 = a[m + s];
+      return cx<double>{gc * r.x + f1.x * a1 + f2.x * a2, gc * r.y + f1.y * a1 + f2.y * a2};
+    });
+    wave_sync();
+    wdst_core<double, N1, B, S, PS>(buf, stw, lane);
+    for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
+      const int b = idx / M, x = idx % M;
+      if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
+    }
+    wave_sync();
+  }
+}
+
 // ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
 // W layout [q][half][x]; every wave owns UNITS frequencies (2*UNITS lines) at a time.
 template <typename P, int N1>
@@ -990,23 +1044,23 @@ template <typename P, int N1> constexpr int default_tx() {
 }
 
 template <typename P, int N, int TS>
-hipError_t tfft_fwd_ts(const wc_plan &p, const double *v, const GenIn *gen) {
+hipError_t tfft_fwd_ts(const wc_plan &p, const double *v, const GenIn *gen, cx<P> *out) {
   if constexpr (!TimeCfg<P, N, TS>::FITS) {
-    return tfft_fwd_ts<P, N, 4>(p, v, gen);
+    return tfft_fwd_ts<P, N, 4>(p, v, gen, out);
   } else {
     dim3 grid((p.m + TS - 1) / TS);
     ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
     if constexpr (std::is_same<P, double>::value) {
       if (gen) {
         hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, true>), grid, dim3(TimeCfg<P, N, TS>::NT), 0, p.stream, v,
-                           (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
+                           out, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p),
                            p.m, *gen);
         return hipGetLastError();
       }
     }
     if (gen) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tfft_fwd<P, N, TS, false>), grid, dim3(TimeCfg<P, N, TS>::NT), 0, p.stream, v,
-                       (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m,
+                       out, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m,
                        GenIn{});
     return hipGetLastError();
   }
@@ -1029,11 +1083,13 @@ hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *npa
 }
 
 template <typename P, int N>
-hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen) {
+hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen,
+                        cx<P> *out = nullptr) {
+  if (!out) out = (cx<P> *)p.d_specA;
   switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
-    case 4: return tfft_fwd_ts<P, N, 4>(p, v, gen);
-    case 8: return tfft_fwd_ts<P, N, 8>(p, v, gen);
-    default: return tfft_fwd_ts<P, N, 16>(p, v, gen);
+    case 4: return tfft_fwd_ts<P, N, 4>(p, v, gen, out);
+    case 8: return tfft_fwd_ts<P, N, 8>(p, v, gen, out);
+    default: return tfft_fwd_ts<P, N, 16>(p, v, gen, out);
   }
 }
 
@@ -1062,7 +1118,7 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c) {
 }
 
 template <typename P, int N1>
-hipError_t run_space(const wc_plan &p, const ContractOut *co) {
+hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_gen = nullptr) {
   using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
@@ -1084,8 +1140,20 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co) {
   hipError_t e;
   {
     ProfScope ps(p, K_DST_X1_FWD, bytes);
-    hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
-                       p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
+    if constexpr (std::is_same<P, double>::value) {
+      if (rows_gen) {
+        hipLaunchKernelGGL((k_dst_rows_lrgen<N1>), gr, dim3(64 * R::WPB), 0, p.stream,
+                           (const cx<double> *)p.d_lr_spec, W, nlines, p.d_lr_a,
+                           (const cx<double> *)p.d_lr_rank, *rows_gen, Tabs<P>::tws(p),
+                           Tabs<P>::sin(p));
+      } else {
+        hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
+                           p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
+      }
+    } else {
+      hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
+                         p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
+    }
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
@@ -1117,18 +1185,27 @@ template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
   hipError_t e = hipErrorInvalidValue;
-  switch (p.n) {
+  // 2D low-rank Arnoldi step: the spectrum comes from the cycle's transformed r0
+  const bool hoist = std::is_same<P, double>::value && gen && co && p.dims == 2 && p.d_lr_spec;
+  if (hoist) {
+    ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
+    hipLaunchKernelGGL(k_lr_coef, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       p.stream, *gen, p.d_lr_a, p.m);
+    e = hipGetLastError();
+  } else {
+    switch (p.n) {
 #define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, v, gen); break;
-    WC_POW2_CASES(CASE_N)
+      WC_POW2_CASES(CASE_N)
 #undef CASE_N
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   if (p.var_coeff) {
     e = mg_space_apply(p);
   } else {
     switch (p.N1) {
-#define CASE_S(NN) case NN: e = run_space<P, NN>(p, co); break;
+#define CASE_S(NN) case NN: e = run_space<P, NN>(p, co, hoist ? gen : nullptr); break;
       WC_POW2_CASES(CASE_S)
 #undef CASE_S
       default: return hipErrorInvalidValue;
@@ -1516,6 +1593,17 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
   ContractOut co{hat_out, -p.lr_gn, -p.lr_rn, p.d_lr_rho, p.d_lr_part};  // omega = e^{i pi} = -1
   int np = 0;
   return pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
+}
+
+hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
+  if (!p.d_lr_spec || p.opts.precision != WC_FP64) return hipErrorInvalidValue;
+  switch (p.n) {
+#define CASE_N(NN) \
+  case NN: return run_tfft_fwd<double, NN>(p, r0, nullptr, (cx<double> *)p.d_lr_spec);
+    WC_POW2_CASES(CASE_N)
+#undef CASE_N
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int pc_partials_needed(int n, int m, int precision) {
