@@ -765,7 +765,8 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
 // ---- 2D low-rank GMRES: the first x1 pass reads the spectrum of v = c r0 + [g (x) a1;
 // r (x) a2] without a time transform: the transform is linear and r0 fixed within a cycle,
 // so Vhat[q][h][s] = c R0hat[q][h][s] + F[q][h][0] a1[s] + F[q][h][1] a2[s] with F the
-// stored spectra of g and r (complex) and a1, a2 real.
+// stored spectra of g and r (complex) and a1, a2 real.  (a1, a2 come from a small kernel:
+// forming them inside the loads from the compact coordinates made this pass 25% slower.)
 __global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, double *__restrict__ a, int m) {
   const int s = blockIdx.x * kThreads + threadIdx.x;
   if (s >= m) return;
@@ -1185,8 +1186,9 @@ template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
   hipError_t e = hipErrorInvalidValue;
-  // 2D low-rank Arnoldi step: the spectrum comes from the cycle's transformed r0
-  const bool hoist = std::is_same<P, double>::value && gen && co && p.dims == 2 && p.d_lr_spec;
+  // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
+  // cycle's transformed r0, in the first sine pass
+  const bool hoist = std::is_same<P, double>::value && gen && p.dims == 2 && p.d_lr_spec;
   if (hoist) {
     ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
     hipLaunchKernelGGL(k_lr_coef, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
