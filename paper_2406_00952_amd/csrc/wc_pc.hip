@@ -762,6 +762,8 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
   }
 }
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
 // ---- 2D low-rank GMRES: the first x1 pass reads the spectrum of v = c r0 + [g (x) a1;
 // r (x) a2] without a time transform: the transform is linear and r0 fixed within a cycle,
 // so Vhat[q][h][s] = c R0hat[q][h][s] + F[q][h][0] a1[s] + F[q][h][1] a2[s] with F the
@@ -802,7 +804,11 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_lrgen(
       if (l >= nlines) return cx<double>{0.0, 0.0};
       const int qh = l / M;
       const size_t s = (size_t)(l - qh * M) * M + x;
-      const cx<double> r = R0hat[(size_t)l * M + x];
+      // streamed past the caches: the spectral array this pass writes should stay in the
+      // memory-side cache for the x2 pass (measured: x2 pass 200 -> 174 us)
+      const d2 rv =
+          __builtin_nontemporal_load(reinterpret_cast<const d2 *>(R0hat + (size_t)l * M + x));
+      const cx<double> r = {rv.x, rv.y};
       const cx<double> f1 = F[2 * qh], f2 = F[2 * qh + 1];
       const double a1 = a[s], a2 = a[m + s];
       return cx<double>{gc * r.x + f1.x * a1 + f2.x * a2, gc * r.y + f1.y * a1 + f2.y * a2};
