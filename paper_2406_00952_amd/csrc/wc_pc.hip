@@ -512,8 +512,16 @@ __device__ __forceinline__ void tfft_fwd_tile(const double *__restrict__ v, cx<P
     ra[it] = 0.0;
     rb[it] = 0.0;
     if ((N * TS % NT == 0 || idx < N * TS) && gs < m) {
-      ra[it] = v1[(size_t)k * m + gs];
-      rb[it] = v2[(size_t)k * m + gs];
+      if constexpr (std::is_same<P, double>::value) {
+        // FP64: the input is streamed past the caches, the spectral array this pass writes
+        // (as large as the memory-side cache) keeps it (measured 159 -> 147 us at n = 256,
+        // M = 255; in FP32 the whole spectral array fits and streaming the input loses)
+        ra[it] = __builtin_nontemporal_load(v1 + (size_t)k * m + gs);
+        rb[it] = __builtin_nontemporal_load(v2 + (size_t)k * m + gs);
+      } else {
+        ra[it] = v1[(size_t)k * m + gs];
+        rb[it] = v2[(size_t)k * m + gs];
+      }
     }
   }
   // twiddles are staged while the tile's loads are in flight
