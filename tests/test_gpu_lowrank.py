@@ -106,3 +106,37 @@ def test_lowrank_rejects_other_methods(env):
         wc.Plan(2, 31, 32, method="minres_abs_ps", lowrank=True)
     with pytest.raises(wc.WcError):
         wc.Plan(2, 31, 32, method="gmres_ps", precision="mixed", lowrank=True)
+
+
+def test_full_size_solve_in_bench_configuration(env):
+    """The 2D Crank-Nicolson workload (M = 255, n = 256, gamma = 1e-4, seed 0) solved as
+    bench.py times it (low-rank GMRES(30)-P_S, autotuned tiles, captured iterations): the
+    right-hand side equals the oracle's, the oracle's operator confirms the true relative
+    residual, and the iteration count is within 2 of the oracle's own GMRES(30)-P_S."""
+    torch, wc = env
+    from oracle.discretization import rhs_tilde, transformed_rhs
+    dims, M, n = 2, 255, 256
+    print("full-size solve", dims, M, n, flush=True)
+    d = datagen.config_problem(dims, M, n, seed=0, noise_sigma=1e-3)
+    pr = Problem(dims=dims, M=M, n=n, theta=0.5, gamma=1e-4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    f, g, y0 = dev(d["f"]), dev(d["g"]), dev(d["y0"])
+    plan = wc.Plan(dims, M, n, theta=0.5, gamma=1e-4, method="gmres_ps", tol=1e-8, maxit=500,
+                   lowrank=True, graphs=True)
+    plan.autotune(reps=2)
+    x = torch.empty(2 * n * pr.m, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    plan.rhs(f, g, y0, b)
+    for _ in range(2):  # the second solve replays the captured iterations
+        info = plan.krylov(b, x)
+    xs = x.cpu().numpy()
+    gt, ft = rhs_tilde(pr, d["f"], d["g"], d["y0"])
+    bref = transformed_rhs(pr, gt, ft, False)
+    assert np.abs(b.cpu().numpy() - bref).max() <= 1e-13 * np.abs(bref).max()
+    res = np.linalg.norm(bref - AllAtOnce(pr).Ahat(xs)) / np.linalg.norm(bref)
+    print("  gpu iters", info.iters, "relres", info.relres, "oracle-operator relres", res,
+          flush=True)
+    assert info.relres <= 1e-8 and res <= 1.05e-8
+    ref = osolver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps", tol=1e-8, restart=30)
+    print("  oracle iters", ref["iters"], flush=True)
+    assert abs(info.iters - ref["iters"]) <= 2
