@@ -197,20 +197,39 @@ __global__ __launch_bounds__(kThreads) void k_recover(const double *__restrict__
   if (s >= m) return;
   const size_t nm = (size_t)n * m;
   const double omt = 1.0 - theta, ith = 1.0 / theta;
+  // the loads of KB time levels are issued before the recurrence consumes them
+  constexpr int KB = 8;
   if (blockIdx.y == 0) {
     double prev = 0.0;
-    for (int k = 0; k < n; ++k) {
-      const double v = (x[(size_t)k * m + s] * inv_sqrt_gamma - omt * prev) * ith;
-      y[(size_t)k * m + s] = v;
-      prev = v;
+    for (int k0 = 0; k0 < n; k0 += KB) {
+      double xv[KB];
+#pragma unroll
+      for (int u2 = 0; u2 < KB; ++u2)
+        xv[u2] = k0 + u2 < n ? x[(size_t)(k0 + u2) * m + s] : 0.0;
+#pragma unroll
+      for (int u2 = 0; u2 < KB; ++u2) {
+        if (k0 + u2 >= n) break;
+        const double v = (xv[u2] * inv_sqrt_gamma - omt * prev) * ith;
+        y[(size_t)(k0 + u2) * m + s] = v;
+        prev = v;
+      }
     }
   } else {
     double next = 0.0;
-    for (int k = n - 1; k >= 0; --k) {
-      const double v = (x[nm + (size_t)k * m + s] - omt * next) * ith;
-      p[(size_t)k * m + s] = v;
-      if (u) u[(size_t)k * m + s] = v * inv_gamma;
-      next = v;
+    for (int k0 = n - 1; k0 >= 0; k0 -= KB) {
+      double xv[KB];
+#pragma unroll
+      for (int u2 = 0; u2 < KB; ++u2)
+        xv[u2] = k0 - u2 >= 0 ? x[nm + (size_t)(k0 - u2) * m + s] : 0.0;
+#pragma unroll
+      for (int u2 = 0; u2 < KB; ++u2) {
+        const int k = k0 - u2;
+        if (k < 0) break;
+        const double v = (xv[u2] - omt * next) * ith;
+        p[(size_t)k * m + s] = v;
+        if (u) u[(size_t)k * m + s] = v * inv_gamma;
+        next = v;
+      }
     }
   }
 }

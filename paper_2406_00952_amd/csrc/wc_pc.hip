@@ -255,7 +255,7 @@ template <typename T, int N1, int B, int S, int PS>
 __device__ __forceinline__ void wdst_core(cx<T> *buf, const cx<T> *__restrict__ tw, int lane) {
   constexpr int H = N1 / 2;
   constexpr int ITEMS = H * B;
-  wfft<T, N1, 1, B, S, PS, false>(buf, tw, lane);
+  wfft<T, N1, 1, B, S, PS, false, true>(buf, tw, lane);
   // post-processing: every lane owns CH consecutive k of one line; the running sum is a
   // sequential scan inside the chunk plus a shuffle scan of the chunk totals.
   constexpr int CH = ITEMS >= 64 ? ITEMS / 64 : 1;
@@ -315,7 +315,7 @@ __device__ __forceinline__ void wdst_regs(cx<T> *buf, const cx<T> *__restrict__ 
                                           bool &valid) {
   using L = DstLanes<T, N1, B>;
   constexpr int CH = L::CH, G = L::G;
-  wfft<T, N1, 1, B, S, PS, false>(buf, tw, lane);
+  wfft<T, N1, 1, B, S, PS, false, true>(buf, tw, lane);
   b = lane / G;
   const int g = lane % G;
   k0 = g * CH;
