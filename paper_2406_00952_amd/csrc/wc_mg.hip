@@ -214,9 +214,10 @@ __global__ __launch_bounds__(kThreads) void k_mg_smooth(cx<P> *__restrict__ u,
   const int M = L.M, half = (M + 1) / 2, rows = D == 2 ? M : 1;
   const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= (size_t)nsys * rows * half) return;
-  const int t = (int)(idx % half);
-  const size_t r = idx / half;
-  const int j = (int)(r % rows), sys = (int)(r / rows);
+  // index arithmetic in 32 bits (every level holds fewer than 2^32 points)
+  const unsigned ui = (unsigned)idx, r = ui / (unsigned)half;
+  const int t = (int)(ui - r * (unsigned)half);
+  const int j = (int)(r % (unsigned)rows), sys = (int)(r / (unsigned)rows);
   const int i = color_i<D>(t, j, color);
   if (i >= M) return;
   const size_t np = (size_t)rows * M;
@@ -237,8 +238,9 @@ __global__ __launch_bounds__(kThreads) void k_mg_restrict(const cx<P> *__restric
   const size_t npc = (size_t)rows * Mc, np = (size_t)(D == 2 ? M : 1) * M;
   const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= (size_t)nsys * npc) return;
-  const int sys = (int)(idx / npc);
-  const int o = (int)(idx % npc), I = o % Mc, J = o / Mc;
+  const unsigned ui = (unsigned)idx, un = (unsigned)npc;  // 32-bit index arithmetic
+  const int sys = (int)(ui / un);
+  const int o = (int)(ui - (unsigned)sys * un), I = o % Mc, J = o / Mc;
   fc[idx] = restrict_val<P, D>(u + sys * np, f + sys * np, L, sys_shift(shifts, sys), tau, I, J);
 }
 
@@ -333,7 +335,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_mix(const cx<P> *__restrict__ s
                                                      int nq, double inv_n, int out) {
   const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= (size_t)nq * m) return;
-  const int q = (int)(idx / m), s = (int)(idx % m);
+  const unsigned ui = (unsigned)idx;  // 32-bit index arithmetic
+  const int q = (int)(ui / (unsigned)m), s = (int)(ui - (unsigned)q * (unsigned)m);
   const size_t o0 = ((size_t)q * 2) * m + s, o1 = o0 + m;
   const cx<P> x0 = src[o0], x1 = src[o1];
   if (!mix) {

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const double *__restrict__ f,
   const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
   const size_t nm = (size_t)a.n * a.m;
   if (idx >= nm) return;
-  const int k = (int)(idx / a.m), s = (int)(idx % a.m);
+  const unsigned ui = (unsigned)idx;  // n m < 2^32
+  const int k = (int)(ui / (unsigned)a.m), s = (int)(ui - (unsigned)k * (unsigned)a.m);
   const double th = a.theta, omt = 1.0 - th;
   double ft = a.tau * (th * f[(size_t)(k + 1) * a.m + s] + omt * f[(size_t)k * a.m + s]);
   double gt = a.tau * (th * g[(size_t)k * a.m + s] + omt * g[(size_t)(k + 1) * a.m + s]);
@@ -544,7 +545,8 @@ __global__ __launch_bounds__(kThreads) void k_lr_perp(const double *__restrict__
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nm;
        i += (size_t)gridDim.x * kThreads) {
-    const int k = (int)(i / m), s = (int)(i % m);
+    const unsigned ui = (unsigned)i;  // n m < 2^32
+    const int k = (int)(ui / (unsigned)m), s = (int)(ui - (unsigned)k * (unsigned)m);
     const double d1 = r0[i] - gr[k] * s0[s];
     const double d2 = r0[nm + i] - gr[n + k] * s0[m + s];
     acc += d1 * d1 + d2 * d2;
