@@ -284,7 +284,8 @@ def serve(args):
 
 def main():
     args = parse()
-    if args.method != "gmres_ps" or args.precision != "fp64" or args.coeff != "const":
+    if (args.method != "gmres_ps" or args.coeff != "const"
+            or (args.precision != "fp64" and args.dims != 2)):
         args.lowrank = 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no "

@@ -60,7 +60,10 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   if (!(op->tol > 0) || op->maxit < 1) return WC_E_ARG;
   if (op->method == WC_GMRES_PS && (op->restart < 1 || op->restart > kMaxRestart)) return WC_E_ARG;
   if (op->method == WC_MINRES_ABS_PS && pr->a_face_host) return WC_E_ARG;  // |P_S| needs a == 1
-  if (op->lowrank && (op->method != WC_GMRES_PS || op->precision != WC_FP64 || pr->a_face_host))
+  // low-rank GMRES: a == 1; the FP32 preconditioner (restarts on the FP64 true residual
+  // correct what FP32 leaves, like iterative refinement) in 2D only
+  if (op->lowrank && (op->method != WC_GMRES_PS || pr->a_face_host ||
+                      (op->precision == WC_MIXED && pr->dims != 2)))
     return WC_E_ARG;
   const double m = std::pow((double)pr->M, pr->dims);
   if (m * pr->n * 2.0 > 4.0e9) return WC_E_ARG;  // 32-bit spatial indexing inside kernels
@@ -425,6 +428,11 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     if (!std::isfinite(relres)) { st = WC_E_NONFINITE; break; }
     if (relres <= tol) { st = WC_OK; break; }
     if (total >= p->opts.maxit) { st = WC_E_MAXIT; break; }
+    // low-rank form with the FP32 preconditioner: a cycle cannot take the true residual
+    // much below the FP32 level of its start, so it stops there and the next cycle
+    // restarts from the FP64 true residual (iterative refinement)
+    const double cycle_tol =
+        lr && p->opts.precision == WC_MIXED ? std::max(tol, kMixedCycleDrop * relres) : tol;
     if (lr) {  // compact coordinates of r0 (its range part and the rest)
       WC_TRY(launch_lr_setup(*p, R0, V));
       if (p->d_lr_spec) WC_TRY(launch_lr_spectrum(*p, R0));
@@ -487,7 +495,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       jd = j + 1;
       relres_est = std::fabs(g[j + 1]) / bnorm;
       if (!std::isfinite(relres_est) || r == 0.0) { stop = true; break; }
-      if (relres_est <= tol || hn == 0.0 || total >= p->opts.maxit) stop = true;
+      if (relres_est <= cycle_tol || hn == 0.0 || total >= p->opts.maxit) stop = true;
     }
     // back substitution R y = g; the update uses the unnormalised vectors, so y_i / nu_i
     for (int i = jd - 1; i >= 0; --i) {

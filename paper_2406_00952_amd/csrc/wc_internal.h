@@ -26,6 +26,9 @@ constexpr int kMaxRestart = 32;
 // the drop reflects the convergence rate, not the preconditioner's quality; a
 // hundredfold drop in norm costs about two digits of orthogonality.
 constexpr double kReorthEta2 = 1e-4;
+// Low-rank GMRES with the FP32 preconditioner: relative reduction a restart cycle aims for
+// (about twenty FP32 unit roundoffs: below it the FP32 apply's own error dominates)
+constexpr double kMixedCycleDrop = 1e-6;
 // multigrid (variable a): LDS budget of the single-workgroup coarse cycle, capacity of
 // the per-system norm partials, and the floor of the cycle tolerance in FP32
 constexpr size_t kMgLdsBytes = 60 * 1024;

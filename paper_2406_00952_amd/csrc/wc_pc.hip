@@ -693,28 +693,29 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
 // consecutive frequencies at a time and accumulates sum_q 2 Re(rho_h[q] Y_q[x1]) in the
 // registers that hold its outputs, so the spectrum is not written back:
 // part[c][h m + x2 M + x1].
-template <int N1>
-__global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double> *__restrict__ W,
+template <typename P, int N1>
+__global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<P> *__restrict__ W,
                                                                 int nq, ContractOut co,
-                                                                const cx<double> *__restrict__ twg,
-                                                                const double *__restrict__ sing) {
-  using R = RowCfg<double, N1>;
+                                                                const cx<P> *__restrict__ twg,
+                                                                const P *__restrict__ sing) {
+  // transforms in P (FP64, or FP32 for the mixed form), sums over frequencies in FP64
+  using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
-  __shared__ cx<double> lds[R::WPB][R::PN * S];
-  __shared__ cx<double> stw[N1];
-  __shared__ double ssin[N1];
+  __shared__ cx<P> lds[R::WPB][R::PN * S];
+  __shared__ cx<P> stw[N1];
+  __shared__ P ssin[N1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     stw[i] = twg[i];
     ssin[i] = sing[i];
   }
   __syncthreads();
-  cx<double> *buf = lds[wv];
+  cx<P> *buf = lds[wv];
   const size_t m = (size_t)M * M;
   const int per = (nq + kContractChunks - 1) / kContractChunks;
   const int ntasks = kContractChunks * 2 * M;
   const cx<double> *rho = reinterpret_cast<const cx<double> *>(co.rho);
-  using L = DstLanes<double, N1, B>;
+  using L = DstLanes<P, N1, B>;
   for (int task = blockIdx.x * R::WPB + wv; task < ntasks; task += gridDim.x * R::WPB) {
     const int c = task / (2 * M), rem = task % (2 * M), h = rem / M, x2 = rem % M;
     const int q0 = c * per, q1 = q0 + per < nq ? q0 + per : nq;
@@ -726,19 +727,19 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
     int b = 0, k0 = 0;
     bool valid = false;
     for (int qb = q0; qb < q1; qb += B) {
-      dst_pre_global<double, N1, B, S, PS>(buf, ssin, lane, [&](int bb, int x) {
+      dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int bb, int x) {
         return qb + bb < q1 ? W[((size_t)(qb + bb) * 2 + h) * m + (size_t)x2 * M + x]
-                            : cx<double>{0.0, 0.0};
+                            : cx<P>{(P)0, (P)0};
       });
       wave_sync();
-      cx<double> odd[L::CH], even[L::CH];
-      wdst_regs<double, N1, B, S, PS>(buf, stw, lane, odd, even, b, k0, valid);
+      cx<P> odd[L::CH], even[L::CH];
+      wdst_regs<P, N1, B, S, PS>(buf, stw, lane, odd, even, b, k0, valid);
       if (valid && qb + b < q1) {
         const cx<double> u = rh[qb + b];
 #pragma unroll
         for (int cc = 0; cc < L::CH; ++cc) {
-          aodd[cc] += 2.0 * (u.x * odd[cc].x - u.y * odd[cc].y);
-          aeven[cc] += 2.0 * (u.x * even[cc].x - u.y * even[cc].y);
+          aodd[cc] += 2.0 * (u.x * (double)odd[cc].x - u.y * (double)odd[cc].y);
+          aeven[cc] += 2.0 * (u.x * (double)even[cc].x - u.y * (double)even[cc].y);
         }
       }
       wave_sync();
@@ -770,7 +771,17 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<double>
   }
 }
 
-typedef double d2 __attribute__((ext_vector_type(2)));
+// one complex value loaded past the caches (non-temporal)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cx<double> load_stream(const cx<double> *p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> load_stream(const cx<float> *p) {
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+  return {v.x, v.y};
+}
 
 // ---- 2D low-rank GMRES: the first x1 pass reads the spectrum of v = c r0 + [g (x) a1;
 // r (x) a2] without a time transform: the transform is linear and r0 fixed within a cycle,
@@ -785,16 +796,16 @@ __global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, double *__restri
   a[m + s] = gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s];
 }
 
-template <int N1>
+template <typename P, int N1>
 __global__ __launch_bounds__(kThreads) void k_dst_rows_lrgen(
-    const cx<double> *__restrict__ R0hat, cx<double> *__restrict__ W, int nlines,
+    const cx<P> *__restrict__ R0hat, cx<P> *__restrict__ W, int nlines,
     const double *__restrict__ a, const cx<double> *__restrict__ F, GenIn gi,
-    const cx<double> *__restrict__ twg, const double *__restrict__ sing) {
-  using R = RowCfg<double, N1>;
+    const cx<P> *__restrict__ twg, const P *__restrict__ sing) {
+  using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
-  __shared__ cx<double> lds[R::WPB][R::PN * S];
-  __shared__ cx<double> stw[N1];
-  __shared__ double ssin[N1];
+  __shared__ cx<P> lds[R::WPB][R::PN * S];
+  __shared__ cx<P> stw[N1];
+  __shared__ P ssin[N1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     stw[i] = twg[i];
@@ -803,26 +814,24 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_lrgen(
   __syncthreads();
   const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
   const size_t m = (size_t)M * M;
-  cx<double> *buf = lds[wv];
+  cx<P> *buf = lds[wv];
   const int ngroups = (nlines + B - 1) / B;
   for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
     const int l0 = grp * B;
-    dst_pre_global<double, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
+    dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
       const int l = l0 + b;  // line (q, h, x2): l = (2q + h) M + x2
-      if (l >= nlines) return cx<double>{0.0, 0.0};
+      if (l >= nlines) return cx<P>{(P)0, (P)0};
       const int qh = l / M;
       const size_t s = (size_t)(l - qh * M) * M + x;
       // streamed past the caches: the spectral array this pass writes should stay in the
       // memory-side cache for the x2 pass (measured: x2 pass 200 -> 174 us)
-      const d2 rv =
-          __builtin_nontemporal_load(reinterpret_cast<const d2 *>(R0hat + (size_t)l * M + x));
-      const cx<double> r = {rv.x, rv.y};
+      const cx<P> r = load_stream(R0hat + (size_t)l * M + x);
       const cx<double> f1 = F[2 * qh], f2 = F[2 * qh + 1];
       const double a1 = a[s], a2 = a[m + s];
-      return cx<double>{gc * r.x + f1.x * a1 + f2.x * a2, gc * r.y + f1.y * a1 + f2.y * a2};
+      return cx<P>{(P)(gc * r.x + f1.x * a1 + f2.x * a2), (P)(gc * r.y + f1.y * a1 + f2.y * a2)};
     });
     wave_sync();
-    wdst_core<double, N1, B, S, PS>(buf, stw, lane);
+    wdst_core<P, N1, B, S, PS>(buf, stw, lane);
     for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
       const int b = idx / M, x = idx % M;
       if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
@@ -1155,16 +1164,11 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
   hipError_t e;
   {
     ProfScope ps(p, K_DST_X1_FWD, bytes);
-    if constexpr (std::is_same<P, double>::value) {
-      if (rows_gen) {
-        hipLaunchKernelGGL((k_dst_rows_lrgen<N1>), gr, dim3(64 * R::WPB), 0, p.stream,
-                           (const cx<double> *)p.d_lr_spec, W, nlines, p.d_lr_a,
-                           (const cx<double> *)p.d_lr_rank, *rows_gen, Tabs<P>::tws(p),
-                           Tabs<P>::sin(p));
-      } else {
-        hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
-                           p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
-      }
+    if (rows_gen) {
+      hipLaunchKernelGGL((k_dst_rows_lrgen<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
+                         (const cx<P> *)p.d_lr_spec, W, nlines, p.d_lr_a,
+                         (const cx<double> *)p.d_lr_rank, *rows_gen, Tabs<P>::tws(p),
+                         Tabs<P>::sin(p));
     } else {
       hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
                          p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
@@ -1178,15 +1182,13 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
     default: e = cols_tx<P, N1, 8>(p, kind, c); break;
   }
   if (e != hipSuccess) return e;
-  if constexpr (std::is_same<P, double>::value) {
-    if (co) {  // low-rank GMRES: the last pass contracts over time instead of writing back
-      const int ntasks = kContractChunks * 2 * M;
-      dim3 gt(row_grid(ntasks, R::WPB));
-      ProfScope ps(p, K_DST_X1_INV, bytes / 2 + 16.0 * kContractChunks * p.m);
-      hipLaunchKernelGGL((k_dst_rows_contract<N1>), gt, dim3(64 * R::WPB), 0, p.stream,
-                         (const cx<double> *)W, p.n / 2, *co, Tabs<P>::tws(p), Tabs<P>::sin(p));
-      return hipGetLastError();
-    }
+  if (co) {  // low-rank GMRES: the last pass contracts over time instead of writing back
+    const int ntasks = kContractChunks * 2 * M;
+    dim3 gt(row_grid(ntasks, R::WPB));
+    ProfScope ps(p, K_DST_X1_INV, bytes / 2 + 16.0 * kContractChunks * p.m);
+    hipLaunchKernelGGL((k_dst_rows_contract<P, N1>), gt, dim3(64 * R::WPB), 0, p.stream,
+                       (const cx<P> *)W, p.n / 2, *co, Tabs<P>::tws(p), Tabs<P>::sin(p));
+    return hipGetLastError();
   }
   ProfScope ps(p, K_DST_X1_INV, bytes);
   hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
@@ -1202,7 +1204,7 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   hipError_t e = hipErrorInvalidValue;
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
-  const bool hoist = std::is_same<P, double>::value && gen && p.dims == 2 && p.d_lr_spec;
+  const bool hoist = gen && p.dims == 2 && p.d_lr_spec;
   if (hoist) {
     ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
     hipLaunchKernelGGL(k_lr_coef, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
@@ -1228,10 +1230,12 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
     }
   }
   if (e != hipSuccess) return e;
-  if constexpr (std::is_same<P, double>::value) {
-    if (co) {  // low-rank GMRES: contract over time on the spectrum
-      const int nq = p.n / 2;
-      if (p.dims == 1) {  // 2D: the inverse x1 pass already contracted
+  if (co) {  // low-rank GMRES: contract over time on the spectrum
+    const int nq = p.n / 2;
+    if (p.dims == 1) {  // 2D: the inverse x1 pass already contracted
+      if constexpr (!std::is_same<P, double>::value) {
+        return hipErrorInvalidValue;  // the 1D low-rank form is FP64 only
+      } else {
         ProfScope ps(p, K_CONTRACT, (double)p.n * p.m * sizeof(cx<double>) +
                                         16.0 * kContractChunks * p.m);
         hipLaunchKernelGGL(k_contract_freq, dim3((p.m + kThreads - 1) / kThreads, kContractChunks),
@@ -1239,12 +1243,12 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
                            nq);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
-      ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
-      hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                         p.stream, *co, p.m);
-      *nparts = 0;
-      return hipGetLastError();
     }
+    ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
+    hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       p.stream, *co, p.m);
+    *nparts = 0;
+    return hipGetLastError();
   }
   switch (p.n) {
 #define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts); break;
@@ -1263,9 +1267,9 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
 // sizes.  Instances of every grid M share a time-pass launch when their n is the same,
 // and instances of every n share a sine-pass launch when their M is the same: a launch
 // whose LDS is sized for the largest tile runs the small tiles at the large tile's
-// occupancy, so a pass launches once per tile shape present (at most four).  (A grid-stride loop over the units
-// keeps loop-invariant addressing live across units: about 60 more VGPRs, one workgroup
-// per CU.)  The dynamic LDS holds the largest tile of the batch and, behind it, the
+// occupancy, so a pass launches once per tile shape present (at most four).  (A
+// grid-stride loop over the units keeps loop-invariant addressing live across units:
+// about 60 more VGPRs, one workgroup per CU.)  The dynamic LDS holds the largest tile of the batch and, behind it, the
 // unit's own twiddle and sine tables, staged like the single kernels do; units are
 // spread over the XCDs like the single kernels' tiles.
 struct BatchArgs {
@@ -1604,18 +1608,23 @@ hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool do
 
 hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *hat_in,
                              double *hat_out, double *w) {
-  if (p.opts.precision != WC_FP64) return hipErrorInvalidValue;
+  if (p.opts.precision != WC_FP64 && !p.d_lr_spec) return hipErrorInvalidValue;
   GenIn gen{hat_in, p.d_lr_s0, p.d_lr_gr, p.d_scal + S_LR_SQN0, 1.0 / p.lr_gn, 1.0 / p.lr_rn};
   ContractOut co{hat_out, -p.lr_gn, -p.lr_rn, p.d_lr_rho, p.d_lr_part};  // omega = e^{i pi} = -1
   int np = 0;
-  return pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
+  return p.opts.precision == WC_MIXED
+             ? pc_apply_t<float>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr)
+             : pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
 }
 
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
-  if (!p.d_lr_spec || p.opts.precision != WC_FP64) return hipErrorInvalidValue;
+  if (!p.d_lr_spec) return hipErrorInvalidValue;
+  const bool f32 = p.opts.precision == WC_MIXED;
   switch (p.n) {
-#define CASE_N(NN) \
-  case NN: return run_tfft_fwd<double, NN>(p, r0, nullptr, (cx<double> *)p.d_lr_spec);
+#define CASE_N(NN)                                                                   \
+  case NN:                                                                           \
+    return f32 ? run_tfft_fwd<float, NN>(p, r0, nullptr, (cx<float> *)p.d_lr_spec)   \
+               : run_tfft_fwd<double, NN>(p, r0, nullptr, (cx<double> *)p.d_lr_spec);
     WC_POW2_CASES(CASE_N)
 #undef CASE_N
     default: return hipErrorInvalidValue;

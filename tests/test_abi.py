@@ -113,7 +113,9 @@ def test_lowrank_options_and_footprint(wc):
     nvec = 2 * 256 * 255 * 255 * 8
     assert 0 < lr < full - 25 * nvec  # the basis is compact: ~4 system vectors instead of ~35
     assert wc.footprint_bytes(2, 31, 32, method="minres_abs_ps", lowrank=True) == 0
-    assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", precision="mixed", lowrank=True) == 0
+    assert wc.footprint_bytes(1, 31, 32, method="gmres_ps", precision="mixed", lowrank=True) == 0
+    mixed = wc.footprint_bytes(2, 255, 256, method="gmres_ps", precision="mixed", lowrank=True)
+    assert 0 < mixed < lr  # 2D: the same compact basis with an FP32 spectral array
     a = np.ones(2 * 31 * 32)
     assert wc.footprint_bytes(2, 31, 32, method="gmres_ps", a_face=a, lowrank=True) == 0
 

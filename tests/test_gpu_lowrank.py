@@ -105,7 +105,49 @@ def test_lowrank_rejects_other_methods(env):
     with pytest.raises(wc.WcError):
         wc.Plan(2, 31, 32, method="minres_abs_ps", lowrank=True)
     with pytest.raises(wc.WcError):
-        wc.Plan(2, 31, 32, method="gmres_ps", precision="mixed", lowrank=True)
+        wc.Plan(1, 63, 32, method="gmres_ps", precision="mixed", lowrank=True)  # 2D only
+
+
+MIXED_CASES = [
+    # dims, M, n, theta, gamma, restart
+    (2, 31, 32, 0.5, 1e-4, 30),
+    (2, 63, 64, 0.5, 1e-2, 30),
+    (2, 63, 64, 1.0, 1e-6, 30),
+    (2, 31, 32, 0.5, 1e-6, 3),   # several restart cycles
+    (2, 127, 16, 0.6, 1e-4, 2),
+]
+
+
+@pytest.mark.parametrize("dims,M,n,theta,gamma,restart", MIXED_CASES)
+def test_lowrank_mixed_precision(env, dims, M, n, theta, gamma, restart):
+    """Low-rank GMRES with the FP32 preconditioner: the compact Arnoldi process holds
+    for the FP32 apply, and the restart on the FP64 true residual removes what FP32
+    leaves (each cycle's true residual is at the FP32 level of the last), so the solve
+    still meets 1e-8 by the oracle's operator, in at most a few more iterations than the
+    oracle's FP64 GMRES, and the solution is within FP32 accuracy of the oracle's."""
+    torch, wc = env
+    print("lowrank mixed", dims, M, n, theta, gamma, restart, flush=True)
+    d = datagen.config_problem(dims, M, n, seed=11, noise_sigma=1e-3)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma)
+    ref = osolver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps", tol=1e-8, restart=restart,
+                        maxit=600)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    f, g, y0 = dev(d["f"]), dev(d["g"]), dev(d["y0"])
+    plan = wc.Plan(dims, M, n, theta=theta, gamma=gamma, method="gmres_ps", precision="mixed",
+                   restart=restart, tol=1e-8, maxit=600, lowrank=True)
+    x = torch.empty(2 * n * pr.m, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(x)
+    plan.rhs(f, g, y0, b)
+    info = plan.krylov(b, x)
+    res = np.linalg.norm(ref["b"] - AllAtOnce(pr).Ahat(x.cpu().numpy())) / np.linalg.norm(ref["b"])
+    print("  gpu iters", info.iters, "restarts", info.restarts, "relres", info.relres,
+          "oracle-operator relres", res, "oracle iters", ref["iters"], flush=True)
+    assert info.relres <= 1e-8 and res <= 1.05e-8
+    assert info.iters <= ref["iters"] + 6
+    ref_t = osolver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps", tol=1e-12, restart=restart,
+                          maxit=800)
+    sc = np.abs(ref_t["x"]).max()
+    assert np.abs(x.cpu().numpy() - ref_t["x"]).max() <= 1e-5 * sc
 
 
 def test_full_size_solve_in_bench_configuration(env):
