@@ -136,7 +136,7 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.vecs = (size_t)krylov_vectors(pr, op) * s.nvec * sizeof(double);
   if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g, r, rho, partials
     s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 4 * (size_t)pr->n +
-               (size_t)kContractChunks * 2 * m) * sizeof(double);
+               (size_t)std::max(kContractChunks, kColChunks) * 2 * m) * sizeof(double);
   if (op->lowrank && pr->dims == 2)  // spectrum of r0, rank-term spectra, a1 and a2
     s.vecs += s.spec_bytes + (4 * (size_t)pr->n + 2 * m) * sizeof(double);
   s.mg = 0;
@@ -921,7 +921,8 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     p->lr_len = 1 + 2 * (size_t)p->m;
     alloc((void **)&p->d_lr_s0, 2 * (size_t)p->m * sizeof(double));
     alloc((void **)&p->d_lr_hat, (size_t)(opts->restart + 2) * p->lr_len * sizeof(double));
-    alloc((void **)&p->d_lr_part, (size_t)kContractChunks * 2 * p->m * sizeof(double));
+    alloc((void **)&p->d_lr_part,
+          (size_t)std::max(kContractChunks, kColChunks) * 2 * p->m * sizeof(double));
     if (p->dims == 2) {  // (the rank-term spectra were uploaded with the tables)
       alloc((void **)&p->d_lr_spec, sz.spec_bytes);
       alloc((void **)&p->d_lr_a, 2 * (size_t)p->m * sizeof(double));

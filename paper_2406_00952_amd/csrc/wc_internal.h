@@ -167,9 +167,9 @@ struct wc_plan {
   double *d_lr_part = nullptr;      // kContractChunks x 2m
   // 2D: the time transform is linear and r0 is fixed within a cycle, so the Arnoldi steps
   // take the spectrum of c r0 + [g (x) a1; r (x) a2] from these instead of transforming
-  double *d_lr_spec = nullptr;      // time transform of the cycle's r0 (spectral layout, FP64)
+  double *d_lr_spec = nullptr;      // time and x1 transforms of the cycle's r0 (spectral layout)
   double *d_lr_rank = nullptr;      // n/2 x 2 halves x 2 complex: spectra of g and of r
-  double *d_lr_a = nullptr;         // 2m: a1, a2 of the current compact vector
+  double *d_lr_a = nullptr;         // m complex: a1 + i a2 of the current vector, x1-transformed
 
   mutable wc::Profiler prof;
   // captured Krylov iterations: GMRES step j in slot j (first restart cycle) or
@@ -234,8 +234,10 @@ struct ContractOut {
   const double *rho;   // n complex: rho_r[q] then rho_g[q], q < n/2 (frequency l = q + 1)
   double *part;        // kContractChunks x 2m partial sums
 };
-// frequency chunks of the contraction kernel (deterministic two-stage sum)
+// frequency chunks of the contraction kernels (deterministic two-stage sums): 1D, and the
+// 2D x2 pass (more chunks: its workgroups are chunks x column tiles)
 constexpr int kContractChunks = 8;
+constexpr int kColChunks = 16;
 
 
 // ---- launchers (wc_ops.hip) -------------------------------------------------
@@ -297,7 +299,8 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
 // and sqrt(N0) into the scalar slots; hat = [sqrt(N0), |g| s0_1, |r| s0_2].  Expects
 // ||r0||^2 in d_scal[S_DOT] (launch_dot before).
 hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
-// 2D low-rank GMRES: time transform of the cycle's r0 into d_lr_spec (once per cycle)
+// 2D low-rank GMRES: time transform and x1 sine transform of the cycle's r0 into
+// d_lr_spec (once per cycle)
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0);
 bool pc_supported(int n, int N1);
 

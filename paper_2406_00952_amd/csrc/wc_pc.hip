@@ -43,6 +43,18 @@ template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { re
 template <typename T> __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
 template <typename T> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
 
+// one complex value loaded past the caches (non-temporal)
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cx<double> load_stream(const cx<double> *p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> load_stream(const cx<float> *p) {
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+  return {v.x, v.y};
+}
+
 // Orders the LDS accesses of one wavefront (LDS operations of a wave complete in order;
 // this stops the compiler from moving them across the point).
 __device__ __forceinline__ void wave_sync() {
@@ -688,156 +700,15 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
     dst_rows_group<P, N1>(W, nlines, grp, stw, ssin, lds[wv], lane);
 }
 
-// ---- 2D low-rank GMRES: inverse x1 sine transform fused with the time contraction ----
-// Each wave owns (frequency chunk c, block row h, row x2); it transforms the B lines of
-// consecutive frequencies at a time and accumulates sum_q 2 Re(rho_h[q] Y_q[x1]) in the
-// registers that hold its outputs, so the spectrum is not written back:
-// part[c][h m + x2 M + x1].
-template <typename P, int N1>
-__global__ __launch_bounds__(kThreads) void k_dst_rows_contract(const cx<P> *__restrict__ W,
-                                                                int nq, ContractOut co,
-                                                                const cx<P> *__restrict__ twg,
-                                                                const P *__restrict__ sing) {
-  // transforms in P (FP64, or FP32 for the mixed form), sums over frequencies in FP64
-  using R = RowCfg<P, N1>;
-  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
-  __shared__ cx<P> lds[R::WPB][R::PN * S];
-  __shared__ cx<P> stw[N1];
-  __shared__ P ssin[N1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    stw[i] = twg[i];
-    ssin[i] = sing[i];
-  }
-  __syncthreads();
-  cx<P> *buf = lds[wv];
-  const size_t m = (size_t)M * M;
-  const int per = (nq + kContractChunks - 1) / kContractChunks;
-  const int ntasks = kContractChunks * 2 * M;
-  const cx<double> *rho = reinterpret_cast<const cx<double> *>(co.rho);
-  using L = DstLanes<P, N1, B>;
-  for (int task = blockIdx.x * R::WPB + wv; task < ntasks; task += gridDim.x * R::WPB) {
-    const int c = task / (2 * M), rem = task % (2 * M), h = rem / M, x2 = rem % M;
-    const int q0 = c * per, q1 = q0 + per < nq ? q0 + per : nq;
-    const cx<double> *rh = rho + (size_t)h * nq;
-    // this lane's outputs: Y_{2k+1} at x = 2k and Y_{2k} at x = 2k - 1, k = k0 + cc
-    double aodd[L::CH], aeven[L::CH];
-#pragma unroll
-    for (int cc = 0; cc < L::CH; ++cc) aodd[cc] = aeven[cc] = 0.0;
-    int b = 0, k0 = 0;
-    bool valid = false;
-    for (int qb = q0; qb < q1; qb += B) {
-      dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int bb, int x) {
-        return qb + bb < q1 ? W[((size_t)(qb + bb) * 2 + h) * m + (size_t)x2 * M + x]
-                            : cx<P>{(P)0, (P)0};
-      });
-      wave_sync();
-      cx<P> odd[L::CH], even[L::CH];
-      wdst_regs<P, N1, B, S, PS>(buf, stw, lane, odd, even, b, k0, valid);
-      if (valid && qb + b < q1) {
-        const cx<double> u = rh[qb + b];
-#pragma unroll
-        for (int cc = 0; cc < L::CH; ++cc) {
-          aodd[cc] += 2.0 * (u.x * (double)odd[cc].x - u.y * (double)odd[cc].y);
-          aeven[cc] += 2.0 * (u.x * (double)even[cc].x - u.y * (double)even[cc].y);
-        }
-      }
-      wave_sync();
-    }
-    // the B lines of a group are different frequencies of the same row: add the lanes
-    // that hold the same k for other b (lanes b*G + g), then lane b = 0 writes
-    constexpr int G = L::G;
-#pragma unroll
-    for (int cc = 0; cc < L::CH; ++cc) {
-      double so = aodd[cc], se = aeven[cc];
-#pragma unroll
-      for (int bb = 1; bb < B; ++bb) {
-        so += __shfl(aodd[cc], (lane + bb * G) & 63, 64);
-        se += __shfl(aeven[cc], (lane + bb * G) & 63, 64);
-      }
-      aodd[cc] = so;
-      aeven[cc] = se;
-    }
-    if (lane < G) {
-      double *dst = co.part + (size_t)c * 2 * m + (size_t)h * m + (size_t)x2 * M;
-      const int kk0 = lane * L::CH;
-#pragma unroll
-      for (int cc = 0; cc < L::CH; ++cc) {
-        const int k = kk0 + cc;
-        if (k > 0) dst[2 * k - 1] = aeven[cc];
-        if (2 * k < M) dst[2 * k] = aodd[cc];
-      }
-    }
-  }
-}
-
-// one complex value loaded past the caches (non-temporal)
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ cx<double> load_stream(const cx<double> *p) {
-  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
-  return {v.x, v.y};
-}
-__device__ __forceinline__ cx<float> load_stream(const cx<float> *p) {
-  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
-  return {v.x, v.y};
-}
-
-// ---- 2D low-rank GMRES: the first x1 pass reads the spectrum of v = c r0 + [g (x) a1;
-// r (x) a2] without a time transform: the transform is linear and r0 fixed within a cycle,
-// so Vhat[q][h][s] = c R0hat[q][h][s] + F[q][h][0] a1[s] + F[q][h][1] a2[s] with F the
-// stored spectra of g and r (complex) and a1, a2 real.  (a1, a2 come from a small kernel:
-// forming them inside the loads from the compact coordinates made this pass 25% slower.)
-__global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, double *__restrict__ a, int m) {
+// ---- 2D low-rank GMRES: a1, a2 of the current compact vector, packed as a1 + i a2 for
+// their x1 sine transform (the generated x2 pass's A1 + i A2)
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, cx<P> *__restrict__ a, int m) {
   const int s = blockIdx.x * kThreads + threadIdx.x;
   if (s >= m) return;
   const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
-  a[s] = gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s];
-  a[m + s] = gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s];
-}
-
-template <typename P, int N1>
-__global__ __launch_bounds__(kThreads) void k_dst_rows_lrgen(
-    const cx<P> *__restrict__ R0hat, cx<P> *__restrict__ W, int nlines,
-    const double *__restrict__ a, const cx<double> *__restrict__ F, GenIn gi,
-    const cx<P> *__restrict__ twg, const P *__restrict__ sing) {
-  using R = RowCfg<P, N1>;
-  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
-  __shared__ cx<P> lds[R::WPB][R::PN * S];
-  __shared__ cx<P> stw[N1];
-  __shared__ P ssin[N1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    stw[i] = twg[i];
-    ssin[i] = sing[i];
-  }
-  __syncthreads();
-  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
-  const size_t m = (size_t)M * M;
-  cx<P> *buf = lds[wv];
-  const int ngroups = (nlines + B - 1) / B;
-  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
-    const int l0 = grp * B;
-    dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
-      const int l = l0 + b;  // line (q, h, x2): l = (2q + h) M + x2
-      if (l >= nlines) return cx<P>{(P)0, (P)0};
-      const int qh = l / M;
-      const size_t s = (size_t)(l - qh * M) * M + x;
-      // streamed past the caches: the spectral array this pass writes should stay in the
-      // memory-side cache for the x2 pass (measured: x2 pass 200 -> 174 us)
-      const cx<P> r = load_stream(R0hat + (size_t)l * M + x);
-      const cx<double> f1 = F[2 * qh], f2 = F[2 * qh + 1];
-      const double a1 = a[s], a2 = a[m + s];
-      return cx<P>{(P)(gc * r.x + f1.x * a1 + f2.x * a2), (P)(gc * r.y + f1.y * a1 + f2.y * a2)};
-    });
-    wave_sync();
-    wdst_core<P, N1, B, S, PS>(buf, stw, lane);
-    for (int idx = lane; idx < B * M; idx += 64) {  // coalesced store of the B lines
-      const int b = idx / M, x = idx % M;
-      if (l0 + b < nlines) W[(size_t)(l0 + b) * M + x] = buf[pk<PS>(x + 1) * S + b];
-    }
-    wave_sync();
-  }
+  a[s] = cx<P>{(P)(gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
+               (P)(gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
 }
 
 // ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
@@ -902,12 +773,29 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
 
 // ---- 2D: x2-DST, step 2, x2-iDST on tiles of TX x1-columns (both block rows) -------
 // W layout [q][half][x2][x1], x1 already sine transformed (index j1).
-template <typename P, int N1, int TX, bool TABL>
+//
+// Generated input (2D low-rank GMRES): both transforms that precede this pass are linear
+// and r0 is fixed within a cycle, so the x1-transformed spectrum of c r0 + [g (x) a1;
+// r (x) a2] is c Y0 + F[q][h][0] A1 + F[q][h][1] A2, with Y0 the cycle's transformed r0,
+// F the time spectra of g and r, and A1 + i A2 the x1 sine transform of a1 + i a2.
+template <typename P> struct ColsGen {
+  const cx<P> *Y0;          // [q][h][x2][j1]
+  const cx<P> *A;           // [x2][j1]: (A1, A2)
+  const cx<double> *F;      // [q][h][2]
+  const double *hat, *sqn0; // c = hat[0] / sqn0 (0 when sqn0 = 0)
+};
+
+// ACC: instead of writing the tile back, add 2 Re(rho_h[q] Z) of every output to acc (the
+// thread's outputs in store order; rho_h = rho[h nq + q]).
+template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false>
 __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
                                                const P *__restrict__ sing,
                                                const cx<P> *__restrict__ lam,
                                                const P *__restrict__ mu, int kind, P tau, P alpha,
-                                               P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin) {
+                                               P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin,
+                                               ColsGen<P> cg = {},
+                                               const cx<double> *__restrict__ rho = nullptr,
+                                               int nq = 0, double *acc = nullptr) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
@@ -924,6 +812,8 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   constexpr int H = N1 / 2, TP = H * 2 * TX;
   constexpr int LIT = (TP + NT - 1) / NT;
   cx<P> ra[LIT], rb[LIT];
+  double gc = 0.0;
+  if constexpr (GEN) gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int idx = tid + it * NT;
@@ -931,9 +821,21 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
     ra[it] = cx<P>{(P)0, (P)0};
     rb[it] = cx<P>{(P)0, (P)0};
     if (idx < TP && c0 + c < M) {
-      const cx<P> *src = (h ? slab1 : slab0) + c0 + c;
-      ra[it] = src[(size_t)(i - 1) * M];
-      rb[it] = src[(size_t)(N1 - i - 1) * M];
+      const size_t o1 = (size_t)(i - 1) * M + c0 + c, o2 = (size_t)(N1 - i - 1) * M + c0 + c;
+      if constexpr (GEN) {
+        const cx<P> *Y = cg.Y0 + ((size_t)q * 2 + h) * M * M;
+        const cx<double> f1 = cg.F[(q * 2 + h) * 2], f2 = cg.F[(q * 2 + h) * 2 + 1];
+        const cx<P> y1 = load_stream(Y + o1), y2 = load_stream(Y + o2);
+        const cx<P> a1 = cg.A[o1], a2 = cg.A[o2];
+        ra[it] = cx<P>{(P)(gc * y1.x + f1.x * a1.x + f2.x * a1.y),
+                       (P)(gc * y1.y + f1.y * a1.x + f2.y * a1.y)};
+        rb[it] = cx<P>{(P)(gc * y2.x + f1.x * a2.x + f2.x * a2.y),
+                       (P)(gc * y2.y + f1.y * a2.x + f2.y * a2.y)};
+      } else {
+        const cx<P> *src = h ? slab1 : slab0;
+        ra[it] = src[o1];
+        rb[it] = src[o2];
+      }
     }
   }
   if constexpr (TABL) {
@@ -974,10 +876,25 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   wave_sync();
   wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
   __syncthreads();
-  for (int idx = tid; idx < TT; idx += NT) {
-    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
-    if (c0 + c < M)
-      (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
+  if constexpr (ACC) {
+    const cx<double> r0 = rho[q], r1 = rho[nq + q];
+    constexpr int CIT = (TT + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < CIT; ++it) {
+      const int idx = tid + it * NT;
+      if (TT % NT == 0 || idx < TT) {
+        const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+        const cx<P> z = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
+        const cx<double> r = h ? r1 : r0;
+        acc[it] += 2.0 * (r.x * (double)z.x - r.y * (double)z.y);
+      }
+    }
+  } else {
+    for (int idx = tid; idx < TT; idx += NT) {
+      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+      if (c0 + c < M)
+        (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
+    }
   }
 }
 
@@ -994,6 +911,87 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode(cx<P> *__
   __shared__ P ssin[C::TAB_LDS ? N1 : 1];
   cols_mode_tile<P, N1, TX, C::TAB_LDS>(W, twg, sing, lam, mu, kind, tau, alpha, cnorm,
                                         xcd_tile(blockIdx.x, gridDim.x), buf, stw, ssin);
+}
+
+// the x2 pass on the generated input, writing the spectrum (the cycle's update)
+template <typename P, int N1, int TX>
+__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
+    cx<P> *__restrict__ W, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
+    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
+    ColsGen<P> cg) {
+  using C = ColCfg<P, N1, TX>;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  cols_mode_tile<P, N1, TX, C::TAB_LDS, true>(W, twg, sing, lam, mu, kind, tau, alpha, cnorm,
+                                              xcd_tile(blockIdx.x, gridDim.x), buf, stw, ssin,
+                                              cg);
+}
+
+// 2D low-rank GMRES step: the x2 pass on the generated input, contracted over time before
+// the inverse x1 transform (the contraction sum_q 2 Re(rho_q Z_q) commutes with it, the
+// sine transform being real), so the spectrum is never written: workgroup (chunk, column
+// tile) runs the tile body for the frequencies of its chunk and writes its sums,
+// part[chunk][h m + x2 M + j1].
+template <typename P, int N1, int TX>
+__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
+    const cx<P> *__restrict__ twg, const P *__restrict__ sing, const cx<P> *__restrict__ lam,
+    const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm, ColsGen<P> cg,
+    const cx<double> *__restrict__ rho, int nq, double *__restrict__ part) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int M = N1 - 1, TT = 2 * TX * M, NT = C::NT, CIT = (TT + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int ncx = (N1 - 2 + TX) / TX;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int chunk = t / ncx, ct = t % ncx;
+  const int per = (nq + kColChunks - 1) / kColChunks;
+  const int q0 = chunk * per, q1 = q0 + per < nq ? q0 + per : nq;
+  double acc[CIT];
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) acc[it] = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    // (the spectrum argument is not written in this mode)
+    cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true>(const_cast<cx<P> *>(cg.Y0), twg, sing, lam,
+                                                      mu, kind, tau, alpha, cnorm, q * ncx + ct,
+                                                      buf, stw, ssin, cg, rho, nq, acc);
+    __syncthreads();  // the next frequency reuses the LDS
+  }
+  const size_t m = (size_t)M * M;
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) {
+    const int idx = threadIdx.x + it * NT;
+    if (TT % NT == 0 || idx < TT) {
+      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX), j1 = ct * TX + c;
+      if (j1 < M) part[(size_t)chunk * 2 * m + h * m + (size_t)x2 * M + j1] = acc[it];
+    }
+  }
+}
+
+// sums of the chunks, packed as C_0 + i C_1 per spatial point for the inverse x1 transform
+__global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__restrict__ part,
+                                                            cx<double> *__restrict__ out,
+                                                            int m) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int c = 0; c < kColChunks; ++c) {
+    a += part[(size_t)c * 2 * m + s];
+    b += part[(size_t)c * 2 * m + m + s];
+  }
+  out[s] = cx<double>{a, b};
+}
+
+// hat_out of the contracted output: [0, |g| omega C_0, |r| omega C_1]
+__global__ __launch_bounds__(kThreads) void k_contract_scale(const cx<double> *__restrict__ c,
+                                                             ContractOut co, int m) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) co.hat[0] = 0.0;
+  if (s >= m) return;
+  co.hat[1 + s] = co.gn_omega * c[s].x;
+  co.hat[1 + m + s] = co.rn_omega * c[s].y;
 }
 
 
@@ -1127,18 +1125,44 @@ hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *np
 }
 
 template <typename P, int N1, int TX>
-hipError_t cols_tx(const wc_plan &p, int kind, double c) {
+hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
+                   const ContractOut *co) {
   if constexpr (!ColCfg<P, N1, TX>::FITS) {
-    return cols_tx<P, N1, 4>(p, kind, c);
+    return cols_tx<P, N1, 4>(p, kind, c, cg, co);
   } else {
     constexpr int M = N1 - 1;
-    dim3 gc(((M + TX - 1) / TX) * (p.n / 2));
+    const int ncx = (M + TX - 1) / TX;
+    if (cg && co) {  // generated input, contracted over time (2D low-rank GMRES step)
+      ProfScope ps(p, K_PAIR_MODE, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
+      hipLaunchKernelGGL((k_cols_contract<P, N1, TX>), dim3(kColChunks * ncx),
+                         dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
+                         Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
+                         (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2, co->part);
+      return hipGetLastError();
+    }
+    dim3 gc(ncx * (p.n / 2));
     ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0, p.stream,
-                       (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
-                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
+    if (cg)
+      hipLaunchKernelGGL((k_cols_mode_gen<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0,
+                         p.stream, (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p),
+                         Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c, *cg);
+    else
+      hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0, p.stream,
+                         (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
+                         Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
     return hipGetLastError();
   }
+}
+
+// x1 sine transform of nlines contiguous lines in place
+template <typename P, int N1>
+hipError_t dst_rows_on(const wc_plan &p, cx<P> *buf, int nlines, int prof_id, double bytes) {
+  using R = RowCfg<P, N1>;
+  dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
+  ProfScope ps(p, prof_id, bytes);
+  hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream, buf, nlines,
+                     Tabs<P>::tws(p), Tabs<P>::sin(p));
+  return hipGetLastError();
 }
 
 template <typename P, int N1>
@@ -1161,33 +1185,35 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
   }
   const int nlines = p.n * M;  // n/2 frequencies x 2 block rows x M rows
   dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
-  hipError_t e;
-  {
-    ProfScope ps(p, K_DST_X1_FWD, bytes);
-    if (rows_gen) {
-      hipLaunchKernelGGL((k_dst_rows_lrgen<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
-                         (const cx<P> *)p.d_lr_spec, W, nlines, p.d_lr_a,
-                         (const cx<double> *)p.d_lr_rank, *rows_gen, Tabs<P>::tws(p),
-                         Tabs<P>::sin(p));
-    } else {
-      hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0,
-                         p.stream, W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
-    }
-    e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  ColsGen<P> cg{};
+  if (rows_gen) {  // 2D low-rank GMRES: the x2 pass generates its input (no x1 pass here)
+    cg = ColsGen<P>{(const cx<P> *)p.d_lr_spec, (const cx<P> *)p.d_lr_a,
+                    (const cx<double> *)p.d_lr_rank, rows_gen->hat, rows_gen->sqn0};
+  } else {
+    e = dst_rows_on<P, N1>(p, W, nlines, K_DST_X1_FWD, bytes);
   }
   if (e != hipSuccess) return e;
+  const ColsGen<P> *cgp = rows_gen ? &cg : nullptr;
+  const ContractOut *cop = rows_gen ? co : nullptr;
   switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
-    case 4: e = cols_tx<P, N1, 4>(p, kind, c); break;
-    case 16: e = cols_tx<P, N1, 16>(p, kind, c); break;
-    default: e = cols_tx<P, N1, 8>(p, kind, c); break;
+    case 4: e = cols_tx<P, N1, 4>(p, kind, c, cgp, cop); break;
+    case 16: e = cols_tx<P, N1, 16>(p, kind, c, cgp, cop); break;
+    default: e = cols_tx<P, N1, 8>(p, kind, c, cgp, cop); break;
   }
   if (e != hipSuccess) return e;
-  if (co) {  // low-rank GMRES: the last pass contracts over time instead of writing back
-    const int ntasks = kContractChunks * 2 * M;
-    dim3 gt(row_grid(ntasks, R::WPB));
-    ProfScope ps(p, K_DST_X1_INV, bytes / 2 + 16.0 * kContractChunks * p.m);
-    hipLaunchKernelGGL((k_dst_rows_contract<P, N1>), gt, dim3(64 * R::WPB), 0, p.stream,
-                       (const cx<P> *)W, p.n / 2, *co, Tabs<P>::tws(p), Tabs<P>::sin(p));
+  if (co) {  // low-rank GMRES step: sum the chunks, inverse x1 transform of C_0 + i C_1
+    if (!rows_gen) return hipErrorInvalidValue;
+    cx<double> *pk2 = (cx<double> *)p.d_lr_a;  // free again once the x2 pass has run
+    const dim3 g1((p.m + kThreads - 1) / kThreads);
+    {
+      ProfScope ps(p, K_CONTRACT, 16.0 * kColChunks * p.m + 16.0 * p.m);
+      hipLaunchKernelGGL(k_contract_pack, g1, dim3(kThreads), 0, p.stream, co->part, pk2, p.m);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = dst_rows_on<double, N1>(p, pk2, M, K_CONTRACT, 32.0 * p.m)) != hipSuccess) return e;
+    ProfScope ps(p, K_CONTRACT, 32.0 * p.m);
+    hipLaunchKernelGGL(k_contract_scale, g1, dim3(kThreads), 0, p.stream, pk2, *co, p.m);
     return hipGetLastError();
   }
   ProfScope ps(p, K_DST_X1_INV, bytes);
@@ -1205,11 +1231,24 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
   const bool hoist = gen && p.dims == 2 && p.d_lr_spec;
-  if (hoist) {
-    ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
-    hipLaunchKernelGGL(k_lr_coef, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       p.stream, *gen, p.d_lr_a, p.m);
-    e = hipGetLastError();
+  if (hoist) {  // a1 + i a2 and its x1 sine transform (M lines)
+    {
+      ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
+      hipLaunchKernelGGL((k_lr_coef<P>), dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads),
+                         0, p.stream, *gen, (cx<P> *)p.d_lr_a, p.m);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      switch (p.N1) {
+#define CASE_S(NN)                                                                           \
+  case NN:                                                                                   \
+    e = dst_rows_on<P, NN>(p, (cx<P> *)p.d_lr_a, p.M, K_LR_SETUP, 2.0 * p.m * sizeof(cx<P>)); \
+    break;
+        WC_POW2_CASES(CASE_S)
+#undef CASE_S
+        default: return hipErrorInvalidValue;
+      }
+    }
   } else {
     switch (p.n) {
 #define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, v, gen); break;
@@ -1244,10 +1283,11 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
     }
+    *nparts = 0;
+    if (p.dims == 2) return hipSuccess;  // 2D: the x2 pass and its tail contracted
     ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
     hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
                        p.stream, *co, p.m);
-    *nparts = 0;
     return hipGetLastError();
   }
   switch (p.n) {
@@ -1617,18 +1657,32 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
              : pc_apply_t<double>(p, r0, w, nullptr, &np, &gen, hat_out ? &co : nullptr);
 }
 
-hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
-  if (!p.d_lr_spec) return hipErrorInvalidValue;
-  const bool f32 = p.opts.precision == WC_MIXED;
+namespace {
+template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r0) {
+  hipError_t e = hipErrorInvalidValue;
+  cx<P> *Y = (cx<P> *)p.d_lr_spec;
   switch (p.n) {
-#define CASE_N(NN)                                                                   \
-  case NN:                                                                           \
-    return f32 ? run_tfft_fwd<float, NN>(p, r0, nullptr, (cx<float> *)p.d_lr_spec)   \
-               : run_tfft_fwd<double, NN>(p, r0, nullptr, (cx<double> *)p.d_lr_spec);
+#define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, r0, nullptr, Y); break;
     WC_POW2_CASES(CASE_N)
 #undef CASE_N
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
+  const int nlines = p.n * p.M;
+  switch (p.N1) {
+#define CASE_S(NN) \
+  case NN: return dst_rows_on<P, NN>(p, Y, nlines, K_DST_X1_FWD, 2.0 * p.nvec * sizeof(P));
+    WC_POW2_CASES(CASE_S)
+#undef CASE_S
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
+  if (!p.d_lr_spec || p.dims != 2) return hipErrorInvalidValue;
+  return p.opts.precision == WC_MIXED ? lr_spectrum_t<float>(p, r0)
+                                      : lr_spectrum_t<double>(p, r0);
 }
 
 int pc_partials_needed(int n, int m, int precision) {
