@@ -1014,11 +1014,44 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
         btx = p->tx_cols;
       }
     }
+  p->ts_time = bts;
+  p->tx_cols = btx;
+  // 2D low-rank GMRES: the contracting x2 pass loops over frequencies and keeps more
+  // registers live, so its tile width is timed on its own (on placeholder data)
+  if (e == hipSuccess && p->d_lr_spec) {
+    const size_t spec_doubles = (size_t)p->n * p->m * (p->opts.precision == WC_MIXED ? 1 : 2);
+    double *hat = p->d_lr_hat, *hat_out = p->d_lr_hat + p->lr_len;
+    e = launch_fill(*p, p->d_lr_spec, 1e-3, spec_doubles);
+    if (e == hipSuccess) e = launch_fill(*p, hat, 1.0, p->lr_len);
+    if (e == hipSuccess) e = launch_fill(*p, p->d_lr_s0, 0.0, 2 * (size_t)p->m);
+    if (e == hipSuccess) e = launch_fill(*p, p->d_scal + S_LR_SQN0, 1.0, 1);
+    float bestc = -1.f;
+    int bc = 0;
+    bool bo = false;
+    const int cands[4] = {4, 8, 4, 8};
+    for (int ic = 0; ic < 4 && e == hipSuccess; ++ic) {
+      p->tx_contract = cands[ic];
+      p->contract_opq = ic >= 2;
+      e = launch_pc_lowrank(*p, v, hat, hat_out, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_pc_lowrank(*p, v, hat, hat_out, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess && (bestc < 0.f || ms < bestc)) {
+        bestc = ms;
+        bc = cands[ic];
+        bo = p->contract_opq;
+      }
+    }
+    p->tx_contract = bc;
+    p->contract_opq = bo;
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   p->prof.on = prof;
-  p->ts_time = bts;
-  p->tx_cols = btx;
   drop_graphs(p);  // captured launches hold the previous kernel choice
   if (e != hipSuccess) return WC_E_HIP;
   if (ts_out) *ts_out = bts;

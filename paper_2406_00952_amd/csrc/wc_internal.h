@@ -113,6 +113,8 @@ struct wc_plan {
   int num_cu = 256;              // compute units of the plan's device
   int ts_time = 0;               // time-FFT tile width (0: default)
   int tx_cols = 0;               // x2-pass tile width (0: default)
+  int tx_contract = 0;           // tile width of the contracting x2 pass (0: as tx_cols)
+  bool contract_opq = false;     // its address arithmetic recomputed per frequency
   wc_opts opts{};
   hipStream_t stream = nullptr;
   size_t nvec = 0;          // 2*n*m

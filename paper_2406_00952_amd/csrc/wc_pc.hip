@@ -787,7 +787,8 @@ template <typename P> struct ColsGen {
 
 // ACC: instead of writing the tile back, add 2 Re(rho_h[q] Z) of every output to acc (the
 // thread's outputs in store order; rho_h = rho[h nq + q]).
-template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false>
+template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false,
+          bool OPQ = false>
 __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
                                                const P *__restrict__ sing,
                                                const cx<P> *__restrict__ lam,
@@ -799,7 +800,12 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int tid = threadIdx.x;
+  // OPQ (a body repeated over frequencies): an opaque copy of the thread index keeps the
+  // compiler from hoisting the tile's address arithmetic out of that loop, where it would
+  // stay live across the whole body; the autotuner picks whichever form runs faster
+  if constexpr (OPQ) asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wv = tid >> 6;
   const int ncx = (N1 - 2 + TX) / TX;  // column tiles per frequency, M = N1 - 1 columns
   const int q = t / ncx;
   const int c0 = (t % ncx) * TX;
@@ -933,7 +939,7 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
 // sine transform being real), so the spectrum is never written: workgroup (chunk, column
 // tile) runs the tile body for the frequencies of its chunk and writes its sums,
 // part[chunk][h m + x2 M + j1].
-template <typename P, int N1, int TX>
+template <typename P, int N1, int TX, bool OPQ>
 __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
     const cx<P> *__restrict__ twg, const P *__restrict__ sing, const cx<P> *__restrict__ lam,
     const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm, ColsGen<P> cg,
@@ -953,9 +959,9 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
   for (int it = 0; it < CIT; ++it) acc[it] = 0.0;
   for (int q = q0; q < q1; ++q) {
     // (the spectrum argument is not written in this mode)
-    cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true>(const_cast<cx<P> *>(cg.Y0), twg, sing, lam,
-                                                      mu, kind, tau, alpha, cnorm, q * ncx + ct,
-                                                      buf, stw, ssin, cg, rho, nq, acc);
+    cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ>(
+        const_cast<cx<P> *>(cg.Y0), twg, sing, lam, mu, kind, tau, alpha, cnorm, q * ncx + ct,
+        buf, stw, ssin, cg, rho, nq, acc);
     __syncthreads();  // the next frequency reuses the LDS
   }
   const size_t m = (size_t)M * M;
@@ -1134,10 +1140,18 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
     const int ncx = (M + TX - 1) / TX;
     if (cg && co) {  // generated input, contracted over time (2D low-rank GMRES step)
       ProfScope ps(p, K_PAIR_MODE, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
-      hipLaunchKernelGGL((k_cols_contract<P, N1, TX>), dim3(kColChunks * ncx),
-                         dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
-                         Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
-                         (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2, co->part);
+      if (p.contract_opq)
+        hipLaunchKernelGGL((k_cols_contract<P, N1, TX, true>), dim3(kColChunks * ncx),
+                           dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
+                           Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
+                           (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2,
+                           co->part);
+      else
+        hipLaunchKernelGGL((k_cols_contract<P, N1, TX, false>), dim3(kColChunks * ncx),
+                           dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
+                           Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
+                           (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2,
+                           co->part);
       return hipGetLastError();
     }
     dim3 gc(ncx * (p.n / 2));
@@ -1196,7 +1210,9 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
   if (e != hipSuccess) return e;
   const ColsGen<P> *cgp = rows_gen ? &cg : nullptr;
   const ContractOut *cop = rows_gen ? co : nullptr;
-  switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
+  int tx = p.tx_cols ? p.tx_cols : default_tx<P, N1>();
+  if (cop && p.tx_contract) tx = p.tx_contract;
+  switch (tx) {
     case 4: e = cols_tx<P, N1, 4>(p, kind, c, cgp, cop); break;
     case 16: e = cols_tx<P, N1, 16>(p, kind, c, cgp, cop); break;
     default: e = cols_tx<P, N1, 8>(p, kind, c, cgp, cop); break;
