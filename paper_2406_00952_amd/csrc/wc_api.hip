@@ -1027,11 +1027,11 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
     if (e == hipSuccess) e = launch_fill(*p, p->d_scal + S_LR_SQN0, 1.0, 1);
     float bestc = -1.f;
     int bc = 0;
-    bool bo = false;
-    const int cands[4] = {4, 8, 4, 8};
-    for (int ic = 0; ic < 4 && e == hipSuccess; ++ic) {
-      p->tx_contract = cands[ic];
-      p->contract_opq = ic >= 2;
+    bool bo = false, bp = false;
+    for (int ic = 0; ic < 8 && e == hipSuccess; ++ic) {
+      p->tx_contract = (ic & 1) ? 8 : 4;
+      p->contract_opq = (ic & 2) != 0;
+      p->contract_pf = (ic & 4) != 0;
       e = launch_pc_lowrank(*p, v, hat, hat_out, nullptr);
       if (e == hipSuccess) e = hipEventRecord(a, p->stream);
       for (int r = 0; r < reps && e == hipSuccess; ++r)
@@ -1042,12 +1042,14 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
       if (e == hipSuccess && (bestc < 0.f || ms < bestc)) {
         bestc = ms;
-        bc = cands[ic];
+        bc = p->tx_contract;
         bo = p->contract_opq;
+        bp = p->contract_pf;
       }
     }
     p->tx_contract = bc;
     p->contract_opq = bo;
+    p->contract_pf = bp;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

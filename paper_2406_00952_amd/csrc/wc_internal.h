@@ -115,6 +115,7 @@ struct wc_plan {
   int tx_cols = 0;               // x2-pass tile width (0: default)
   int tx_contract = 0;           // tile width of the contracting x2 pass (0: as tx_cols)
   bool contract_opq = false;     // its address arithmetic recomputed per frequency
+  bool contract_pf = false;      // the next frequency's loads issued ahead
   wc_opts opts{};
   hipStream_t stream = nullptr;
   size_t nvec = 0;          // 2*n*m

@@ -785,10 +785,48 @@ template <typename P> struct ColsGen {
   const double *hat, *sqn0; // c = hat[0] / sqn0 (0 when sqn0 = 0)
 };
 
+// The loads of x2 tile t (or its generated input): item (c, h, i) of thread tid reads rows
+// i-1 and N1-i-1 of column c0+c of block row h.
+template <typename P, int N1, int TX, bool GEN>
+__device__ __forceinline__ void cols_tile_load(cx<P> *__restrict__ W, const ColsGen<P> &cg,
+                                               int t, int tid, double gc, cx<P> *ra, cx<P> *rb) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int M = N1 - 1, NT = C::NT, H = N1 / 2, TP = H * 2 * TX;
+  constexpr int LIT = (TP + NT - 1) / NT;
+  const int ncx = (N1 - 2 + TX) / TX;
+  const int q = t / ncx, c0 = (t % ncx) * TX;
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX);
+    ra[it] = cx<P>{(P)0, (P)0};
+    rb[it] = cx<P>{(P)0, (P)0};
+    if (idx < TP && c0 + c < M) {
+      const size_t o1 = (size_t)(i - 1) * M + c0 + c, o2 = (size_t)(N1 - i - 1) * M + c0 + c;
+      if constexpr (GEN) {
+        const cx<P> *Y = cg.Y0 + ((size_t)q * 2 + h) * M * M;
+        const cx<double> f1 = cg.F[(q * 2 + h) * 2], f2 = cg.F[(q * 2 + h) * 2 + 1];
+        const cx<P> y1 = load_stream(Y + o1), y2 = load_stream(Y + o2);
+        const cx<P> a1 = cg.A[o1], a2 = cg.A[o2];
+        ra[it] = cx<P>{(P)(gc * y1.x + f1.x * a1.x + f2.x * a1.y),
+                       (P)(gc * y1.y + f1.y * a1.x + f2.y * a1.y)};
+        rb[it] = cx<P>{(P)(gc * y2.x + f1.x * a2.x + f2.x * a2.y),
+                       (P)(gc * y2.y + f1.y * a2.x + f2.y * a2.y)};
+      } else {
+        const cx<P> *src = W + ((size_t)q * 2 + h) * M * M;
+        ra[it] = src[o1];
+        rb[it] = src[o2];
+      }
+    }
+  }
+}
+
 // ACC: instead of writing the tile back, add 2 Re(rho_h[q] Z) of every output to acc (the
 // thread's outputs in store order; rho_h = rho[h nq + q]).
+// PRE: the tile's loads arrive in pra/prb (issued earlier); tile tn's loads (tn >= 0) are
+// issued into them while this tile is transformed.
 template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false,
-          bool OPQ = false>
+          bool OPQ = false, bool PRE = false>
 __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
                                                const P *__restrict__ sing,
                                                const cx<P> *__restrict__ lam,
@@ -796,7 +834,9 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
                                                P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin,
                                                ColsGen<P> cg = {},
                                                const cx<double> *__restrict__ rho = nullptr,
-                                               int nq = 0, double *acc = nullptr) {
+                                               int nq = 0, double *acc = nullptr,
+                                               cx<P> *pra = nullptr, cx<P> *prb = nullptr,
+                                               int tn = -1) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
@@ -820,29 +860,15 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   cx<P> ra[LIT], rb[LIT];
   double gc = 0.0;
   if constexpr (GEN) gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
+  if constexpr (PRE) {
 #pragma unroll
-  for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * NT;
-    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX);
-    ra[it] = cx<P>{(P)0, (P)0};
-    rb[it] = cx<P>{(P)0, (P)0};
-    if (idx < TP && c0 + c < M) {
-      const size_t o1 = (size_t)(i - 1) * M + c0 + c, o2 = (size_t)(N1 - i - 1) * M + c0 + c;
-      if constexpr (GEN) {
-        const cx<P> *Y = cg.Y0 + ((size_t)q * 2 + h) * M * M;
-        const cx<double> f1 = cg.F[(q * 2 + h) * 2], f2 = cg.F[(q * 2 + h) * 2 + 1];
-        const cx<P> y1 = load_stream(Y + o1), y2 = load_stream(Y + o2);
-        const cx<P> a1 = cg.A[o1], a2 = cg.A[o2];
-        ra[it] = cx<P>{(P)(gc * y1.x + f1.x * a1.x + f2.x * a1.y),
-                       (P)(gc * y1.y + f1.y * a1.x + f2.y * a1.y)};
-        rb[it] = cx<P>{(P)(gc * y2.x + f1.x * a2.x + f2.x * a2.y),
-                       (P)(gc * y2.y + f1.y * a2.x + f2.y * a2.y)};
-      } else {
-        const cx<P> *src = h ? slab1 : slab0;
-        ra[it] = src[o1];
-        rb[it] = src[o2];
-      }
+    for (int it = 0; it < LIT; ++it) {
+      ra[it] = pra[it];
+      rb[it] = prb[it];
     }
+    if (tn >= 0) cols_tile_load<P, N1, TX, GEN>(W, cg, tn, tid, gc, pra, prb);
+  } else {
+    cols_tile_load<P, N1, TX, GEN>(W, cg, t, tid, gc, ra, rb);
   }
   if constexpr (TABL) {
     for (int i = tid; i < N1; i += NT) {
@@ -939,7 +965,7 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
 // sine transform being real), so the spectrum is never written: workgroup (chunk, column
 // tile) runs the tile body for the frequencies of its chunk and writes its sums,
 // part[chunk][h m + x2 M + j1].
-template <typename P, int N1, int TX, bool OPQ>
+template <typename P, int N1, int TX, bool OPQ, bool PF>
 __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
     const cx<P> *__restrict__ twg, const P *__restrict__ sing, const cx<P> *__restrict__ lam,
     const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm, ColsGen<P> cg,
@@ -957,12 +983,26 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
   double acc[CIT];
 #pragma unroll
   for (int it = 0; it < CIT; ++it) acc[it] = 0.0;
-  for (int q = q0; q < q1; ++q) {
-    // (the spectrum argument is not written in this mode)
-    cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ>(
-        const_cast<cx<P> *>(cg.Y0), twg, sing, lam, mu, kind, tau, alpha, cnorm, q * ncx + ct,
-        buf, stw, ssin, cg, rho, nq, acc);
-    __syncthreads();  // the next frequency reuses the LDS
+  // (the spectrum argument is not written in this mode)
+  cx<P> *const W0 = const_cast<cx<P> *>(cg.Y0);
+  if constexpr (PF) {  // the next frequency's loads are in flight while one is transformed
+    constexpr int LIT = (N1 / 2 * 2 * TX + NT - 1) / NT;
+    cx<P> pra[LIT], prb[LIT];
+    const double gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
+    if (q0 < q1) cols_tile_load<P, N1, TX, true>(W0, cg, q0 * ncx + ct, threadIdx.x, gc, pra, prb);
+    for (int q = q0; q < q1; ++q) {
+      cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ, true>(
+          W0, twg, sing, lam, mu, kind, tau, alpha, cnorm, q * ncx + ct, buf, stw, ssin, cg, rho,
+          nq, acc, pra, prb, q + 1 < q1 ? (q + 1) * ncx + ct : -1);
+      __syncthreads();  // the next frequency reuses the LDS
+    }
+  } else {
+    for (int q = q0; q < q1; ++q) {
+      cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ>(W0, twg, sing, lam, mu, kind, tau,
+                                                             alpha, cnorm, q * ncx + ct, buf, stw,
+                                                             ssin, cg, rho, nq, acc);
+      __syncthreads();  // the next frequency reuses the LDS
+    }
   }
   const size_t m = (size_t)M * M;
 #pragma unroll
@@ -1138,20 +1178,20 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
   } else {
     constexpr int M = N1 - 1;
     const int ncx = (M + TX - 1) / TX;
-    if (cg && co) {  // generated input, contracted over time (2D low-rank GMRES step)
+    if constexpr (TX == 16) {  // the contracting pass has 4- and 8-column forms
+      if (cg && co) return cols_tx<P, N1, 8>(p, kind, c, cg, co);
+    } else if (cg && co) {  // generated input, contracted over time (low-rank step)
       ProfScope ps(p, K_PAIR_MODE, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
-      if (p.contract_opq)
-        hipLaunchKernelGGL((k_cols_contract<P, N1, TX, true>), dim3(kColChunks * ncx),
-                           dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
-                           Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
-                           (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2,
-                           co->part);
-      else
-        hipLaunchKernelGGL((k_cols_contract<P, N1, TX, false>), dim3(kColChunks * ncx),
-                           dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),
-                           Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
-                           (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2,
-                           co->part);
+#define WC_CC(OPQ, PF)                                                                     \
+  hipLaunchKernelGGL((k_cols_contract<P, N1, TX, OPQ, PF>), dim3(kColChunks * ncx),          \
+                     dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),              \
+                     Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,       \
+                     (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2, co->part)
+      if (p.contract_opq && p.contract_pf) WC_CC(true, true);
+      else if (p.contract_opq) WC_CC(true, false);
+      else if (p.contract_pf) WC_CC(false, true);
+      else WC_CC(false, false);
+#undef WC_CC
       return hipGetLastError();
     }
     dim3 gc(ncx * (p.n / 2));
