@@ -896,8 +896,6 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
       p->num_cu = cus;
   }
   const Sizes sz = sizes_of(prob, opts);
-  if (const char *e = std::getenv("WC_TS")) p->ts_time = std::atoi(e);
-  if (const char *e = std::getenv("WC_TX")) p->tx_cols = std::atoi(e);
   {
     const wc_status ts = set_tables(p, prob);
     if (ts != WC_OK) {
