@@ -700,16 +700,75 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows(cx<P> *__restrict__ W, in
     dst_rows_group<P, N1>(W, nlines, grp, stw, ssin, lds[wv], lane);
 }
 
-// ---- 2D low-rank GMRES: a1, a2 of the current compact vector, packed as a1 + i a2 for
-// their x1 sine transform (the generated x2 pass's A1 + i A2)
-template <typename P>
-__global__ __launch_bounds__(kThreads) void k_lr_coef(GenIn gi, cx<P> *__restrict__ a, int m) {
-  const int s = blockIdx.x * kThreads + threadIdx.x;
-  if (s >= m) return;
-  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
-  a[s] = cx<P>{(P)(gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
-               (P)(gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
+// ---- x1 sine transform of lines read and written through functors (the m-point work of
+// a low-rank step: its input is formed as it loads and its output finished as it stores)
+template <typename P, int N1, typename Src, typename Dst>
+__global__ __launch_bounds__(kThreads) void k_dst_rows_fn(int nlines, const cx<P> *__restrict__ twg,
+                                                          const P *__restrict__ sing, Src src,
+                                                          Dst dst) {
+  using R = RowCfg<P, N1>;
+  constexpr int M = N1 - 1, B = R::B, S = R::S, PS = R::PS;
+  __shared__ cx<P> lds[R::WPB][R::PN * S];
+  __shared__ cx<P> stw[N1];
+  __shared__ P ssin[N1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    stw[i] = twg[i];
+    ssin[i] = sing[i];
+  }
+  __syncthreads();
+  cx<P> *buf = lds[wv];
+  const int ngroups = (nlines + B - 1) / B;
+  for (int grp = blockIdx.x * R::WPB + wv; grp < ngroups; grp += gridDim.x * R::WPB) {
+    const int l0 = grp * B;
+    dst_pre_global<P, N1, B, S, PS>(buf, ssin, lane, [&](int b, int x) {
+      return l0 + b < nlines ? src(l0 + b, x) : cx<P>{(P)0, (P)0};
+    });
+    wave_sync();
+    wdst_core<P, N1, B, S, PS>(buf, stw, lane);
+    for (int idx = lane; idx < B * M; idx += 64) {
+      const int b = idx / M, x = idx % M;
+      if (l0 + b < nlines) dst(l0 + b, x, buf[pk<PS>(x + 1) * S + b]);
+    }
+    wave_sync();
+  }
 }
+
+// line x2 of a1 + i a2 for the current compact vector ...
+template <typename P> struct LrCoefSrc {
+  GenIn gi;
+  int m, M;
+  __device__ cx<P> operator()(int x2, int x) const {
+    const int s = x2 * M + x;
+    const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+    return cx<P>{(P)(gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
+                 (P)(gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
+  }
+};
+// ... stored as A[x2][j1]
+template <typename P> struct StoreA {
+  cx<P> *A;
+  int M;
+  __device__ void operator()(int x2, int x, cx<P> v) const { A[x2 * M + x] = v; }
+};
+// line x2 of C_0 + i C_1 (the packed chunk sums) ...
+struct PackedSrc {
+  const cx<double> *c;
+  int M;
+  __device__ cx<double> operator()(int x2, int j1) const { return c[x2 * M + j1]; }
+};
+// ... and the compact output [0, |g| omega C_0, |r| omega C_1] after the inverse x1 transform
+struct StoreHat {
+  ContractOut co;
+  int m, M;
+  __device__ void operator()(int x2, int x, cx<double> v) const {
+    const int s = x2 * M + x;
+    if (s == 0) co.hat[0] = 0.0;
+    co.hat[1 + s] = co.gn_omega * v.x;
+    co.hat[1 + m + s] = co.rn_omega * v.y;
+  }
+};
+
 
 // ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
 // W layout [q][half][x]; every wave owns UNITS frequencies (2*UNITS lines) at a time.
@@ -1030,15 +1089,6 @@ __global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__rest
   out[s] = cx<double>{a, b};
 }
 
-// hat_out of the contracted output: [0, |g| omega C_0, |r| omega C_1]
-__global__ __launch_bounds__(kThreads) void k_contract_scale(const cx<double> *__restrict__ c,
-                                                             ContractOut co, int m) {
-  const int s = blockIdx.x * kThreads + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) co.hat[0] = 0.0;
-  if (s >= m) return;
-  co.hat[1 + s] = co.gn_omega * c[s].x;
-  co.hat[1 + m + s] = co.rn_omega * c[s].y;
-}
 
 
 // ---- low-rank GMRES: time contraction on the spectrum (replaces the inverse FFT) ----
@@ -1208,6 +1258,17 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
   }
 }
 
+template <typename P, int N1, typename Src, typename Dst>
+hipError_t launch_rows_fn(const wc_plan &p, int nlines, Src src, Dst dst, int prof_id,
+                          double bytes) {
+  using R = RowCfg<P, N1>;
+  dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
+  ProfScope ps(p, prof_id, bytes);
+  hipLaunchKernelGGL((k_dst_rows_fn<P, N1, Src, Dst>), gr, dim3(64 * R::WPB), 0, p.stream,
+                     nlines, Tabs<P>::tws(p), Tabs<P>::sin(p), src, dst);
+  return hipGetLastError();
+}
+
 // x1 sine transform of nlines contiguous lines in place
 template <typename P, int N1>
 hipError_t dst_rows_on(const wc_plan &p, cx<P> *buf, int nlines, int prof_id, double bytes) {
@@ -1267,10 +1328,8 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
       hipLaunchKernelGGL(k_contract_pack, g1, dim3(kThreads), 0, p.stream, co->part, pk2, p.m);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = dst_rows_on<double, N1>(p, pk2, M, K_CONTRACT, 32.0 * p.m)) != hipSuccess) return e;
-    ProfScope ps(p, K_CONTRACT, 32.0 * p.m);
-    hipLaunchKernelGGL(k_contract_scale, g1, dim3(kThreads), 0, p.stream, pk2, *co, p.m);
-    return hipGetLastError();
+    return launch_rows_fn<double, N1>(p, M, PackedSrc{pk2, M}, StoreHat{*co, p.m, M},
+                                      K_CONTRACT, 32.0 * p.m);
   }
   ProfScope ps(p, K_DST_X1_INV, bytes);
   hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
@@ -1287,23 +1346,17 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
   const bool hoist = gen && p.dims == 2 && p.d_lr_spec;
-  if (hoist) {  // a1 + i a2 and its x1 sine transform (M lines)
-    {
-      ProfScope ps(p, K_LR_SETUP, 16.0 * p.m + 16.0 * p.m);
-      hipLaunchKernelGGL((k_lr_coef<P>), dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads),
-                         0, p.stream, *gen, (cx<P> *)p.d_lr_a, p.m);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-      switch (p.N1) {
-#define CASE_S(NN)                                                                           \
-  case NN:                                                                                   \
-    e = dst_rows_on<P, NN>(p, (cx<P> *)p.d_lr_a, p.M, K_LR_SETUP, 2.0 * p.m * sizeof(cx<P>)); \
+  if (hoist) {  // a1 + i a2, formed as its x1 sine transform (M lines) loads
+    const LrCoefSrc<P> src{*gen, p.m, p.M};
+    const StoreA<P> dst{(cx<P> *)p.d_lr_a, p.M};
+    switch (p.N1) {
+#define CASE_S(NN)                                                                            \
+  case NN:                                                                                    \
+    e = launch_rows_fn<P, NN>(p, p.M, src, dst, K_LR_SETUP, 32.0 * p.m + p.m * sizeof(cx<P>)); \
     break;
-        WC_POW2_CASES(CASE_S)
+      WC_POW2_CASES(CASE_S)
 #undef CASE_S
-        default: return hipErrorInvalidValue;
-      }
+      default: return hipErrorInvalidValue;
     }
   } else {
     switch (p.n) {
