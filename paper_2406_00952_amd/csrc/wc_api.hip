@@ -26,7 +26,7 @@ const char *kernel_name(int id) {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
       "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re", "mg_smooth", "mg_restrict",
-      "mg_lds", "mg_norm", "mg_mix", "lr_setup", "contract"};
+      "mg_lds", "mg_norm", "mg_mix", "lr_setup", "contract", "pair_contract"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -1056,6 +1056,16 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   if (e != hipSuccess) return WC_E_HIP;
   if (ts_out) *ts_out = bts;
   if (tx_out) *tx_out = btx;
+  return WC_OK;
+}
+
+wc_status wc_plan_forms(const wc_plan *p, int out[5]) {
+  if (!p || !out) return WC_E_ARG;
+  out[0] = p->ts_time;
+  out[1] = p->tx_cols;
+  out[2] = p->tx_contract;
+  out[3] = p->contract_opq ? 1 : 0;
+  out[4] = p->contract_pf ? 1 : 0;
   return WC_OK;
 }
 

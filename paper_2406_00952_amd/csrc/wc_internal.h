@@ -79,7 +79,7 @@ enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
   K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_MG_SMOOTH, K_MG_RESTRICT,
-  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_CONTRACT, K_COUNT
+  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_CONTRACT, K_PAIR_CONTRACT, K_COUNT
 };
 const char *kernel_name(int id);
 

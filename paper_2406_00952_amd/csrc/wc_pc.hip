@@ -441,6 +441,8 @@ template <typename P, int N1, int TX> struct ColCfg {
   static constexpr int PN = padded<PS>(N1);
   static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);
   static constexpr int S = 2 * TX + 1;
+  static constexpr int CPW = TX / WAVES;                    // columns per wave
+  static constexpr int MIT = (CPW * (N1 - 1) + 63) / 64;    // lane items of a wave's columns
   static constexpr int TILE = PN * S * CXB;
   static constexpr bool FITS = TILE <= kCuLds - 1024;
   static constexpr bool TAB_LDS = blocks_per_cu(TILE + TAB) == blocks_per_cu(TILE);
@@ -880,8 +882,10 @@ __device__ __forceinline__ void cols_tile_load(cx<P> *__restrict__ W, const Cols
   }
 }
 
-// ACC: instead of writing the tile back, add 2 Re(rho_h[q] Z) of every output to acc (the
-// thread's outputs in store order; rho_h = rho[h nq + q]).
+// ACC: stop after the per-mode solve and add 2 Re(rho_h[q] Zhat) of every solved mode to
+// acc (rho_h = rho[h nq + q]; lane item it of the wave's columns holds block row 0 in
+// acc[2 it] and row 1 in acc[2 it + 1]).  The inverse x2 transform is a real matrix, so it
+// commutes with this real-part sum over frequencies: the caller applies it once to the sum.
 // PRE: the tile's loads arrive in pra/prb (issued earlier); tile tn's loads (tn >= 0) are
 // issued into them while this tile is transformed.
 template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false,
@@ -954,6 +958,22 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   cx<P> *wb = buf + wv * 2 * CPW;
   wdst_core<P, N1, 2 * CPW, S, PS>(wb, tw, lane);
   const cx<P> l = lam[q];
+  if constexpr (ACC) {
+    const cx<double> r0 = rho[q], r1 = rho[nq + q];
+#pragma unroll
+    for (int it = 0; it < C::MIT; ++it) {
+      const int idx = lane + 64 * it;
+      const int c = idx / M, j2 = idx % M;
+      const int j1 = c0 + wv * CPW + c;
+      if (idx >= CPW * M || j1 >= M) continue;
+      cx<P> a = wb[pk<PS>(j2 + 1) * S + 2 * c];
+      cx<P> bb = wb[pk<PS>(j2 + 1) * S + 2 * c + 1];
+      mode_op<P>(a, bb, l, mu[j1] + mu[j2], kind, tau, alpha, cnorm);
+      acc[2 * it] += 2.0 * (r0.x * (double)a.x - r0.y * (double)a.y);
+      acc[2 * it + 1] += 2.0 * (r1.x * (double)bb.x - r1.y * (double)bb.y);
+    }
+    return;
+  }
   for (int idx = lane; idx < CPW * M; idx += 64) {
     const int c = idx / M, j2 = idx % M;
     const int j1 = c0 + wv * CPW + c;
@@ -967,20 +987,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   wave_sync();
   wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
   __syncthreads();
-  if constexpr (ACC) {
-    const cx<double> r0 = rho[q], r1 = rho[nq + q];
-    constexpr int CIT = (TT + NT - 1) / NT;
-#pragma unroll
-    for (int it = 0; it < CIT; ++it) {
-      const int idx = tid + it * NT;
-      if (TT % NT == 0 || idx < TT) {
-        const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
-        const cx<P> z = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
-        const cx<double> r = h ? r1 : r0;
-        acc[it] += 2.0 * (r.x * (double)z.x - r.y * (double)z.y);
-      }
-    }
-  } else {
+  {
     for (int idx = tid; idx < TT; idx += NT) {
       const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
       if (c0 + c < M)
@@ -1030,7 +1037,7 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
     const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm, ColsGen<P> cg,
     const cx<double> *__restrict__ rho, int nq, double *__restrict__ part) {
   using C = ColCfg<P, N1, TX>;
-  constexpr int M = N1 - 1, TT = 2 * TX * M, NT = C::NT, CIT = (TT + NT - 1) / NT;
+  constexpr int M = N1 - 1, TT = 2 * TX * M, NT = C::NT, CPW = C::CPW, S = C::S, PS = C::PS;
   __shared__ cx<P> buf[C::PN * C::S];
   __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
   __shared__ P ssin[C::TAB_LDS ? N1 : 1];
@@ -1039,9 +1046,10 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
   const int chunk = t / ncx, ct = t % ncx;
   const int per = (nq + kColChunks - 1) / kColChunks;
   const int q0 = chunk * per, q1 = q0 + per < nq ? q0 + per : nq;
-  double acc[CIT];
+  // the chunk's sums in x2 sine coordinates, two block rows per lane item
+  double acc[2 * C::MIT];
 #pragma unroll
-  for (int it = 0; it < CIT; ++it) acc[it] = 0.0;
+  for (int it = 0; it < 2 * C::MIT; ++it) acc[it] = 0.0;
   // (the spectrum argument is not written in this mode)
   cx<P> *const W0 = const_cast<cx<P> *>(cg.Y0);
   if constexpr (PF) {  // the next frequency's loads are in flight while one is transformed
@@ -1063,14 +1071,29 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
       __syncthreads();  // the next frequency reuses the LDS
     }
   }
-  const size_t m = (size_t)M * M;
+  // one inverse x2 transform of the sums (a chunk without frequencies writes zeros; its
+  // workgroup never loaded the tables)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cx<P> *wb = buf + wv * 2 * CPW;
 #pragma unroll
-  for (int it = 0; it < CIT; ++it) {
-    const int idx = threadIdx.x + it * NT;
-    if (TT % NT == 0 || idx < TT) {
-      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX), j1 = ct * TX + c;
-      if (j1 < M) part[(size_t)chunk * 2 * m + h * m + (size_t)x2 * M + j1] = acc[it];
+  for (int it = 0; it < C::MIT; ++it) {
+    const int idx = lane + 64 * it;
+    if (idx < CPW * M) {
+      const int c = idx / M, j2 = idx % M;
+      wb[pk<PS>(j2 + 1) * S + 2 * c] = cx<P>{(P)acc[2 * it], (P)0};
+      wb[pk<PS>(j2 + 1) * S + 2 * c + 1] = cx<P>{(P)acc[2 * it + 1], (P)0};
     }
+  }
+  wave_sync();
+  if (q0 < q1)
+    wdst<P, N1, 2 * CPW, S, PS>(wb, C::TAB_LDS ? stw : twg, C::TAB_LDS ? ssin : sing, lane);
+  __syncthreads();
+  const size_t m = (size_t)M * M;
+  for (int idx = threadIdx.x; idx < TT; idx += NT) {
+    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX), j1 = ct * TX + c;
+    if (j1 < M)
+      part[(size_t)chunk * 2 * m + h * m + (size_t)x2 * M + j1] =
+          (double)buf[pk<PS>(x2 + 1) * S + 2 * c + h].x;
   }
 }
 
@@ -1231,7 +1254,7 @@ hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
     if constexpr (TX == 16) {  // the contracting pass has 4- and 8-column forms
       if (cg && co) return cols_tx<P, N1, 8>(p, kind, c, cg, co);
     } else if (cg && co) {  // generated input, contracted over time (low-rank step)
-      ProfScope ps(p, K_PAIR_MODE, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
+      ProfScope ps(p, K_PAIR_CONTRACT, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
 #define WC_CC(OPQ, PF)                                                                     \
   hipLaunchKernelGGL((k_cols_contract<P, N1, TX, OPQ, PF>), dim3(kColChunks * ncx),          \
                      dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),              \
