@@ -148,12 +148,10 @@ def log(*a):
 KERNEL_SOURCE = {"tfft": "wc_pc.hip", "dst": "wc_pc.hip", "pair": "wc_pc.hip", "mg": "wc_mg.hip"}
 
 
-def measured_traffic(kernel, workload, args, forms):
+def measured_traffic(kernel, workload, args):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     profiles/<kernel>_<workload>_pmc.md (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy),
-    or None when there is none for this configuration or the kernel's source changed since.
-    The contracting x2 pass has eight forms (chosen by the autotuner): its summary gives the
-    traffic of each, and the one this plan launches is taken."""
+    or None when there is none for this configuration or the kernel's source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.md")
     if not os.path.exists(path) or args.precision != "fp64" or args.method != "gmres_ps":
@@ -166,13 +164,9 @@ def measured_traffic(kernel, workload, args, forms):
     src = KERNEL_SOURCE.get(kernel.split("_")[0], "wc_ops.hip")
     with open(os.path.join(ROOT, "paper_2406_00952_amd", "csrc", src), "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
-    key = "traffic_bytes_per_launch"
-    if kernel == "pair_contract":
-        key += (f".tx{forms['tx_contract']}_opq{forms['contract_opq']}"
-                f"_pf{forms['contract_pf']}")
-    if fields.get("source_sha256") != digest or key not in fields:
+    if fields.get("source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
         return None
-    return float(fields[key])
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(args, d, gpu_iters):
@@ -431,8 +425,7 @@ def main():
                   for k, v in pc_stats.items() if v[0] > 0}
 
     workload = (f"heat{args.dims}d{'_sin' if args.coeff == 'sin' else ''}_M{args.M}_n{args.n}")
-    forms = plan.forms()
-    traffic = measured_traffic(dom, workload, args, forms)
+    traffic = measured_traffic(dom, workload, args)
     out = {
         "metric": "solve ms to 1e-8 rel. residual; PC-apply HBM GB/s; p50/p99 served latency",
         "value": round(ms_per_step, 3),
@@ -449,7 +442,6 @@ def main():
                    "precision": args.precision, "restart": args.restart, "tol": 1e-8,
                    "flexible": bool(args.flexible) and not args.lowrank,
                    "lowrank": bool(args.lowrank), "tiles_ts_tx": list(tiles),
-                   "forms": forms,
                    "mg_tol": args.mg_tol if args.coeff == "sin" else None,
                    "mg_cycles": args.mg_cycles if args.coeff == "sin" else None,
                    "dof": 2 * n * m, "seed": args.seed},

@@ -148,19 +148,9 @@ wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
 /* Times the preconditioner apply (reps applies per candidate, after one warm-up)
  * for every time-FFT tile width (4, 8, 16 spatial columns per workgroup) and,
  * in 2D with a = 1, every x2-pass tile width (4, 8, 16 columns), keeps the
- * fastest pair in the plan and reports it (ts, tx may be NULL).  A 2D low-rank
- * GMRES plan also times the eight forms of its contracting x2 pass (see
- * wc_plan_forms) on placeholder data and keeps the fastest.  Uses the plan's
- * Krylov vectors and low-rank buffers as scratch: call it between solves.
- * Synchronous. */
+ * fastest pair in the plan and reports it (ts, tx may be NULL).  Uses the plan's
+ * Krylov vectors as scratch: call it between solves.  Synchronous. */
 wc_status wc_plan_autotune(wc_plan *plan, int reps, int *ts, int *tx);
-/* The kernel forms the plan launches (host only, no GPU call).  out[0]: time-FFT
- * tile width; out[1]: x2-pass tile width; out[2]: tile width (4 or 8 columns) of
- * the contracting x2 pass of the 2D low-rank GMRES step; out[3]: 1 if that pass
- * keeps its address arithmetic per frequency, 0 if the compiler may hoist it;
- * out[4]: 1 if it loads the next frequency's inputs ahead.  0 in out[0..2] means
- * the built-in default.  WC_E_ARG for a NULL argument. */
-wc_status wc_plan_forms(const wc_plan *plan, int out[5]);
 
 /* Right-hand side of the transformed system (Section 1: f_tilde, g_tilde
  * with M = I; eqn:main_system / eqn:main_system_nonsym).

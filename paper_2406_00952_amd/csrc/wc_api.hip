@@ -26,7 +26,7 @@ const char *kernel_name(int id) {
       "tfft_fwd", "dst_x1_fwd", "pair_mode", "dst_x1_inv", "tfft_inv", "matvec", "rhs",
       "recover", "lincomb3", "dot", "finalize", "minres_update", "minres_scalar", "multidot",
       "multiaxpy", "scale", "fill", "multidot_re", "multiaxpy_re", "mg_smooth", "mg_restrict",
-      "mg_lds", "mg_norm", "mg_mix", "lr_setup", "contract", "pair_contract"};
+      "mg_lds", "mg_norm", "mg_mix", "lr_setup", "contract", "pair_contract", "dst_x2_fwd"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -1014,41 +1014,6 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
     }
   p->ts_time = bts;
   p->tx_cols = btx;
-  // 2D low-rank GMRES: the contracting x2 pass loops over frequencies and keeps more
-  // registers live, so its tile width is timed on its own (on placeholder data)
-  if (e == hipSuccess && p->d_lr_spec) {
-    const size_t spec_doubles = (size_t)p->n * p->m * (p->opts.precision == WC_MIXED ? 1 : 2);
-    double *hat = p->d_lr_hat, *hat_out = p->d_lr_hat + p->lr_len;
-    e = launch_fill(*p, p->d_lr_spec, 1e-3, spec_doubles);
-    if (e == hipSuccess) e = launch_fill(*p, hat, 1.0, p->lr_len);
-    if (e == hipSuccess) e = launch_fill(*p, p->d_lr_s0, 0.0, 2 * (size_t)p->m);
-    if (e == hipSuccess) e = launch_fill(*p, p->d_scal + S_LR_SQN0, 1.0, 1);
-    float bestc = -1.f;
-    int bc = 0;
-    bool bo = false, bp = false;
-    for (int ic = 0; ic < 8 && e == hipSuccess; ++ic) {
-      p->tx_contract = (ic & 1) ? 8 : 4;
-      p->contract_opq = (ic & 2) != 0;
-      p->contract_pf = (ic & 4) != 0;
-      e = launch_pc_lowrank(*p, v, hat, hat_out, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(a, p->stream);
-      for (int r = 0; r < reps && e == hipSuccess; ++r)
-        e = launch_pc_lowrank(*p, v, hat, hat_out, nullptr);
-      if (e == hipSuccess) e = hipEventRecord(b, p->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      if (e == hipSuccess && (bestc < 0.f || ms < bestc)) {
-        bestc = ms;
-        bc = p->tx_contract;
-        bo = p->contract_opq;
-        bp = p->contract_pf;
-      }
-    }
-    p->tx_contract = bc;
-    p->contract_opq = bo;
-    p->contract_pf = bp;
-  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   p->prof.on = prof;
@@ -1056,16 +1021,6 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   if (e != hipSuccess) return WC_E_HIP;
   if (ts_out) *ts_out = bts;
   if (tx_out) *tx_out = btx;
-  return WC_OK;
-}
-
-wc_status wc_plan_forms(const wc_plan *p, int out[5]) {
-  if (!p || !out) return WC_E_ARG;
-  out[0] = p->ts_time;
-  out[1] = p->tx_cols;
-  out[2] = p->tx_contract;
-  out[3] = p->contract_opq ? 1 : 0;
-  out[4] = p->contract_pf ? 1 : 0;
   return WC_OK;
 }
 

@@ -79,7 +79,7 @@ enum KernelId : int {
   K_TFFT_FWD = 0, K_DST_X1_FWD, K_PAIR_MODE, K_DST_X1_INV, K_TFFT_INV, K_MATVEC, K_RHS,
   K_RECOVER, K_LINCOMB, K_DOT, K_FINALIZE, K_MINRES_UPDATE, K_MINRES_SCALAR, K_MULTIDOT,
   K_MULTIAXPY, K_SCALE, K_FILL, K_MULTIDOT_RE, K_MULTIAXPY_RE, K_MG_SMOOTH, K_MG_RESTRICT,
-  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_CONTRACT, K_PAIR_CONTRACT, K_COUNT
+  K_MG_LDS, K_MG_NORM, K_MG_MIX, K_LR_SETUP, K_CONTRACT, K_PAIR_CONTRACT, K_DST_X2_FWD, K_COUNT
 };
 const char *kernel_name(int id);
 
@@ -113,9 +113,6 @@ struct wc_plan {
   int num_cu = 256;              // compute units of the plan's device
   int ts_time = 0;               // time-FFT tile width (0: default)
   int tx_cols = 0;               // x2-pass tile width (0: default)
-  int tx_contract = 0;           // tile width of the contracting x2 pass (0: as tx_cols)
-  bool contract_opq = false;     // its address arithmetic recomputed per frequency
-  bool contract_pf = false;      // the next frequency's loads issued ahead
   wc_opts opts{};
   hipStream_t stream = nullptr;
   size_t nvec = 0;          // 2*n*m
@@ -167,12 +164,13 @@ struct wc_plan {
   double *d_lr_s0 = nullptr;        // 2m
   double *d_lr_hat = nullptr;       // (restart + 2) compact vectors of lr_len
   double *d_lr_rho = nullptr;       // n complex: contraction weights per kept frequency
-  double *d_lr_part = nullptr;      // kContractChunks x 2m
-  // 2D: the time transform is linear and r0 is fixed within a cycle, so the Arnoldi steps
-  // take the spectrum of c r0 + [g (x) a1; r (x) a2] from these instead of transforming
+  double *d_lr_part = nullptr;      // max(kContractChunks, kColChunks) x 2m
+  // 2D: the time and sine transforms are linear and r0 is fixed within a cycle, so the
+  // Arnoldi steps take the spectrum of c r0 + [g (x) a1; r (x) a2] from these instead of
+  // transforming (the x1 and x2 transforms of r0's spectrum sit in d_specA for the cycle)
   double *d_lr_spec = nullptr;      // time and x1 transforms of the cycle's r0 (spectral layout)
   double *d_lr_rank = nullptr;      // n/2 x 2 halves x 2 complex: spectra of g and of r
-  double *d_lr_a = nullptr;         // m complex: a1 + i a2 of the current vector, x1-transformed
+  double *d_lr_a = nullptr;         // m complex: a1 + i a2 of the current vector, sine-transformed
 
   mutable wc::Profiler prof;
   // captured Krylov iterations: GMRES step j in slot j (first restart cycle) or
@@ -235,10 +233,10 @@ struct ContractOut {
   double *hat;
   double gn_omega, rn_omega;
   const double *rho;   // n complex: rho_r[q] then rho_g[q], q < n/2 (frequency l = q + 1)
-  double *part;        // kContractChunks x 2m partial sums
+  double *part;        // chunks x 2m partial sums (1D: kContractChunks, 2D: kColChunks)
 };
 // frequency chunks of the contraction kernels (deterministic two-stage sums): 1D, and the
-// 2D x2 pass (more chunks: its workgroups are chunks x column tiles)
+// 2D pointwise step (more chunks: its grid is chunks x m / 256 workgroups)
 constexpr int kContractChunks = 8;
 constexpr int kColChunks = 16;
 
@@ -303,7 +301,7 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
 // ||r0||^2 in d_scal[S_DOT] (launch_dot before).
 hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
 // 2D low-rank GMRES: time transform and x1 sine transform of the cycle's r0 into
-// d_lr_spec (once per cycle)
+// d_lr_spec, and its x2 sine transform into d_specA (once per cycle)
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0);
 bool pc_supported(int n, int N1);
 

@@ -772,6 +772,15 @@ struct StoreHat {
 };
 
 
+// x2 lines (one per x1 index j1) of an m-point field [x2][j1], read and written in place:
+// the x2 sine transform of A and the inverse x2 transform of the packed sums
+template <typename T> struct ColLine {
+  cx<T> *f;
+  int M;
+  __device__ cx<T> operator()(int j1, int x2) const { return f[x2 * M + j1]; }
+  __device__ void operator()(int j1, int x2, cx<T> v) const { f[x2 * M + j1] = v; }
+};
+
 // ---- 1D: DST, step 2, inverse DST on both block rows of each frequency, in place ----
 // W layout [q][half][x]; every wave owns UNITS frequencies (2*UNITS lines) at a time.
 template <typename P, int N1>
@@ -882,32 +891,39 @@ __device__ __forceinline__ void cols_tile_load(cx<P> *__restrict__ W, const Cols
   }
 }
 
-// ACC: stop after the per-mode solve and add 2 Re(rho_h[q] Zhat) of every solved mode to
-// acc (rho_h = rho[h nq + q]; lane item it of the wave's columns holds block row 0 in
-// acc[2 it] and row 1 in acc[2 it + 1]).  The inverse x2 transform is a real matrix, so it
-// commutes with this real-part sum over frequencies: the caller applies it once to the sum.
-// PRE: the tile's loads arrive in pra/prb (issued earlier); tile tn's loads (tn >= 0) are
-// issued into them while this tile is transformed.
-template <typename P, int N1, int TX, bool TABL, bool GEN = false, bool ACC = false,
-          bool OPQ = false, bool PRE = false>
+// The first sine transform's pre-processing of a tile's loads (cols_tile_load order): item
+// (c, h, i) writes y_i and y_{N1-i} of tile column 2c+h, and slot 0 is cleared.
+template <typename P, int N1, int TX>
+__device__ __forceinline__ void cols_pre_lds(const cx<P> *ra, const cx<P> *rb, cx<P> *buf,
+                                             const P *sn, int tid) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int S = C::S, PS = C::PS, NT = C::NT, H = N1 / 2, TP = H * 2 * TX;
+  constexpr int LIT = (TP + NT - 1) / NT;
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (idx >= TP) continue;
+    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX), col = 2 * c + h;
+    const P sv = sn[i];
+    const cx<P> sum = cadd(ra[it], rb[it]);
+    const cx<P> dif = cscale(csub(ra[it], rb[it]), (P)0.5);
+    buf[pk<PS>(i) * S + col] = cadd(cscale(sum, sv), dif);
+    if (i != H) buf[pk<PS>(N1 - i) * S + col] = csub(cscale(sum, sv), dif);
+    if (i == 1) buf[col] = cx<P>{(P)0, (P)0};
+  }
+}
+
+template <typename P, int N1, int TX, bool TABL, bool GEN = false>
 __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
                                                const P *__restrict__ sing,
                                                const cx<P> *__restrict__ lam,
                                                const P *__restrict__ mu, int kind, P tau, P alpha,
                                                P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin,
-                                               ColsGen<P> cg = {},
-                                               const cx<double> *__restrict__ rho = nullptr,
-                                               int nq = 0, double *acc = nullptr,
-                                               cx<P> *pra = nullptr, cx<P> *prb = nullptr,
-                                               int tn = -1) {
+                                               ColsGen<P> cg = {}) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
-  int tid = threadIdx.x;
-  // OPQ (a body repeated over frequencies): an opaque copy of the thread index keeps the
-  // compiler from hoisting the tile's address arithmetic out of that loop, where it would
-  // stay live across the whole body; the autotuner picks whichever form runs faster
-  if constexpr (OPQ) asm volatile("" : "+v"(tid));
+  const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int ncx = (N1 - 2 + TX) / TX;  // column tiles per frequency, M = N1 - 1 columns
   const int q = t / ncx;
@@ -923,16 +939,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   cx<P> ra[LIT], rb[LIT];
   double gc = 0.0;
   if constexpr (GEN) gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
-  if constexpr (PRE) {
-#pragma unroll
-    for (int it = 0; it < LIT; ++it) {
-      ra[it] = pra[it];
-      rb[it] = prb[it];
-    }
-    if (tn >= 0) cols_tile_load<P, N1, TX, GEN>(W, cg, tn, tid, gc, pra, prb);
-  } else {
-    cols_tile_load<P, N1, TX, GEN>(W, cg, t, tid, gc, ra, rb);
-  }
+  cols_tile_load<P, N1, TX, GEN>(W, cg, t, tid, gc, ra, rb);
   if constexpr (TABL) {
     for (int i = tid; i < N1; i += NT) {
       stw[i] = twg[i];
@@ -941,39 +948,12 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   }
   __syncthreads();  // the sine table is read below
   const P *sn = TABL ? ssin : sing;
-#pragma unroll
-  for (int it = 0; it < LIT; ++it) {
-    const int idx = tid + it * NT;
-    if (idx >= TP) continue;
-    const int c = idx % TX, h = (idx / TX) & 1, i = 1 + idx / (2 * TX), col = 2 * c + h;
-    const P sv = sn[i];
-    const cx<P> sum = cadd(ra[it], rb[it]);
-    const cx<P> dif = cscale(csub(ra[it], rb[it]), (P)0.5);
-    buf[pk<PS>(i) * S + col] = cadd(cscale(sum, sv), dif);
-    if (i != H) buf[pk<PS>(N1 - i) * S + col] = csub(cscale(sum, sv), dif);
-    if (i == 1) buf[col] = cx<P>{(P)0, (P)0};
-  }
+  cols_pre_lds<P, N1, TX>(ra, rb, buf, sn, tid);
   __syncthreads();
   const cx<P> *tw = TABL ? stw : twg;
   cx<P> *wb = buf + wv * 2 * CPW;
   wdst_core<P, N1, 2 * CPW, S, PS>(wb, tw, lane);
   const cx<P> l = lam[q];
-  if constexpr (ACC) {
-    const cx<double> r0 = rho[q], r1 = rho[nq + q];
-#pragma unroll
-    for (int it = 0; it < C::MIT; ++it) {
-      const int idx = lane + 64 * it;
-      const int c = idx / M, j2 = idx % M;
-      const int j1 = c0 + wv * CPW + c;
-      if (idx >= CPW * M || j1 >= M) continue;
-      cx<P> a = wb[pk<PS>(j2 + 1) * S + 2 * c];
-      cx<P> bb = wb[pk<PS>(j2 + 1) * S + 2 * c + 1];
-      mode_op<P>(a, bb, l, mu[j1] + mu[j2], kind, tau, alpha, cnorm);
-      acc[2 * it] += 2.0 * (r0.x * (double)a.x - r0.y * (double)a.y);
-      acc[2 * it + 1] += 2.0 * (r1.x * (double)bb.x - r1.y * (double)bb.y);
-    }
-    return;
-  }
   for (int idx = lane; idx < CPW * M; idx += 64) {
     const int c = idx / M, j2 = idx % M;
     const int j1 = c0 + wv * CPW + c;
@@ -987,12 +967,10 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   wave_sync();
   wdst<P, N1, 2 * CPW, S, PS>(wb, tw, sn, lane);
   __syncthreads();
-  {
-    for (int idx = tid; idx < TT; idx += NT) {
-      const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
-      if (c0 + c < M)
-        (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
-    }
+  for (int idx = tid; idx < TT; idx += NT) {
+    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+    if (c0 + c < M)
+      (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
   }
 }
 
@@ -1031,72 +1009,6 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
 // sine transform being real), so the spectrum is never written: workgroup (chunk, column
 // tile) runs the tile body for the frequencies of its chunk and writes its sums,
 // part[chunk][h m + x2 M + j1].
-template <typename P, int N1, int TX, bool OPQ, bool PF>
-__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_contract(
-    const cx<P> *__restrict__ twg, const P *__restrict__ sing, const cx<P> *__restrict__ lam,
-    const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm, ColsGen<P> cg,
-    const cx<double> *__restrict__ rho, int nq, double *__restrict__ part) {
-  using C = ColCfg<P, N1, TX>;
-  constexpr int M = N1 - 1, TT = 2 * TX * M, NT = C::NT, CPW = C::CPW, S = C::S, PS = C::PS;
-  __shared__ cx<P> buf[C::PN * C::S];
-  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
-  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
-  const int ncx = (N1 - 2 + TX) / TX;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int chunk = t / ncx, ct = t % ncx;
-  const int per = (nq + kColChunks - 1) / kColChunks;
-  const int q0 = chunk * per, q1 = q0 + per < nq ? q0 + per : nq;
-  // the chunk's sums in x2 sine coordinates, two block rows per lane item
-  double acc[2 * C::MIT];
-#pragma unroll
-  for (int it = 0; it < 2 * C::MIT; ++it) acc[it] = 0.0;
-  // (the spectrum argument is not written in this mode)
-  cx<P> *const W0 = const_cast<cx<P> *>(cg.Y0);
-  if constexpr (PF) {  // the next frequency's loads are in flight while one is transformed
-    constexpr int LIT = (N1 / 2 * 2 * TX + NT - 1) / NT;
-    cx<P> pra[LIT], prb[LIT];
-    const double gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
-    if (q0 < q1) cols_tile_load<P, N1, TX, true>(W0, cg, q0 * ncx + ct, threadIdx.x, gc, pra, prb);
-    for (int q = q0; q < q1; ++q) {
-      cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ, true>(
-          W0, twg, sing, lam, mu, kind, tau, alpha, cnorm, q * ncx + ct, buf, stw, ssin, cg, rho,
-          nq, acc, pra, prb, q + 1 < q1 ? (q + 1) * ncx + ct : -1);
-      __syncthreads();  // the next frequency reuses the LDS
-    }
-  } else {
-    for (int q = q0; q < q1; ++q) {
-      cols_mode_tile<P, N1, TX, C::TAB_LDS, true, true, OPQ>(W0, twg, sing, lam, mu, kind, tau,
-                                                             alpha, cnorm, q * ncx + ct, buf, stw,
-                                                             ssin, cg, rho, nq, acc);
-      __syncthreads();  // the next frequency reuses the LDS
-    }
-  }
-  // one inverse x2 transform of the sums (a chunk without frequencies writes zeros; its
-  // workgroup never loaded the tables)
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  cx<P> *wb = buf + wv * 2 * CPW;
-#pragma unroll
-  for (int it = 0; it < C::MIT; ++it) {
-    const int idx = lane + 64 * it;
-    if (idx < CPW * M) {
-      const int c = idx / M, j2 = idx % M;
-      wb[pk<PS>(j2 + 1) * S + 2 * c] = cx<P>{(P)acc[2 * it], (P)0};
-      wb[pk<PS>(j2 + 1) * S + 2 * c + 1] = cx<P>{(P)acc[2 * it + 1], (P)0};
-    }
-  }
-  wave_sync();
-  if (q0 < q1)
-    wdst<P, N1, 2 * CPW, S, PS>(wb, C::TAB_LDS ? stw : twg, C::TAB_LDS ? ssin : sing, lane);
-  __syncthreads();
-  const size_t m = (size_t)M * M;
-  for (int idx = threadIdx.x; idx < TT; idx += NT) {
-    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX), j1 = ct * TX + c;
-    if (j1 < M)
-      part[(size_t)chunk * 2 * m + h * m + (size_t)x2 * M + j1] =
-          (double)buf[pk<PS>(x2 + 1) * S + 2 * c + h].x;
-  }
-}
-
 // sums of the chunks, packed as C_0 + i C_1 per spatial point for the inverse x1 transform
 __global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__restrict__ part,
                                                             cx<double> *__restrict__ out,
@@ -1113,6 +1025,96 @@ __global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__rest
 }
 
 
+
+// x2 sine transform of both block rows of every frequency, out of place: the cycle's r0
+// spectrum in full sine coordinates, from which a 2D low-rank step works pointwise
+template <typename P, int N1, int TX>
+__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
+    const cx<P> *__restrict__ in, cx<P> *__restrict__ out, const cx<P> *__restrict__ twg,
+    const P *__restrict__ sing) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int M = N1 - 1, S = C::S, PS = C::PS, NT = C::NT, CPW = C::CPW, TT = 2 * TX * M;
+  constexpr int LIT = (N1 / 2 * 2 * TX + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int ncx = (N1 - 2 + TX) / TX;
+  const int q = t / ncx, c0 = (t % ncx) * TX;
+  cx<P> ra[LIT], rb[LIT];
+  cols_tile_load<P, N1, TX, false>(const_cast<cx<P> *>(in), ColsGen<P>{}, t, tid, 0.0, ra, rb);
+  if constexpr (C::TAB_LDS) {
+    for (int i = tid; i < N1; i += NT) {
+      stw[i] = twg[i];
+      ssin[i] = sing[i];
+    }
+  }
+  __syncthreads();
+  cols_pre_lds<P, N1, TX>(ra, rb, buf, C::TAB_LDS ? ssin : sing, tid);
+  __syncthreads();
+  wdst_core<P, N1, 2 * CPW, S, PS>(buf + wv * 2 * CPW, C::TAB_LDS ? stw : twg, lane);
+  __syncthreads();
+  cx<P> *o0 = out + (size_t)q * 2 * M * M;
+  for (int idx = tid; idx < TT; idx += NT) {
+    const int c = idx % TX, h = (idx / TX) & 1, j2 = idx / (2 * TX);
+    if (c0 + c < M)
+      o0[(size_t)h * M * M + (size_t)j2 * M + c0 + c] = buf[pk<PS>(j2 + 1) * S + 2 * c + h];
+  }
+}
+
+// 2D low-rank GMRES step, pointwise in full sine coordinates (both sine transforms are real
+// matrices, so they commute with forming the input and with the real-part sum over
+// frequencies).  For spatial mode s and frequency q the input is
+//   u_h = c Yhat0[q][h][s] + F[q][h][0] Re Ahat[s] + F[q][h][1] Im Ahat[s]  (h = 0, 1),
+// the per-mode solve maps (u_0, u_1) to (z_0, z_1), and
+//   part[chunk][h][s] = sum over the chunk's q of 2 Re(rho[h nq + q] z_h).
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_lr_contract(
+    const cx<P> *__restrict__ Yh, const cx<P> *__restrict__ Ah, const cx<double> *__restrict__ F,
+    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
+    const double *__restrict__ hat, const double *__restrict__ sqn0,
+    const cx<double> *__restrict__ rho, int nq, int M, double *__restrict__ part) {
+  constexpr int QB = 8;  // frequencies whose loads are issued together
+  const int m = M * M;
+  const int s = blockIdx.x * kThreads + threadIdx.x, chunk = blockIdx.y;
+  if (s >= m) return;
+  const int per = (nq + kColChunks - 1) / kColChunks;
+  const int q0 = chunk * per, q1 = q0 + per < nq ? q0 + per : nq;
+  const double gc = *sqn0 > 0.0 ? hat[0] / *sqn0 : 0.0;
+  const int j2 = s / M, j1 = s - j2 * M;
+  const P mus = mu[j1] + mu[j2];
+  const cx<P> a = Ah[s];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int qb = q0; qb < q1; qb += QB) {
+    cx<P> y0[QB], y1[QB];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      if (qb + u < q1) {
+        y0[u] = load_stream(Yh + (size_t)(qb + u) * 2 * m + s);
+        y1[u] = load_stream(Yh + ((size_t)(qb + u) * 2 + 1) * m + s);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u) {
+      const int q = qb + u;
+      if (q < q1) {
+        const cx<double> f00 = F[q * 4], f01 = F[q * 4 + 1], f10 = F[q * 4 + 2],
+                         f11 = F[q * 4 + 3];
+        cx<P> z0{(P)(gc * y0[u].x + f00.x * a.x + f01.x * a.y),
+                 (P)(gc * y0[u].y + f00.y * a.x + f01.y * a.y)};
+        cx<P> z1{(P)(gc * y1[u].x + f10.x * a.x + f11.x * a.y),
+                 (P)(gc * y1[u].y + f10.y * a.x + f11.y * a.y)};
+        mode_op<P>(z0, z1, lam[q], mus, kind, tau, alpha, cnorm);
+        const cx<double> r0 = rho[q], r1 = rho[nq + q];
+        acc0 += 2.0 * (r0.x * (double)z0.x - r0.y * (double)z0.y);
+        acc1 += 2.0 * (r1.x * (double)z1.x - r1.y * (double)z1.y);
+      }
+    }
+  }
+  part[(size_t)chunk * 2 * m + s] = acc0;
+  part[(size_t)chunk * 2 * m + m + s] = acc1;
+}
 
 // ---- low-rank GMRES: time contraction on the spectrum (replaces the inverse FFT) ----
 // part[c][s] = sum over the frequencies q of chunk c of 2 Re(rho_r[q] A_q[s]), and
@@ -1244,29 +1246,12 @@ hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *np
 }
 
 template <typename P, int N1, int TX>
-hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg,
-                   const ContractOut *co) {
+hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg) {
   if constexpr (!ColCfg<P, N1, TX>::FITS) {
-    return cols_tx<P, N1, 4>(p, kind, c, cg, co);
+    return cols_tx<P, N1, 4>(p, kind, c, cg);
   } else {
     constexpr int M = N1 - 1;
     const int ncx = (M + TX - 1) / TX;
-    if constexpr (TX == 16) {  // the contracting pass has 4- and 8-column forms
-      if (cg && co) return cols_tx<P, N1, 8>(p, kind, c, cg, co);
-    } else if (cg && co) {  // generated input, contracted over time (low-rank step)
-      ProfScope ps(p, K_PAIR_CONTRACT, p.nvec * (double)sizeof(P) + 16.0 * kColChunks * p.m);
-#define WC_CC(OPQ, PF)                                                                     \
-  hipLaunchKernelGGL((k_cols_contract<P, N1, TX, OPQ, PF>), dim3(kColChunks * ncx),          \
-                     dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, Tabs<P>::tws(p),              \
-                     Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,       \
-                     (P)p.alpha, (P)c, *cg, (const cx<double> *)co->rho, p.n / 2, co->part)
-      if (p.contract_opq && p.contract_pf) WC_CC(true, true);
-      else if (p.contract_opq) WC_CC(true, false);
-      else if (p.contract_pf) WC_CC(false, true);
-      else WC_CC(false, false);
-#undef WC_CC
-      return hipGetLastError();
-    }
     dim3 gc(ncx * (p.n / 2));
     ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
     if (cg)
@@ -1304,7 +1289,7 @@ hipError_t dst_rows_on(const wc_plan &p, cx<P> *buf, int nlines, int prof_id, do
 }
 
 template <typename P, int N1>
-hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_gen = nullptr) {
+hipError_t run_space(const wc_plan &p, const GenIn *rows_gen = nullptr) {
   using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
@@ -1333,27 +1318,12 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
   }
   if (e != hipSuccess) return e;
   const ColsGen<P> *cgp = rows_gen ? &cg : nullptr;
-  const ContractOut *cop = rows_gen ? co : nullptr;
-  int tx = p.tx_cols ? p.tx_cols : default_tx<P, N1>();
-  if (cop && p.tx_contract) tx = p.tx_contract;
-  switch (tx) {
-    case 4: e = cols_tx<P, N1, 4>(p, kind, c, cgp, cop); break;
-    case 16: e = cols_tx<P, N1, 16>(p, kind, c, cgp, cop); break;
-    default: e = cols_tx<P, N1, 8>(p, kind, c, cgp, cop); break;
+  switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
+    case 4: e = cols_tx<P, N1, 4>(p, kind, c, cgp); break;
+    case 16: e = cols_tx<P, N1, 16>(p, kind, c, cgp); break;
+    default: e = cols_tx<P, N1, 8>(p, kind, c, cgp); break;
   }
   if (e != hipSuccess) return e;
-  if (co) {  // low-rank GMRES step: sum the chunks, inverse x1 transform of C_0 + i C_1
-    if (!rows_gen) return hipErrorInvalidValue;
-    cx<double> *pk2 = (cx<double> *)p.d_lr_a;  // free again once the x2 pass has run
-    const dim3 g1((p.m + kThreads - 1) / kThreads);
-    {
-      ProfScope ps(p, K_CONTRACT, 16.0 * kColChunks * p.m + 16.0 * p.m);
-      hipLaunchKernelGGL(k_contract_pack, g1, dim3(kThreads), 0, p.stream, co->part, pk2, p.m);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return launch_rows_fn<double, N1>(p, M, PackedSrc{pk2, M}, StoreHat{*co, p.m, M},
-                                      K_CONTRACT, 32.0 * p.m);
-  }
   ProfScope ps(p, K_DST_X1_INV, bytes);
   hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream,
                      W, nlines, Tabs<P>::tws(p), Tabs<P>::sin(p));
@@ -1362,6 +1332,48 @@ hipError_t run_space(const wc_plan &p, const ContractOut *co, const GenIn *rows_
 
 #define WC_POW2_CASES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
+// 2D low-rank GMRES step E v in compact coordinates, all in full sine coordinates: A (a1 + i
+// a2 of the compact vector) by its x1 then x2 sine transforms, the pointwise solve and
+// contraction over frequencies against the cycle's Yhat0 (held in the spectrum array since
+// the cycle began), the chunk sums packed as C_0 + i C_1, and their inverse x2 then x1
+// transforms written as the compact output.
+template <typename P, int N1>
+hipError_t lr_step_t(const wc_plan &p, const GenIn &gen, const ContractOut &co) {
+  constexpr int M = N1 - 1;
+  const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
+  const double c = (1.0 / p.n) * (2.0 / N1) * (2.0 / N1);
+  cx<P> *A = (cx<P> *)p.d_lr_a;
+  hipError_t e = launch_rows_fn<P, N1>(p, M, LrCoefSrc<P>{gen, p.m, M}, StoreA<P>{A, M},
+                                       K_LR_SETUP, 32.0 * p.m + p.m * sizeof(cx<P>));
+  if (e != hipSuccess) return e;
+  e = launch_rows_fn<P, N1>(p, M, ColLine<P>{A, M}, ColLine<P>{A, M}, K_LR_SETUP,
+                            2.0 * p.m * sizeof(cx<P>));
+  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(p, K_PAIR_CONTRACT,
+                 p.nvec * (double)sizeof(P) + p.m * (double)sizeof(cx<P>) +
+                     16.0 * kColChunks * p.m);
+    hipLaunchKernelGGL(k_lr_contract<P>, dim3((p.m + kThreads - 1) / kThreads, kColChunks),
+                       dim3(kThreads), 0, p.stream, (const cx<P> *)p.d_specA,
+                       (const cx<P> *)A, (const cx<double> *)p.d_lr_rank, Tabs<P>::lam(p),
+                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c, gen.hat, gen.sqn0,
+                       (const cx<double> *)co.rho, p.n / 2, M, co.part);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  cx<double> *pk2 = (cx<double> *)p.d_lr_a;  // A is free again once the contraction has run
+  {
+    ProfScope ps(p, K_CONTRACT, 16.0 * kColChunks * p.m + 16.0 * p.m);
+    hipLaunchKernelGGL(k_contract_pack, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, p.stream, co.part, pk2, p.m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  e = launch_rows_fn<double, N1>(p, M, ColLine<double>{pk2, M}, ColLine<double>{pk2, M},
+                                 K_CONTRACT, 32.0 * p.m);
+  if (e != hipSuccess) return e;
+  return launch_rows_fn<double, N1>(p, M, PackedSrc{pk2, M}, StoreHat{co, p.m, M}, K_CONTRACT,
+                                    32.0 * p.m);
+}
+
 template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
@@ -1369,6 +1381,15 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
   const bool hoist = gen && p.dims == 2 && p.d_lr_spec;
+  if (hoist && co) {
+    *nparts = 0;
+    switch (p.N1) {
+#define CASE_S(NN) case NN: return lr_step_t<P, NN>(p, *gen, *co);
+      WC_POW2_CASES(CASE_S)
+#undef CASE_S
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (hoist) {  // a1 + i a2, formed as its x1 sine transform (M lines) loads
     const LrCoefSrc<P> src{*gen, p.m, p.M};
     const StoreA<P> dst{(cx<P> *)p.d_lr_a, p.M};
@@ -1394,19 +1415,20 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
     e = mg_space_apply(p);
   } else {
     switch (p.N1) {
-#define CASE_S(NN) case NN: e = run_space<P, NN>(p, co, hoist ? gen : nullptr); break;
+#define CASE_S(NN) case NN: e = run_space<P, NN>(p, hoist ? gen : nullptr); break;
       WC_POW2_CASES(CASE_S)
 #undef CASE_S
       default: return hipErrorInvalidValue;
     }
   }
   if (e != hipSuccess) return e;
-  if (co) {  // low-rank GMRES: contract over time on the spectrum
-    const int nq = p.n / 2;
-    if (p.dims == 1) {  // 2D: the inverse x1 pass already contracted
-      if constexpr (!std::is_same<P, double>::value) {
-        return hipErrorInvalidValue;  // the 1D low-rank form is FP64 only
-      } else {
+  if (co) {  // 1D low-rank GMRES: contract over time on the spectrum (2D: lr_step_t)
+    if (p.dims != 1) return hipErrorInvalidValue;
+    if constexpr (!std::is_same<P, double>::value) {
+      return hipErrorInvalidValue;  // the 1D low-rank form is FP64 only
+    } else {
+      const int nq = p.n / 2;
+      {
         ProfScope ps(p, K_CONTRACT, (double)p.n * p.m * sizeof(cx<double>) +
                                         16.0 * kContractChunks * p.m);
         hipLaunchKernelGGL(k_contract_freq, dim3((p.m + kThreads - 1) / kThreads, kContractChunks),
@@ -1414,13 +1436,12 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
                            nq);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
+      *nparts = 0;
+      ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
+      hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads),
+                         0, p.stream, *co, p.m);
+      return hipGetLastError();
     }
-    *nparts = 0;
-    if (p.dims == 2) return hipSuccess;  // 2D: the x2 pass and its tail contracted
-    ProfScope ps(p, K_CONTRACT, 16.0 * kContractChunks * p.m + 16.0 * p.m);
-    hipLaunchKernelGGL(k_contract_final, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       p.stream, *co, p.m);
-    return hipGetLastError();
   }
   switch (p.n) {
 #define CASE_N(NN) case NN: e = run_tfft_inv<P, NN>(p, w, dotv, nparts); break;
@@ -1790,6 +1811,22 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
 }
 
 namespace {
+// x2 sine transform of the whole spectrum (the cycle's Yhat0 for the pointwise step)
+template <typename P, int N1>
+hipError_t cols_dst_t(const wc_plan &p, const cx<P> *in, cx<P> *out) {
+  constexpr int TX = default_tx<P, N1>();
+  if constexpr (!ColCfg<P, N1, TX>::FITS) {
+    return hipErrorInvalidValue;
+  } else {
+    const int ncx = (N1 - 2 + TX) / TX;
+    ProfScope ps(p, K_DST_X2_FWD, 2.0 * p.nvec * sizeof(P));
+    hipLaunchKernelGGL((k_cols_dst<P, N1, TX>), dim3(ncx * (p.n / 2)),
+                       dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, in, out, Tabs<P>::tws(p),
+                       Tabs<P>::sin(p));
+    return hipGetLastError();
+  }
+}
+
 template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r0) {
   hipError_t e = hipErrorInvalidValue;
   cx<P> *Y = (cx<P> *)p.d_lr_spec;
@@ -1802,8 +1839,11 @@ template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r
   if (e != hipSuccess) return e;
   const int nlines = p.n * p.M;
   switch (p.N1) {
-#define CASE_S(NN) \
-  case NN: return dst_rows_on<P, NN>(p, Y, nlines, K_DST_X1_FWD, 2.0 * p.nvec * sizeof(P));
+#define CASE_S(NN)                                                                 \
+  case NN:                                                                         \
+    e = dst_rows_on<P, NN>(p, Y, nlines, K_DST_X1_FWD, 2.0 * p.nvec * sizeof(P));  \
+    if (e == hipSuccess) e = cols_dst_t<P, NN>(p, Y, (cx<P> *)p.d_specA);          \
+    return e;
     WC_POW2_CASES(CASE_S)
 #undef CASE_S
     default: return hipErrorInvalidValue;

@@ -73,7 +73,6 @@ _lib.wc_plan_destroy.argtypes = [_vp]
 _lib.wc_plan_retarget.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Opts)]
 _lib.wc_plan_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int)]
-_lib.wc_plan_forms.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _lib.wc_plan_set_stream.argtypes = [_vp, _vp]
 _lib.wc_rhs.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.wc_matvec.argtypes = [_vp, _vp, _vp]
@@ -105,13 +104,12 @@ for _f in ("wc_batch_create", "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch
 for _f in ("wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
            "wc_server_wait", "wc_server_cancel"):
     getattr(_lib, _f).restype = ctypes.c_int
-for _f in ("wc_plan_retarget", "wc_plan_autotune", "wc_plan_forms", "wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
+for _f in ("wc_plan_retarget", "wc_plan_autotune", "wc_profile", "wc_plan_create", "wc_plan_destroy", "wc_plan_set_stream", "wc_rhs", "wc_matvec",
            "wc_pc_apply", "wc_recover", "wc_krylov", "wc_solve"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_plan_create",
-            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_forms",
-            "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
+            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
             "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read",
             "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
             "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use", "wc_batch_create",
@@ -239,13 +237,6 @@ class Plan:
         self._check(_lib.wc_plan_autotune(self._h, int(reps), ctypes.byref(ts), ctypes.byref(tx)),
                     "wc_plan_autotune")
         return ts.value, tx.value
-
-    def forms(self) -> dict:
-        """The kernel forms this plan launches (0 = built-in default)."""
-        out = (ctypes.c_int * 5)()
-        self._check(_lib.wc_plan_forms(self._h, out), "wc_plan_forms")
-        return {"ts": out[0], "tx": out[1], "tx_contract": out[2], "contract_opq": out[3],
-                "contract_pf": out[4]}
 
     def set_stream(self, stream):
         self._stream = stream

@@ -107,13 +107,6 @@ def test_retarget_null_plan(wc):
     assert lib.wc_plan_retarget(None, None, None) == wc.WC_E_ARG
 
 
-def test_forms_null_arguments(wc):
-    lib = ctypes.CDLL(LIB)
-    lib.wc_plan_forms.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
-    out = (ctypes.c_int * 5)()
-    assert lib.wc_plan_forms(None, out) == wc.WC_E_ARG
-
-
 def test_lowrank_options_and_footprint(wc):
     full = wc.footprint_bytes(2, 255, 256, method="gmres_ps", restart=30)
     lr = wc.footprint_bytes(2, 255, 256, method="gmres_ps", restart=30, lowrank=True)
