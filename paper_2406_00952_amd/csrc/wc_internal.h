@@ -303,6 +303,9 @@ hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
 // 2D low-rank GMRES: time transform and x1 sine transform of the cycle's r0 into
 // d_lr_spec, and its x2 sine transform into d_specA (once per cycle)
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0);
+// 2D low-rank GMRES: s0 into orthonormal sine coordinates (the compact vectors of a 2D
+// plan are held in them)
+hipError_t launch_lr_sine_s0(const wc_plan &p);
 bool pc_supported(int n, int N1);
 
 // ---- many instances in one launch per pass (2D, a = 1) ------------------------------

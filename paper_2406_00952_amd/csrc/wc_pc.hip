@@ -736,15 +736,37 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_fn(int nlines, const cx<P
   }
 }
 
-// line x2 of a1 + i a2 for the current compact vector ...
-template <typename P> struct LrCoefSrc {
+// 2D low-rank GMRES keeps the compact vectors and s0 in orthonormal sine coordinates
+// (Q = (2/N1) DST_x1 DST_x2, symmetric and orthogonal, so Euclidean inner products are
+// unchanged).  x2 line j1 of a1 + i a2 of the compact vector, in those coordinates ...
+template <typename P> struct SineCoefSrc {
   GenIn gi;
   int m, M;
-  __device__ cx<P> operator()(int x2, int x) const {
-    const int s = x2 * M + x;
+  __device__ cx<P> operator()(int j1, int j2) const {
+    const int s = j2 * M + j1;
     const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
     return cx<P>{(P)(gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
                  (P)(gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
+  }
+};
+// s0_1 + i s0_2 in physical coordinates, line x2, and the same written back (scaled) as
+// line j1 of the x2 pass
+struct PairSrc {
+  const double *s0;
+  int m, M;
+  __device__ cx<double> operator()(int x2, int x) const {
+    const int s = x2 * M + x;
+    return cx<double>{s0[s], s0[m + s]};
+  }
+};
+struct PairStore {
+  double *s0;
+  int m, M;
+  double scale;
+  __device__ void operator()(int j1, int j2, cx<double> v) const {
+    const int s = j2 * M + j1;
+    s0[s] = scale * v.x;
+    s0[m + s] = scale * v.y;
   }
 };
 // ... stored as A[x2][j1]
@@ -753,27 +775,7 @@ template <typename P> struct StoreA {
   int M;
   __device__ void operator()(int x2, int x, cx<P> v) const { A[x2 * M + x] = v; }
 };
-// line x2 of C_0 + i C_1 (the packed chunk sums) ...
-struct PackedSrc {
-  const cx<double> *c;
-  int M;
-  __device__ cx<double> operator()(int x2, int j1) const { return c[x2 * M + j1]; }
-};
-// ... and the compact output [0, |g| omega C_0, |r| omega C_1] after the inverse x1 transform
-struct StoreHat {
-  ContractOut co;
-  int m, M;
-  __device__ void operator()(int x2, int x, cx<double> v) const {
-    const int s = x2 * M + x;
-    if (s == 0) co.hat[0] = 0.0;
-    co.hat[1 + s] = co.gn_omega * v.x;
-    co.hat[1 + m + s] = co.rn_omega * v.y;
-  }
-};
-
-
-// x2 lines (one per x1 index j1) of an m-point field [x2][j1], read and written in place:
-// the x2 sine transform of A and the inverse x2 transform of the packed sums
+// x2 lines (one per x1 index j1) of an m-point field [x2][j1], read and written
 template <typename T> struct ColLine {
   cx<T> *f;
   int M;
@@ -1009,10 +1011,11 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
 // sine transform being real), so the spectrum is never written: workgroup (chunk, column
 // tile) runs the tile body for the frequencies of its chunk and writes its sums,
 // part[chunk][h m + x2 M + j1].
-// sums of the chunks, packed as C_0 + i C_1 per spatial point for the inverse x1 transform
-__global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__restrict__ part,
-                                                            cx<double> *__restrict__ out,
-                                                            int m) {
+// the compact output of a 2D low-rank step in sine coordinates: hat[0] = 0 and
+// hat[1 + h m + s] = scale_h * (sum of the chunk partials of block row h at s)
+__global__ __launch_bounds__(kThreads) void k_lr_hat_out(const double *__restrict__ part,
+                                                         double *__restrict__ hat, int m,
+                                                         double sg, double sr) {
   const int s = blockIdx.x * kThreads + threadIdx.x;
   if (s >= m) return;
   double a = 0.0, b = 0.0;
@@ -1021,7 +1024,9 @@ __global__ __launch_bounds__(kThreads) void k_contract_pack(const double *__rest
     a += part[(size_t)c * 2 * m + s];
     b += part[(size_t)c * 2 * m + m + s];
   }
-  out[s] = cx<double>{a, b};
+  if (s == 0) hat[0] = 0.0;
+  hat[1 + s] = sg * a;
+  hat[1 + m + s] = sr * b;
 }
 
 
@@ -1067,13 +1072,13 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
 // matrices, so they commute with forming the input and with the real-part sum over
 // frequencies).  For spatial mode s and frequency q the input is
 //   u_h = c Yhat0[q][h][s] + F[q][h][0] Re Ahat[s] + F[q][h][1] Im Ahat[s]  (h = 0, 1),
-// the per-mode solve maps (u_0, u_1) to (z_0, z_1), and
+// where Ahat = (N1/2) (a1 + i a2) is formed here from the compact vector and s0 (both in
+// orthonormal sine coordinates), the per-mode solve maps (u_0, u_1) to (z_0, z_1), and
 //   part[chunk][h][s] = sum over the chunk's q of 2 Re(rho[h nq + q] z_h).
 template <typename P>
 __global__ __launch_bounds__(kThreads) void k_lr_contract(
-    const cx<P> *__restrict__ Yh, const cx<P> *__restrict__ Ah, const cx<double> *__restrict__ F,
+    const cx<P> *__restrict__ Yh, GenIn gi, double ascale, const cx<double> *__restrict__ F,
     const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
-    const double *__restrict__ hat, const double *__restrict__ sqn0,
     const cx<double> *__restrict__ rho, int nq, int M, double *__restrict__ part) {
   constexpr int QB = 8;  // frequencies whose loads are issued together
   const int m = M * M;
@@ -1081,10 +1086,11 @@ __global__ __launch_bounds__(kThreads) void k_lr_contract(
   if (s >= m) return;
   const int per = (nq + kColChunks - 1) / kColChunks;
   const int q0 = chunk * per, q1 = q0 + per < nq ? q0 + per : nq;
-  const double gc = *sqn0 > 0.0 ? hat[0] / *sqn0 : 0.0;
+  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
   const int j2 = s / M, j1 = s - j2 * M;
   const P mus = mu[j1] + mu[j2];
-  const cx<P> a = Ah[s];
+  const cx<double> a{ascale * (gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
+                     ascale * (gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
   double acc0 = 0.0, acc1 = 0.0;
   for (int qb = q0; qb < q1; qb += QB) {
     cx<P> y0[QB], y1[QB];
@@ -1332,45 +1338,46 @@ hipError_t run_space(const wc_plan &p, const GenIn *rows_gen = nullptr) {
 
 #define WC_POW2_CASES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
-// 2D low-rank GMRES step E v in compact coordinates, all in full sine coordinates: A (a1 + i
-// a2 of the compact vector) by its x1 then x2 sine transforms, the pointwise solve and
-// contraction over frequencies against the cycle's Yhat0 (held in the spectrum array since
-// the cycle began), the chunk sums packed as C_0 + i C_1, and their inverse x2 then x1
-// transforms written as the compact output.
+// 2D low-rank GMRES step E v in compact coordinates, with the compact vectors, s0 and the
+// cycle's Yhat0 (held in the spectrum array since the cycle began) all in sine coordinates:
+// one streaming pass that forms every mode's input, solves it and contracts over
+// frequencies, then the chunk sums scaled into the compact output.  With D the unnormalised
+// 2D sine transform (D D = (N1/2)^2 I) and Q = (2/N1) D, the output Q (omega |g| D C) is
+// omega |g| (N1/2) C.
 template <typename P, int N1>
 hipError_t lr_step_t(const wc_plan &p, const GenIn &gen, const ContractOut &co) {
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
   const double c = (1.0 / p.n) * (2.0 / N1) * (2.0 / N1);
-  cx<P> *A = (cx<P> *)p.d_lr_a;
-  hipError_t e = launch_rows_fn<P, N1>(p, M, LrCoefSrc<P>{gen, p.m, M}, StoreA<P>{A, M},
-                                       K_LR_SETUP, 32.0 * p.m + p.m * sizeof(cx<P>));
-  if (e != hipSuccess) return e;
-  e = launch_rows_fn<P, N1>(p, M, ColLine<P>{A, M}, ColLine<P>{A, M}, K_LR_SETUP,
-                            2.0 * p.m * sizeof(cx<P>));
-  if (e != hipSuccess) return e;
+  const double half = 0.5 * N1;
+  hipError_t e;
   {
     ProfScope ps(p, K_PAIR_CONTRACT,
-                 p.nvec * (double)sizeof(P) + p.m * (double)sizeof(cx<P>) +
-                     16.0 * kColChunks * p.m);
+                 p.nvec * (double)sizeof(P) + 32.0 * p.m + 16.0 * kColChunks * p.m);
     hipLaunchKernelGGL(k_lr_contract<P>, dim3((p.m + kThreads - 1) / kThreads, kColChunks),
-                       dim3(kThreads), 0, p.stream, (const cx<P> *)p.d_specA,
-                       (const cx<P> *)A, (const cx<double> *)p.d_lr_rank, Tabs<P>::lam(p),
-                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c, gen.hat, gen.sqn0,
-                       (const cx<double> *)co.rho, p.n / 2, M, co.part);
+                       dim3(kThreads), 0, p.stream, (const cx<P> *)p.d_specA, gen, half,
+                       (const cx<double> *)p.d_lr_rank, Tabs<P>::lam(p), Tabs<P>::mu(p), kind,
+                       (P)p.tau, (P)p.alpha, (P)c, (const cx<double> *)co.rho, p.n / 2, M,
+                       co.part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  cx<double> *pk2 = (cx<double> *)p.d_lr_a;  // A is free again once the contraction has run
-  {
-    ProfScope ps(p, K_CONTRACT, 16.0 * kColChunks * p.m + 16.0 * p.m);
-    hipLaunchKernelGGL(k_contract_pack, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads),
-                       0, p.stream, co.part, pk2, p.m);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  e = launch_rows_fn<double, N1>(p, M, ColLine<double>{pk2, M}, ColLine<double>{pk2, M},
-                                 K_CONTRACT, 32.0 * p.m);
+  ProfScope ps(p, K_CONTRACT, 16.0 * kColChunks * p.m + 16.0 * p.m);
+  hipLaunchKernelGGL(k_lr_hat_out, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     p.stream, co.part, co.hat, p.m, co.gn_omega * half, co.rn_omega * half);
+  return hipGetLastError();
+}
+
+// s0 (two m-point fields, [x2][x1]) into orthonormal sine coordinates, in place, through
+// the m complex of d_lr_a: x1 transform of s0_1 + i s0_2, then the x2 transform scaled by
+// 2/N1 and split back
+template <int N1> hipError_t lr_sine_s0_t(const wc_plan &p) {
+  constexpr int M = N1 - 1;
+  cx<double> *t = (cx<double> *)p.d_lr_a;
+  hipError_t e = launch_rows_fn<double, N1>(p, M, PairSrc{p.d_lr_s0, p.m, M},
+                                            StoreA<double>{t, M}, K_LR_SETUP, 32.0 * p.m);
   if (e != hipSuccess) return e;
-  return launch_rows_fn<double, N1>(p, M, PackedSrc{pk2, M}, StoreHat{co, p.m, M}, K_CONTRACT,
+  return launch_rows_fn<double, N1>(p, M, ColLine<double>{t, M},
+                                    PairStore{p.d_lr_s0, p.m, M, 2.0 / N1}, K_LR_SETUP,
                                     32.0 * p.m);
 }
 
@@ -1390,9 +1397,9 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
       default: return hipErrorInvalidValue;
     }
   }
-  if (hoist) {  // a1 + i a2, formed as its x1 sine transform (M lines) loads
-    const LrCoefSrc<P> src{*gen, p.m, p.M};
-    const StoreA<P> dst{(cx<P> *)p.d_lr_a, p.M};
+  if (hoist) {  // a1 + i a2 with its x1 transform: Q a is held, and DST_x1 Q = DST_x2
+    const SineCoefSrc<P> src{*gen, p.m, p.M};
+    const ColLine<P> dst{(cx<P> *)p.d_lr_a, p.M};
     switch (p.N1) {
 #define CASE_S(NN)                                                                            \
   case NN:                                                                                    \
@@ -1850,6 +1857,16 @@ template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r
   }
 }
 }  // namespace
+
+hipError_t launch_lr_sine_s0(const wc_plan &p) {
+  if (!p.d_lr_spec || p.dims != 2) return hipErrorInvalidValue;
+  switch (p.N1) {
+#define CASE_S(NN) case NN: return lr_sine_s0_t<NN>(p);
+    WC_POW2_CASES(CASE_S)
+#undef CASE_S
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
   if (!p.d_lr_spec || p.dims != 2) return hipErrorInvalidValue;
