@@ -137,8 +137,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   if (op->lowrank)  // compact basis (restart + 2 vectors of 1 + 2m), s0, g, r, rho, partials
     s.vecs += ((size_t)(op->restart + 2) * (1 + 2 * m) + 2 * m + 4 * (size_t)pr->n +
                (size_t)std::max(kContractChunks, kColChunks) * 2 * m) * sizeof(double);
-  if (op->lowrank && pr->dims == 2)  // spectrum of r0, rank-term spectra, a1 and a2
-    s.vecs += s.spec_bytes + (4 * (size_t)pr->n + 2 * m) * sizeof(double);
+  if (op->lowrank && pr->dims == 2)  // rank-term spectra, a1 and a2 (r0's spectrum: d_specA)
+    s.vecs += (4 * (size_t)pr->n + 2 * m) * sizeof(double);
   s.mg = 0;
   if (pr->a_face_host) {  // fine solution, coarse levels, face pyramid, shifts, rotations
     const MgShape g = mg_shape(pr->dims, pr->M, pr->n, op->precision);
@@ -238,7 +238,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_mg_u2);
   dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat); dfree(p->d_lr_rho);
   dfree(p->d_lr_part);
-  dfree(p->d_lr_spec); dfree(p->d_lr_rank); dfree(p->d_lr_a);
+  dfree(p->d_lr_rank); dfree(p->d_lr_a);
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_mg_fn2);
@@ -435,7 +435,7 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
         lr && p->opts.precision == WC_MIXED ? std::max(tol, kMixedCycleDrop * relres) : tol;
     if (lr) {  // compact coordinates of r0 (its range part and the rest)
       WC_TRY(launch_lr_setup(*p, R0, V));
-      if (p->d_lr_spec) WC_TRY(launch_lr_spectrum(*p, R0));
+      if (p->lr_2d) WC_TRY(launch_lr_spectrum(*p, R0));
       WC_TRY(launch_dot(*p, V, V, S_NU2, len));
       WC_TRY(sync_read(p, S_NU2, 1));
       beta = std::sqrt(p->h_scal[S_NU2]);
@@ -922,7 +922,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     alloc((void **)&p->d_lr_part,
           (size_t)std::max(kContractChunks, kColChunks) * 2 * p->m * sizeof(double));
     if (p->dims == 2) {  // (the rank-term spectra were uploaded with the tables)
-      alloc((void **)&p->d_lr_spec, sz.spec_bytes);
+      p->lr_2d = true;
       alloc((void **)&p->d_lr_a, 2 * (size_t)p->m * sizeof(double));
     }
   }

@@ -167,8 +167,8 @@ struct wc_plan {
   double *d_lr_part = nullptr;      // max(kContractChunks, kColChunks) x 2m
   // 2D: the time and sine transforms are linear and r0 is fixed within a cycle, so the
   // Arnoldi steps take the spectrum of c r0 + [g (x) a1; r (x) a2] from these instead of
-  // transforming (the x1 and x2 transforms of r0's spectrum sit in d_specA for the cycle)
-  double *d_lr_spec = nullptr;      // time and x1 transforms of the cycle's r0 (spectral layout)
+  // transforming (the time, x1 and x2 transforms of r0 sit in d_specA for the cycle)
+  bool lr_2d = false;               // 2D low-rank GMRES
   double *d_lr_rank = nullptr;      // n/2 x 2 halves x 2 complex: spectra of g and of r
   double *d_lr_a = nullptr;         // m complex: a1 + i a2 of the current vector, sine-transformed
 
@@ -297,11 +297,12 @@ hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool do
 hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *hat_in,
                              double *hat_out, double *w);
 // s0 = projection coefficients of r0 on the correction's range; N0 = ||r0 - [g s0_1; r s0_2]||^2
-// and sqrt(N0) into the scalar slots; hat = [sqrt(N0), |g| s0_1, |r| s0_2].  Expects
+// and sqrt(N0) into the scalar slots; hat = [sqrt(N0), |g| s0_1, |r| s0_2] (2D: s0 and the
+// compact vectors in orthonormal sine coordinates).  Expects
 // ||r0||^2 in d_scal[S_DOT] (launch_dot before).
 hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat);
 // 2D low-rank GMRES: time transform and x1 sine transform of the cycle's r0 into
-// d_lr_spec, and its x2 sine transform into d_specA (once per cycle)
+// d_specA, then its x2 sine transform in place (once per cycle)
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0);
 // 2D low-rank GMRES: s0 into orthonormal sine coordinates (the compact vectors of a 2D
 // plan are held in them)

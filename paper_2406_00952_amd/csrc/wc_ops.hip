@@ -785,7 +785,7 @@ hipError_t launch_lr_setup(const wc_plan &p, const double *r0, double *hat) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // 2D: s0, and with it every compact vector, in orthonormal sine coordinates
-  if (p.dims == 2 && p.d_lr_spec && (e = launch_lr_sine_s0(p)) != hipSuccess) return e;
+  if (p.lr_2d && (e = launch_lr_sine_s0(p)) != hipSuccess) return e;
   ProfScope ps(p, K_LR_SETUP, 8.0 * p.lr_len);
   hipLaunchKernelGGL(k_lr_hat0, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
                      p.stream, p.d_partials, nb, p.d_scal, (int)S_LR_N0, p.d_scal + S_DOT,

@@ -738,17 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_dst_rows_fn(int nlines, const cx<P
 
 // 2D low-rank GMRES keeps the compact vectors and s0 in orthonormal sine coordinates
 // (Q = (2/N1) DST_x1 DST_x2, symmetric and orthogonal, so Euclidean inner products are
-// unchanged).  x2 line j1 of a1 + i a2 of the compact vector, in those coordinates ...
-template <typename P> struct SineCoefSrc {
-  GenIn gi;
-  int m, M;
-  __device__ cx<P> operator()(int j1, int j2) const {
-    const int s = j2 * M + j1;
-    const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
-    return cx<P>{(P)(gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
-                 (P)(gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
-  }
-};
+// unchanged).
 // s0_1 + i s0_2 in physical coordinates, line x2, and the same written back (scaled) as
 // line j1 of the x2 pass
 struct PairSrc {
@@ -850,18 +840,11 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
 // and r0 is fixed within a cycle, so the x1-transformed spectrum of c r0 + [g (x) a1;
 // r (x) a2] is c Y0 + F[q][h][0] A1 + F[q][h][1] A2, with Y0 the cycle's transformed r0,
 // F the time spectra of g and r, and A1 + i A2 the x1 sine transform of a1 + i a2.
-template <typename P> struct ColsGen {
-  const cx<P> *Y0;          // [q][h][x2][j1]
-  const cx<P> *A;           // [x2][j1]: (A1, A2)
-  const cx<double> *F;      // [q][h][2]
-  const double *hat, *sqn0; // c = hat[0] / sqn0 (0 when sqn0 = 0)
-};
-
-// The loads of x2 tile t (or its generated input): item (c, h, i) of thread tid reads rows
-// i-1 and N1-i-1 of column c0+c of block row h.
-template <typename P, int N1, int TX, bool GEN>
-__device__ __forceinline__ void cols_tile_load(cx<P> *__restrict__ W, const ColsGen<P> &cg,
-                                               int t, int tid, double gc, cx<P> *ra, cx<P> *rb) {
+// The loads of x2 tile t: item (c, h, i) of thread tid reads rows i-1 and N1-i-1 of
+// column c0+c of block row h.
+template <typename P, int N1, int TX>
+__device__ __forceinline__ void cols_tile_load(const cx<P> *__restrict__ W, int t, int tid,
+                                               cx<P> *ra, cx<P> *rb) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, NT = C::NT, H = N1 / 2, TP = H * 2 * TX;
   constexpr int LIT = (TP + NT - 1) / NT;
@@ -875,20 +858,9 @@ __device__ __forceinline__ void cols_tile_load(cx<P> *__restrict__ W, const Cols
     rb[it] = cx<P>{(P)0, (P)0};
     if (idx < TP && c0 + c < M) {
       const size_t o1 = (size_t)(i - 1) * M + c0 + c, o2 = (size_t)(N1 - i - 1) * M + c0 + c;
-      if constexpr (GEN) {
-        const cx<P> *Y = cg.Y0 + ((size_t)q * 2 + h) * M * M;
-        const cx<double> f1 = cg.F[(q * 2 + h) * 2], f2 = cg.F[(q * 2 + h) * 2 + 1];
-        const cx<P> y1 = load_stream(Y + o1), y2 = load_stream(Y + o2);
-        const cx<P> a1 = cg.A[o1], a2 = cg.A[o2];
-        ra[it] = cx<P>{(P)(gc * y1.x + f1.x * a1.x + f2.x * a1.y),
-                       (P)(gc * y1.y + f1.y * a1.x + f2.y * a1.y)};
-        rb[it] = cx<P>{(P)(gc * y2.x + f1.x * a2.x + f2.x * a2.y),
-                       (P)(gc * y2.y + f1.y * a2.x + f2.y * a2.y)};
-      } else {
-        const cx<P> *src = W + ((size_t)q * 2 + h) * M * M;
-        ra[it] = src[o1];
-        rb[it] = src[o2];
-      }
+      const cx<P> *src = W + ((size_t)q * 2 + h) * M * M;
+      ra[it] = src[o1];
+      rb[it] = src[o2];
     }
   }
 }
@@ -915,13 +887,12 @@ __device__ __forceinline__ void cols_pre_lds(const cx<P> *ra, const cx<P> *rb, c
   }
 }
 
-template <typename P, int N1, int TX, bool TABL, bool GEN = false>
+template <typename P, int N1, int TX, bool TABL>
 __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P> *__restrict__ twg,
                                                const P *__restrict__ sing,
                                                const cx<P> *__restrict__ lam,
                                                const P *__restrict__ mu, int kind, P tau, P alpha,
-                                               P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin,
-                                               ColsGen<P> cg = {}) {
+                                               P cnorm, int t, cx<P> *buf, cx<P> *stw, P *ssin) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS;
   constexpr int CPW = TX / C::WAVES, NT = C::NT;  // columns per wave, threads
@@ -939,9 +910,7 @@ __device__ __forceinline__ void cols_mode_tile(cx<P> *__restrict__ W, const cx<P
   constexpr int H = N1 / 2, TP = H * 2 * TX;
   constexpr int LIT = (TP + NT - 1) / NT;
   cx<P> ra[LIT], rb[LIT];
-  double gc = 0.0;
-  if constexpr (GEN) gc = *cg.sqn0 > 0.0 ? cg.hat[0] / *cg.sqn0 : 0.0;
-  cols_tile_load<P, N1, TX, GEN>(W, cg, t, tid, gc, ra, rb);
+  cols_tile_load<P, N1, TX>(W, t, tid, ra, rb);
   if constexpr (TABL) {
     for (int i = tid; i < N1; i += NT) {
       stw[i] = twg[i];
@@ -991,20 +960,6 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode(cx<P> *__
                                         xcd_tile(blockIdx.x, gridDim.x), buf, stw, ssin);
 }
 
-// the x2 pass on the generated input, writing the spectrum (the cycle's update)
-template <typename P, int N1, int TX>
-__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_mode_gen(
-    cx<P> *__restrict__ W, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
-    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
-    ColsGen<P> cg) {
-  using C = ColCfg<P, N1, TX>;
-  __shared__ cx<P> buf[C::PN * C::S];
-  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
-  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
-  cols_mode_tile<P, N1, TX, C::TAB_LDS, true>(W, twg, sing, lam, mu, kind, tau, alpha, cnorm,
-                                              xcd_tile(blockIdx.x, gridDim.x), buf, stw, ssin,
-                                              cg);
-}
 
 // 2D low-rank GMRES step: the x2 pass on the generated input, contracted over time before
 // the inverse x1 transform (the contraction sum_q 2 Re(rho_q Z_q) commutes with it, the
@@ -1031,12 +986,12 @@ __global__ __launch_bounds__(kThreads) void k_lr_hat_out(const double *__restric
 
 
 
-// x2 sine transform of both block rows of every frequency, out of place: the cycle's r0
-// spectrum in full sine coordinates, from which a 2D low-rank step works pointwise
+// x2 sine transform of both block rows of every frequency (in == out allowed: every tile is
+// read whole before it is written): the cycle's r0 spectrum in full sine coordinates, from
+// which a 2D low-rank step works pointwise
 template <typename P, int N1, int TX>
 __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
-    const cx<P> *__restrict__ in, cx<P> *__restrict__ out, const cx<P> *__restrict__ twg,
-    const P *__restrict__ sing) {
+    const cx<P> *in, cx<P> *out, const cx<P> *__restrict__ twg, const P *__restrict__ sing) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS, NT = C::NT, CPW = C::CPW, TT = 2 * TX * M;
   constexpr int LIT = (N1 / 2 * 2 * TX + NT - 1) / NT;
@@ -1048,7 +1003,7 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
   const int ncx = (N1 - 2 + TX) / TX;
   const int q = t / ncx, c0 = (t % ncx) * TX;
   cx<P> ra[LIT], rb[LIT];
-  cols_tile_load<P, N1, TX, false>(const_cast<cx<P> *>(in), ColsGen<P>{}, t, tid, 0.0, ra, rb);
+  cols_tile_load<P, N1, TX>(in, t, tid, ra, rb);
   if constexpr (C::TAB_LDS) {
     for (int i = tid; i < N1; i += NT) {
       stw[i] = twg[i];
@@ -1065,6 +1020,77 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
     const int c = idx % TX, h = (idx / TX) & 1, j2 = idx / (2 * TX);
     if (c0 + c < M)
       o0[(size_t)h * M * M + (size_t)j2 * M + c0 + c] = buf[pk<PS>(j2 + 1) * S + 2 * c + h];
+  }
+}
+
+// The cycle's update in 2D low-rank GMRES, in place over the spectrum array that holds
+// Yhat0: every tile forms c Yhat0 + F (Re Ahat, Im Ahat) of its modes as it loads, solves
+// them, and applies the inverse x2 transform (the inverse x1 and time transforms follow as
+// in the standard apply).  Ahat = (N1/2)(a1 + i a2) from the compact vector and s0.
+template <typename P, int N1, int TX>
+__global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_update(
+    cx<P> *__restrict__ W, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
+    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
+    GenIn gi, double ascale, const cx<double> *__restrict__ F) {
+  using C = ColCfg<P, N1, TX>;
+  constexpr int M = N1 - 1, S = C::S, PS = C::PS, NT = C::NT, CPW = C::CPW, TT = 2 * TX * M;
+  constexpr int TI = TX * M, LIT = (TI + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * C::S];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int ncx = (N1 - 2 + TX) / TX;
+  const int q = t / ncx, c0 = (t % ncx) * TX;
+  const size_t m = (size_t)M * M;
+  cx<P> *slab0 = W + (size_t)q * 2 * m, *slab1 = slab0 + m;
+  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+  // item (c, j2): both block rows of mode (c0 + c, j2); all loads issued first
+  cx<P> y0[LIT], y1[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT, c = idx % TX, j2 = idx / TX;
+    y0[it] = cx<P>{(P)0, (P)0};
+    y1[it] = cx<P>{(P)0, (P)0};
+    if (idx < TI && c0 + c < M) {
+      y0[it] = load_stream(slab0 + (size_t)j2 * M + c0 + c);
+      y1[it] = load_stream(slab1 + (size_t)j2 * M + c0 + c);
+    }
+  }
+  if constexpr (C::TAB_LDS) {
+    for (int i = tid; i < N1; i += NT) {
+      stw[i] = twg[i];
+      ssin[i] = sing[i];
+    }
+  }
+  const cx<double> f00 = F[q * 4], f01 = F[q * 4 + 1], f10 = F[q * 4 + 2], f11 = F[q * 4 + 3];
+  const cx<P> l = lam[q];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT, c = idx % TX, j2 = idx / TX, j1 = c0 + c;
+    if (idx >= TI) continue;
+    cx<P> u0{(P)0, (P)0}, u1{(P)0, (P)0};
+    if (j1 < M) {
+      const int s = j2 * M + j1;
+      const double ax = ascale * (gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]);
+      const double ay = ascale * (gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s]);
+      u0 = cx<P>{(P)(gc * y0[it].x + f00.x * ax + f01.x * ay),
+                 (P)(gc * y0[it].y + f00.y * ax + f01.y * ay)};
+      u1 = cx<P>{(P)(gc * y1[it].x + f10.x * ax + f11.x * ay),
+                 (P)(gc * y1[it].y + f10.y * ax + f11.y * ay)};
+      mode_op<P>(u0, u1, l, mu[j1] + mu[j2], kind, tau, alpha, cnorm);
+    }
+    buf[pk<PS>(j2 + 1) * S + 2 * c] = u0;
+    buf[pk<PS>(j2 + 1) * S + 2 * c + 1] = u1;
+  }
+  __syncthreads();
+  wdst<P, N1, 2 * CPW, S, PS>(buf + wv * 2 * CPW, C::TAB_LDS ? stw : twg,
+                              C::TAB_LDS ? ssin : sing, lane);
+  __syncthreads();
+  for (int idx = tid; idx < TT; idx += NT) {
+    const int c = idx % TX, h = (idx / TX) & 1, x2 = idx / (2 * TX);
+    if (c0 + c < M)
+      (h ? slab1 : slab0)[(size_t)x2 * M + c0 + c] = buf[pk<PS>(x2 + 1) * S + 2 * c + h];
   }
 }
 
@@ -1252,22 +1278,17 @@ hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *np
 }
 
 template <typename P, int N1, int TX>
-hipError_t cols_tx(const wc_plan &p, int kind, double c, const ColsGen<P> *cg) {
+hipError_t cols_tx(const wc_plan &p, int kind, double c) {
   if constexpr (!ColCfg<P, N1, TX>::FITS) {
-    return cols_tx<P, N1, 4>(p, kind, c, cg);
+    return cols_tx<P, N1, 4>(p, kind, c);
   } else {
     constexpr int M = N1 - 1;
     const int ncx = (M + TX - 1) / TX;
-    dim3 gc(ncx * (p.n / 2));
     ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
-    if (cg)
-      hipLaunchKernelGGL((k_cols_mode_gen<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0,
-                         p.stream, (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p),
-                         Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c, *cg);
-    else
-      hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), gc, dim3(ColCfg<P, N1, TX>::NT), 0, p.stream,
-                         (cx<P> *)p.d_specA, Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p),
-                         Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
+    hipLaunchKernelGGL((k_cols_mode<P, N1, TX>), dim3(ncx * (p.n / 2)),
+                       dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, (cx<P> *)p.d_specA,
+                       Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind,
+                       (P)p.tau, (P)p.alpha, (P)c);
     return hipGetLastError();
   }
 }
@@ -1295,7 +1316,7 @@ hipError_t dst_rows_on(const wc_plan &p, cx<P> *buf, int nlines, int prof_id, do
 }
 
 template <typename P, int N1>
-hipError_t run_space(const wc_plan &p, const GenIn *rows_gen = nullptr) {
+hipError_t run_space(const wc_plan &p) {
   using R = RowCfg<P, N1>;
   constexpr int M = N1 - 1;
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
@@ -1314,20 +1335,12 @@ hipError_t run_space(const wc_plan &p, const GenIn *rows_gen = nullptr) {
   }
   const int nlines = p.n * M;  // n/2 frequencies x 2 block rows x M rows
   dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
-  hipError_t e = hipSuccess;
-  ColsGen<P> cg{};
-  if (rows_gen) {  // 2D low-rank GMRES: the x2 pass generates its input (no x1 pass here)
-    cg = ColsGen<P>{(const cx<P> *)p.d_lr_spec, (const cx<P> *)p.d_lr_a,
-                    (const cx<double> *)p.d_lr_rank, rows_gen->hat, rows_gen->sqn0};
-  } else {
-    e = dst_rows_on<P, N1>(p, W, nlines, K_DST_X1_FWD, bytes);
-  }
+  hipError_t e = dst_rows_on<P, N1>(p, W, nlines, K_DST_X1_FWD, bytes);
   if (e != hipSuccess) return e;
-  const ColsGen<P> *cgp = rows_gen ? &cg : nullptr;
   switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
-    case 4: e = cols_tx<P, N1, 4>(p, kind, c, cgp); break;
-    case 16: e = cols_tx<P, N1, 16>(p, kind, c, cgp); break;
-    default: e = cols_tx<P, N1, 8>(p, kind, c, cgp); break;
+    case 4: e = cols_tx<P, N1, 4>(p, kind, c); break;
+    case 16: e = cols_tx<P, N1, 16>(p, kind, c); break;
+    default: e = cols_tx<P, N1, 8>(p, kind, c); break;
   }
   if (e != hipSuccess) return e;
   ProfScope ps(p, K_DST_X1_INV, bytes);
@@ -1381,13 +1394,44 @@ template <int N1> hipError_t lr_sine_s0_t(const wc_plan &p) {
                                     32.0 * p.m);
 }
 
+// the cycle's update (2D low-rank GMRES): the x2 pass from Yhat0, then the inverse x1
+// transform; the inverse time transform follows in pc_apply_t
+template <typename P, int N1>
+hipError_t lr_update_t(const wc_plan &p, const GenIn &gen) {
+  using R = RowCfg<P, N1>;
+  constexpr int M = N1 - 1, TX = default_tx<P, N1>();
+  if constexpr (!ColCfg<P, N1, TX>::FITS) {
+    return hipErrorInvalidValue;
+  } else {
+    const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
+    const double c = (1.0 / p.n) * (2.0 / N1) * (2.0 / N1);
+    cx<P> *W = (cx<P> *)p.d_specA;
+    const int ncx = (N1 - 2 + TX) / TX;
+    {
+      ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P) + 32.0 * p.m);
+      hipLaunchKernelGGL((k_cols_update<P, N1, TX>), dim3(ncx * (p.n / 2)),
+                         dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, W, Tabs<P>::tws(p),
+                         Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
+                         (P)p.alpha, (P)c, gen, 0.5 * N1, (const cx<double> *)p.d_lr_rank);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const int nlines = p.n * M;
+    dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
+    ProfScope ps(p, K_DST_X1_INV, 2.0 * p.nvec * sizeof(P));
+    hipLaunchKernelGGL((k_dst_rows<P, N1>), gr, dim3(64 * R::WPB), 0, p.stream, W, nlines,
+                       Tabs<P>::tws(p), Tabs<P>::sin(p));
+    return hipGetLastError();
+  }
+}
+
 template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
   hipError_t e = hipErrorInvalidValue;
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
-  const bool hoist = gen && p.dims == 2 && p.d_lr_spec;
+  const bool hoist = gen && p.lr_2d;
   if (hoist && co) {
     *nparts = 0;
     switch (p.N1) {
@@ -1397,14 +1441,9 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
       default: return hipErrorInvalidValue;
     }
   }
-  if (hoist) {  // a1 + i a2 with its x1 transform: Q a is held, and DST_x1 Q = DST_x2
-    const SineCoefSrc<P> src{*gen, p.m, p.M};
-    const ColLine<P> dst{(cx<P> *)p.d_lr_a, p.M};
+  if (hoist) {  // the cycle's update: the spectrum of its input is generated from Yhat0
     switch (p.N1) {
-#define CASE_S(NN)                                                                            \
-  case NN:                                                                                    \
-    e = launch_rows_fn<P, NN>(p, p.M, src, dst, K_LR_SETUP, 32.0 * p.m + p.m * sizeof(cx<P>)); \
-    break;
+#define CASE_S(NN) case NN: e = lr_update_t<P, NN>(p, *gen); break;
       WC_POW2_CASES(CASE_S)
 #undef CASE_S
       default: return hipErrorInvalidValue;
@@ -1416,16 +1455,16 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
 #undef CASE_N
       default: return hipErrorInvalidValue;
     }
-  }
-  if (e != hipSuccess) return e;
-  if (p.var_coeff) {
-    e = mg_space_apply(p);
-  } else {
-    switch (p.N1) {
-#define CASE_S(NN) case NN: e = run_space<P, NN>(p, hoist ? gen : nullptr); break;
-      WC_POW2_CASES(CASE_S)
+    if (e != hipSuccess) return e;
+    if (p.var_coeff) {
+      e = mg_space_apply(p);
+    } else {
+      switch (p.N1) {
+#define CASE_S(NN) case NN: e = run_space<P, NN>(p); break;
+        WC_POW2_CASES(CASE_S)
 #undef CASE_S
-      default: return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+      }
     }
   }
   if (e != hipSuccess) return e;
@@ -1808,7 +1847,7 @@ hipError_t launch_pc_apply(const wc_plan &p, const double *v, double *w, bool do
 
 hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *hat_in,
                              double *hat_out, double *w) {
-  if (p.opts.precision != WC_FP64 && !p.d_lr_spec) return hipErrorInvalidValue;
+  if (p.opts.precision != WC_FP64 && !p.lr_2d) return hipErrorInvalidValue;
   GenIn gen{hat_in, p.d_lr_s0, p.d_lr_gr, p.d_scal + S_LR_SQN0, 1.0 / p.lr_gn, 1.0 / p.lr_rn};
   ContractOut co{hat_out, -p.lr_gn, -p.lr_rn, p.d_lr_rho, p.d_lr_part};  // omega = e^{i pi} = -1
   int np = 0;
@@ -1836,7 +1875,7 @@ hipError_t cols_dst_t(const wc_plan &p, const cx<P> *in, cx<P> *out) {
 
 template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r0) {
   hipError_t e = hipErrorInvalidValue;
-  cx<P> *Y = (cx<P> *)p.d_lr_spec;
+  cx<P> *Y = (cx<P> *)p.d_specA;  // transformed in place, kept for the cycle
   switch (p.n) {
 #define CASE_N(NN) case NN: e = run_tfft_fwd<P, NN>(p, r0, nullptr, Y); break;
     WC_POW2_CASES(CASE_N)
@@ -1849,7 +1888,7 @@ template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r
 #define CASE_S(NN)                                                                 \
   case NN:                                                                         \
     e = dst_rows_on<P, NN>(p, Y, nlines, K_DST_X1_FWD, 2.0 * p.nvec * sizeof(P));  \
-    if (e == hipSuccess) e = cols_dst_t<P, NN>(p, Y, (cx<P> *)p.d_specA);          \
+    if (e == hipSuccess) e = cols_dst_t<P, NN>(p, Y, Y);                            \
     return e;
     WC_POW2_CASES(CASE_S)
 #undef CASE_S
@@ -1859,7 +1898,7 @@ template <typename P> hipError_t lr_spectrum_t(const wc_plan &p, const double *r
 }  // namespace
 
 hipError_t launch_lr_sine_s0(const wc_plan &p) {
-  if (!p.d_lr_spec || p.dims != 2) return hipErrorInvalidValue;
+  if (!p.lr_2d) return hipErrorInvalidValue;
   switch (p.N1) {
 #define CASE_S(NN) case NN: return lr_sine_s0_t<NN>(p);
     WC_POW2_CASES(CASE_S)
@@ -1869,7 +1908,7 @@ hipError_t launch_lr_sine_s0(const wc_plan &p) {
 }
 
 hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
-  if (!p.d_lr_spec || p.dims != 2) return hipErrorInvalidValue;
+  if (!p.lr_2d) return hipErrorInvalidValue;
   return p.opts.precision == WC_MIXED ? lr_spectrum_t<float>(p, r0)
                                       : lr_spectrum_t<double>(p, r0);
 }
