@@ -336,9 +336,9 @@ wc_status run_minres(wc_plan *p, const double *b, double *x, wc_info *info) {
     }
     if (code == ST_NONFINITE) { st = WC_E_NONFINITE; break; }
     // explicit FP64 true residual
-    WC_TRY(launch_matvec(*p, x, AZ, p->d_partials, nullptr));
-    WC_TRY(launch_lincomb3(*p, R, b, AZ, nullptr, -1, 1.0, -1.0, 0.0));
-    WC_TRY(launch_dot(*p, R, R, S_DOT));
+    int mv_blocks = 0;  // R = b - A x and its squared norm in one pass
+    WC_TRY(launch_matvec(*p, x, R, p->d_partials, &mv_blocks, b, true));
+    WC_TRY(launch_finalize(*p, p->d_partials, mv_blocks, 1, S_DOT));
     WC_TRY(sync_read(p, S_DOT, 1));
     relres = std::sqrt(p->h_scal[S_DOT]) / bnorm;
     if (relres <= tol) { st = WC_OK; break; }
@@ -409,18 +409,21 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
     // the cycle's full residual r0 = b - Ahat x (x = 0 in the first cycle: b itself)
     const double *R0 = lr ? (first ? b : R0buf) : nullptr;
     double *Rf = lr ? R0buf : V;
+    int mv_blocks = 0;
     if (first) {
       if (!lr) WC_TRY(launch_lincomb3(*p, Rf, b, nullptr, nullptr, -1, 1.0, 0.0, 0.0));
     } else {
-      WC_TRY(launch_matvec(*p, x, Rf, p->d_partials, nullptr, b, true));
+      WC_TRY(launch_matvec(*p, x, Rf, p->d_partials, &mv_blocks, b, true));
     }
     double beta;
     if (lr) {
-      WC_TRY(launch_dot(*p, R0, R0, S_DOT));
+      // ||r0||^2: the matvec's partial sums (first cycle: r0 = b, whose norm is in S_DOT)
+      if (!first) WC_TRY(launch_finalize(*p, p->d_partials, mv_blocks, 1, S_DOT));
       WC_TRY(sync_read(p, S_DOT, 1));
       relres = std::sqrt(p->h_scal[S_DOT]) / bnorm;
     } else {
-      WC_TRY(launch_dot(*p, V, V, S_NU2));
+      if (first) WC_TRY(launch_dot(*p, V, V, S_NU2));
+      else WC_TRY(launch_finalize(*p, p->d_partials, mv_blocks, 1, S_NU2));
       WC_TRY(sync_read(p, S_NU2, 1));
       beta = std::sqrt(p->h_scal[S_NU2]);
       relres = beta / bnorm;

@@ -91,7 +91,8 @@ struct MvArgs {
 //                    A_hat   = [T x1 - alpha x2; alpha x1 + T^T x2].
 // partials[dir*gridDim.x + block] = this block's share of <y, x>.
 // With sub != nullptr the kernel writes ssign * (y - sub) (same layout as y) and the
-// partial sums are not meaningful.
+// partial sums are this block's share of the squared norm of what it wrote (a residual's
+// norm without another pass over it).
 __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ x,
                                                      double *__restrict__ y,
                                                      const double *__restrict__ sub, MvArgs a,
@@ -143,8 +144,14 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
           out = (uu - zprev) + a.tau * kx[u] + a.alpha * xok[u];
           zprev = uu;
         }
-        yo[(size_t)k * a.m + s] = so ? a.ssign * (out - sk[u]) : out;
-        acc += out * (a.sym ? xok[u] : xc[u]);
+        if (so) {
+          const double v = a.ssign * (out - sk[u]);
+          yo[(size_t)k * a.m + s] = v;
+          acc += v * v;
+        } else {
+          yo[(size_t)k * a.m + s] = out;
+          acc += out * (a.sym ? xok[u] : xc[u]);
+        }
       }
     }
   }
