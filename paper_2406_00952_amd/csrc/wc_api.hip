@@ -463,7 +463,8 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
           // not dominated by v, so one classical Gram-Schmidt pass normally suffices
           if ((e = launch_matvec(*p, Zj, Vn, p->d_partials, nullptr, Vj)) != hipSuccess) return e;
         }
-        if ((e = launch_gram_schmidt(*p, V, j, Vn, len)) != hipSuccess) return e;
+        // the second (DGKS) pass is rare: the host launches it below when the flag is set
+        if ((e = launch_gram_schmidt(*p, V, j, Vn, len, 1)) != hipSuccess) return e;
         return hipMemcpyAsync(p->h_scal + S_WN2, p->d_scal + S_WN2,
                               (S_D2 + j + 1 - S_WN2) * sizeof(double), hipMemcpyDeviceToHost,
                               p->stream);
@@ -472,9 +473,12 @@ wc_status run_gmres(wc_plan *p, const double *b, double *x, wc_info *info) {
       WC_TRY(hipStreamSynchronize(p->stream));
       const bool two = p->h_scal[S_REORTH] != 0.0;
       reorth += two ? 1 : 0;
-      if (!two && p->prof.on) {
-        p->prof.void_last(K_MULTIDOT_RE);
-        p->prof.void_last(K_MULTIAXPY_RE);
+      if (two) {
+        WC_TRY(launch_gs_second_pass(*p, V, j, Vn, len));
+        WC_TRY(hipMemcpyAsync(p->h_scal + S_WN2, p->d_scal + S_WN2,
+                              (S_D2 + j + 1 - S_WN2) * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+        WC_TRY(hipStreamSynchronize(p->stream));
       }
       const double nn = std::sqrt(std::max(p->h_scal[S_NU2 + j + 1], 0.0));
       nu[j + 1] = nn;

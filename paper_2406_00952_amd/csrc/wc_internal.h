@@ -278,12 +278,16 @@ hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, in
 // Gram-Schmidt bookkeeping of GMRES iteration j (one block): stage 1 first-pass dots,
 // 2 first-pass norm and DGKS test, 3 second-pass dots, 4 second-pass norm.
 hipError_t launch_gs_finalize(const wc_plan &p, int stage, int j, int count);
-// Both classical Gram-Schmidt passes of GMRES iteration j on Vn against V_0..V_j (vectors of
+// Classical Gram-Schmidt passes of GMRES iteration j on Vn against V_0..V_j (vectors of
 // length len, 0: a system vector), the second gated on the device by the DGKS test; the
 // bookkeeping of each reduction (the four gs_finalize stages) is done by the last
 // workgroup of that reduction, so the passes are four launches.
+// passes = 1 launches the first pass only (a caller that reads the DGKS flag on the host
+// then runs launch_gs_second_pass itself when it is set).
 hipError_t launch_gram_schmidt(const wc_plan &p, const double *V, int j, double *Vn,
-                               size_t len = 0);
+                               size_t len = 0, int passes = 2);
+hipError_t launch_gs_second_pass(const wc_plan &p, const double *V, int j, double *Vn,
+                                 size_t len = 0);
 hipError_t launch_fill(const wc_plan &p, double *dst, double val, size_t count);
 hipError_t launch_copy(const wc_plan &p, double *dst, const double *src, size_t count);
 

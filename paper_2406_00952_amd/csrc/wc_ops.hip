@@ -746,14 +746,20 @@ hipError_t launch_multiaxpy(const wc_plan &p, double *w, const double *basis, in
 }
 
 hipError_t launch_gram_schmidt(const wc_plan &p, const double *V, int j, double *Vn,
-                               size_t len) {
-  const double *gate = p.d_scal + S_REORTH;
+                               size_t len, int passes) {
   hipError_t e;
   if ((e = multidot_fin(p, V, j + 1, Vn, true, nullptr, nullptr, len, 1, j)) != hipSuccess)
     return e;
   if ((e = multiaxpy_fin(p, Vn, V, j + 1, S_GSC, -1.0, true, nullptr, nullptr, len, 2, j)) !=
       hipSuccess)
     return e;
+  return passes > 1 ? launch_gs_second_pass(p, V, j, Vn, len) : hipSuccess;
+}
+
+hipError_t launch_gs_second_pass(const wc_plan &p, const double *V, int j, double *Vn,
+                                 size_t len) {
+  const double *gate = p.d_scal + S_REORTH;
+  hipError_t e;
   if ((e = multidot_fin(p, V, j + 1, Vn, false, gate, nullptr, len, 3, j)) != hipSuccess)
     return e;
   return multiaxpy_fin(p, Vn, V, j + 1, S_GSC, -1.0, true, gate, nullptr, len, 4, j);

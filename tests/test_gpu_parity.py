@@ -252,3 +252,27 @@ def test_table1_example1_gpu(env, hexp, gamma):
     say("  iters", info.iters, "e_h", eh)
     assert info.iters == int(row[3])
     assert float(f"{eh:.3g}") == pytest.approx(float(row[4]), rel=1e-9)
+
+
+@pytest.mark.parametrize("lowrank", [False, True])
+@pytest.mark.parametrize("graphs", [False, True])
+def test_second_gram_schmidt_pass(env, lowrank, graphs):
+    """1D M=63, n=64 at tol 1e-12 takes the second (DGKS) Gram-Schmidt pass, which the host
+    launches after reading the flag; the solve must still match the oracle's."""
+    torch, wc = env
+    dims, M, n, theta, gamma = 1, 63, 64, 0.5, 1e-4
+    say("second GS pass, lowrank", lowrank, "graphs", graphs)
+    d = datagen.config_problem(dims, M, n, seed=3, noise_sigma=1e-3)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma)
+    ref = osolver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps", tol=1e-13, maxit=400)
+    plan = wc.Plan(dims, M, n, theta=theta, gamma=gamma, method="gmres_ps", tol=1e-12,
+                   maxit=400, lowrank=lowrank, graphs=graphs)
+    y = torch.empty(n * pr.m, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(y)
+    info = plan.solve(dev(torch, d["f"]), dev(torch, d["g"]), dev(torch, d["y0"]), y, p)
+    say("  iters", info.iters, "reorth", info.reorth, "relres", info.relres)
+    assert info.reorth >= 1  # the case exercises the second pass
+    assert info.relres <= 1e-12
+    sc = max(np.abs(ref["y"]).max(), np.abs(ref["p"]).max())
+    assert np.abs(host(y).reshape(n, -1) - ref["y"]).max() <= 1e-10 * sc
+    assert np.abs(host(p).reshape(n, -1) - ref["p"]).max() <= 1e-10 * sc
