@@ -34,6 +34,7 @@ CASES = [
     (2, 15, 8, 1.0, 1e-8, 30),
     (2, 31, 32, 0.5, 1e-6, 3),   # several restart cycles
     (2, 63, 16, 0.6, 1e-4, 2),
+    (2, 127, 4, 1.0, 1e-4, 30),  # two frequencies: most chunks of the contraction are empty
 ]
 
 
@@ -73,11 +74,14 @@ def test_lowrank_gmres_matches_oracle(env, dims, M, n, theta, gamma, restart):
     assert np.abs(p.cpu().numpy().reshape(n, -1) - ref_t["p"]).max() <= 1e-10 * sc
 
 
-def test_lowrank_full_size_matches_standard(env):
-    """2D, M = 255, n = 256 (the 2D Crank-Nicolson workload): the low-rank form and the
-    standard form take the same number of iterations and reach the same solution."""
+@pytest.mark.parametrize("M,n", [(255, 256), (511, 16)])
+def test_lowrank_full_size_matches_standard(env, M, n):
+    """2D, M = 255, n = 256 (the 2D Crank-Nicolson workload), and the 512-point sine
+    transforms (M = 511): the low-rank form and the standard form take the same number of
+    iterations and reach the same solution."""
     torch, wc = env
-    dims, M, n = 2, 255, 256
+    dims = 2
+    print("lowrank vs standard", M, n, flush=True)
     d = datagen.config_problem(dims, M, n, seed=0, noise_sigma=1e-3)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     f, g, y0 = dev(d["f"]), dev(d["g"]), dev(d["y0"])
