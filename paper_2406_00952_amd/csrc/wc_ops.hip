@@ -534,9 +534,22 @@ __global__ __launch_bounds__(kThreads) void k_lr_project(const double *__restric
   if (s >= m) return;
   const double *a = r0, *b = r0 + (size_t)n * m;
   double sa = 0.0, sb = 0.0;
-  for (int k = 0; k < n; ++k) {
-    sa += gr[k] * a[(size_t)k * m + s];
-    sb += gr[n + k] * b[(size_t)k * m + s];
+  constexpr int KB = 8;  // loads of KB time levels issued together; the sums keep their order
+  for (int k0 = 0; k0 < n; k0 += KB) {
+    double va[KB], vb[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int k = k0 + u < n ? k0 + u : n - 1;
+      va[u] = a[(size_t)k * m + s];
+      vb[u] = b[(size_t)k * m + s];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      if (k0 + u < n) {
+        sa += gr[k0 + u] * va[u];
+        sb += gr[n + k0 + u] * vb[u];
+      }
+    }
   }
   s0[s] = sa * inv_g2;
   s0[m + s] = sb * inv_r2;
