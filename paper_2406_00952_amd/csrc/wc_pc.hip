@@ -1023,15 +1023,26 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_dst(
   }
 }
 
+// Ahat = (N1/2)(a1 + i a2) of the compact vector (orthonormal sine coordinates), FP64
+__global__ __launch_bounds__(kThreads) void k_lr_ahat(GenIn gi, double ascale, int m,
+                                                      cx<double> *__restrict__ A) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+  A[s] = cx<double>{ascale * (gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]),
+                    ascale * (gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s])};
+}
+
 // The cycle's update in 2D low-rank GMRES, in place over the spectrum array that holds
 // Yhat0: every tile forms c Yhat0 + F (Re Ahat, Im Ahat) of its modes as it loads, solves
 // them, and applies the inverse x2 transform (the inverse x1 and time transforms follow as
-// in the standard apply).  Ahat = (N1/2)(a1 + i a2) from the compact vector and s0.
+// in the standard apply).
 template <typename P, int N1, int TX>
 __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_update(
     cx<P> *__restrict__ W, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
     const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm,
-    GenIn gi, double ascale, const cx<double> *__restrict__ F) {
+    const double *__restrict__ hat, const double *__restrict__ sqn0,
+    const cx<double> *__restrict__ Ah, const cx<double> *__restrict__ F) {
   using C = ColCfg<P, N1, TX>;
   constexpr int M = N1 - 1, S = C::S, PS = C::PS, NT = C::NT, CPW = C::CPW, TT = 2 * TX * M;
   constexpr int TI = TX * M, LIT = (TI + NT - 1) / NT;
@@ -1044,7 +1055,7 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_update(
   const int q = t / ncx, c0 = (t % ncx) * TX;
   const size_t m = (size_t)M * M;
   cx<P> *slab0 = W + (size_t)q * 2 * m, *slab1 = slab0 + m;
-  const double gc = *gi.sqn0 > 0.0 ? gi.hat[0] / *gi.sqn0 : 0.0;
+  const double gc = *sqn0 > 0.0 ? hat[0] / *sqn0 : 0.0;
   // item (c, j2): both block rows of mode (c0 + c, j2); all loads issued first
   cx<P> y0[LIT], y1[LIT];
 #pragma unroll
@@ -1071,9 +1082,8 @@ __global__ __launch_bounds__((ColCfg<P, N1, TX>::NT)) void k_cols_update(
     if (idx >= TI) continue;
     cx<P> u0{(P)0, (P)0}, u1{(P)0, (P)0};
     if (j1 < M) {
-      const int s = j2 * M + j1;
-      const double ax = ascale * (gi.hat[1 + s] * gi.inv_gn - gc * gi.s0[s]);
-      const double ay = ascale * (gi.hat[1 + m + s] * gi.inv_rn - gc * gi.s0[m + s]);
+      const cx<double> A = Ah[j2 * M + j1];
+      const double ax = A.x, ay = A.y;
       u0 = cx<P>{(P)(gc * y0[it].x + f00.x * ax + f01.x * ay),
                  (P)(gc * y0[it].y + f00.y * ax + f01.y * ay)};
       u1 = cx<P>{(P)(gc * y1[it].x + f10.x * ax + f11.x * ay),
@@ -1406,15 +1416,23 @@ hipError_t lr_update_t(const wc_plan &p, const GenIn &gen) {
     const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
     const double c = (1.0 / p.n) * (2.0 / N1) * (2.0 / N1);
     cx<P> *W = (cx<P> *)p.d_specA;
+    cx<double> *A = (cx<double> *)p.d_lr_a;
     const int ncx = (N1 - 2 + TX) / TX;
+    hipError_t e;
     {
-      ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P) + 32.0 * p.m);
+      ProfScope ps(p, K_LR_SETUP, 48.0 * p.m);
+      hipLaunchKernelGGL(k_lr_ahat, dim3((p.m + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                         p.stream, gen, 0.5 * N1, p.m, A);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P) + 16.0 * p.m);
       hipLaunchKernelGGL((k_cols_update<P, N1, TX>), dim3(ncx * (p.n / 2)),
                          dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, W, Tabs<P>::tws(p),
                          Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
-                         (P)p.alpha, (P)c, gen, 0.5 * N1, (const cx<double> *)p.d_lr_rank);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+                         (P)p.alpha, (P)c, gen.hat, gen.sqn0, (const cx<double> *)A,
+                         (const cx<double> *)p.d_lr_rank);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int nlines = p.n * M;
     dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
