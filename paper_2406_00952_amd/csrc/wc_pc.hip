@@ -836,10 +836,11 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
 // ---- 2D: x2-DST, step 2, x2-iDST on tiles of TX x1-columns (both block rows) -------
 // W layout [q][half][x2][x1], x1 already sine transformed (index j1).
 //
-// Generated input (2D low-rank GMRES): both transforms that precede this pass are linear
-// and r0 is fixed within a cycle, so the x1-transformed spectrum of c r0 + [g (x) a1;
-// r (x) a2] is c Y0 + F[q][h][0] A1 + F[q][h][1] A2, with Y0 the cycle's transformed r0,
-// F the time spectra of g and r, and A1 + i A2 the x1 sine transform of a1 + i a2.
+// 2D low-rank GMRES: the time and sine transforms are linear and r0 is fixed within a
+// cycle, so the fully transformed spectrum of c r0 + [g (x) a1; r (x) a2] is
+// c Yhat0 + F[q][h][0] Re Ahat + F[q][h][1] Im Ahat, with Yhat0 the cycle's transformed r0,
+// F the time spectra of g and r, and Ahat the 2D sine transform of a1 + i a2 (k_lr_contract,
+// k_cols_update).
 // The loads of x2 tile t: item (c, h, i) of thread tid reads rows i-1 and N1-i-1 of
 // column c0+c of block row h.
 template <typename P, int N1, int TX>
