@@ -470,9 +470,25 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict_
     for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
     if (SELF) acc[NS - 1] += wi * wi;
   }
+  // every sum's wave reductions first, then thread 0 adds the waves' sums (block_sum's order)
+  // and writes the partials: one barrier instead of two per sum
+  __shared__ double wsum[NS * (kThreads / 64)];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const double r = block_sum(acc[j], red);
-    if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = r;
+    double v = acc[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) wsum[j * (kThreads / 64) + wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < NS; ++j) {
+      double r = 0.0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) r += wsum[j * (kThreads / 64) + w];
+      partials[(size_t)j * gridDim.x + blockIdx.x] = r;
+    }
   }
   if (stage) finalize_if_last(partials, S, stage, jj, red);
 }
