@@ -41,9 +41,29 @@ def make_request(torch, k, spec):
     return kw, dev(d["f"]), dev(d["g"]), dev(d["y0"]), m
 
 
+# low-rank GMRES requests (a = 1; FP32 preconditioner in 2D only)
+MIX_LR = [
+    (2, 63, 64, 0.5, 1e-4, "gmres_ps", "fp64", "const"),
+    (2, 127, 64, 1.0, 1e-3, "gmres_ps", "mixed", "const"),
+    (1, 255, 128, 0.5, 1e-6, "gmres_ps", "fp64", "const"),
+    (2, 31, 32, 1.0, 1e-2, "gmres_ps", "fp64", "const"),
+    (2, 63, 64, 0.5, 1e-4, "gmres_ps", "fp64", "const"),  # same as the first: plan reuse
+]
+
+
 def test_alone_equals_in_mix(env):
+    _alone_equals_in_mix(env, MIX, False)
+
+
+def test_alone_equals_in_mix_lowrank(env):
+    _alone_equals_in_mix(env, MIX_LR, True)
+
+
+def _alone_equals_in_mix(env, mix, lowrank):
     torch, wc = env
-    reqs = [make_request(torch, k, s) for k, s in enumerate(MIX)]
+    reqs = [make_request(torch, k, s) for k, s in enumerate(mix)]
+    for r in reqs:
+        r[0]["lowrank"] = lowrank
     alone = []
     for kw, f, g, y0, m in reqs:
         y = torch.empty(kw["n"] * m, dtype=torch.float64, device="cuda")
@@ -65,7 +85,8 @@ def test_alone_equals_in_mix(env):
         tickets.append(srv.submit(f, g, y0, y, p, **kw))
     for k, t in enumerate(tickets):
         info, q_ms, tot_ms = srv.wait(t)
-        print("request", k, MIX[k], "iters", info.iters, "queue ms", round(q_ms, 2),
+        print("request", k, mix[k], "lowrank", lowrank, "iters", info.iters, "queue ms",
+              round(q_ms, 2),
               "total ms", round(tot_ms, 2), flush=True)
         assert info.status == wc.WC_OK
         assert info.iters == alone[k][2]
