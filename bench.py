@@ -161,9 +161,12 @@ def measured_traffic(kernel, workload, args):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    src = KERNEL_SOURCE.get(kernel.split("_")[0], "wc_ops.hip")
-    with open(os.path.join(ROOT, "paper_2406_00952_amd", "csrc", src), "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
+    # the kernel's source file and the shared header (launch constants live there)
+    digest = hashlib.sha256()
+    for src in (KERNEL_SOURCE.get(kernel.split("_")[0], "wc_ops.hip"), "wc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2406_00952_amd", "csrc", src), "rb") as fh:
+            digest.update(fh.read())
+    digest = digest.hexdigest()
     if fields.get("source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
