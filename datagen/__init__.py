@@ -25,6 +25,7 @@ import numpy as np
 __all__ = [
     "nodes", "times", "face_coefficients", "smooth_modes", "noise",
     "sinusoidal_a", "example1", "example2", "config_problem", "CONFIGS",
+    "log_uniform_gamma",
 ]
 
 
@@ -202,6 +203,12 @@ def config_problem(dims: int, M: int, n: int, T: float = 1.0, seed: int = 0,
     y0 = np.zeros(M ** dims) if y0_zero else smooth_modes(seed + 4, dims, M, 0 + 1, T)[0]
     a_face = None if coeff == "const" else sinusoidal_a(dims, M)
     return dict(f=np.ascontiguousarray(f), g=np.ascontiguousarray(g), y0=y0, a_face=a_face)
+
+
+def log_uniform_gamma(seed: int, lo: float = -8.0, hi: float = -2.0) -> float:
+    """gamma = 10^U(lo, hi) drawn from default_rng(seed + 1000) (its own stream, so the
+    data of the same seed does not change)."""
+    return float(10.0 ** np.random.default_rng(seed + 1000).uniform(lo, hi))
 
 
 def random_vector(seed: int, size: int) -> np.ndarray:

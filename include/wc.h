@@ -146,11 +146,19 @@ wc_status wc_plan_destroy(wc_plan *plan);
 wc_status wc_plan_retarget(wc_plan *plan, const wc_problem *prob, const wc_opts *opts);
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
 /* Times the preconditioner apply (reps applies per candidate, after one warm-up)
- * for every time-FFT tile width (4, 8, 16 spatial columns per workgroup) and,
- * in 2D with a = 1, every x2-pass tile width (4, 8, 16 columns), keeps the
- * fastest pair in the plan and reports it (ts, tx may be NULL).  Uses the plan's
- * Krylov vectors as scratch: call it between solves.  Synchronous. */
+ * for every time-pass choice and, in 2D with a = 1, every x2-pass choice (the values
+ * of wc_plan_set_tiles), keeps the fastest pair in the plan and reports it (ts, tx may
+ * be NULL).  Uses the plan's Krylov vectors as scratch: call it between solves.
+ * Synchronous. */
 wc_status wc_plan_autotune(wc_plan *plan, int reps, int *ts, int *tx);
+/* Sets the preconditioner's kernel choices directly (e.g. to reuse a choice autotuned on
+ * another plan): ts for the time passes (4, 8, 16: tiles of that many spatial columns
+ * with both block rows packed in one complex sequence; -8, -16: tiles of 8 or 16 columns
+ * of one block row, each transformed as an n/2-point sequence, n >= 64), tx for the
+ * 2D x2 pass (4, 8, 16: tiles of that many x1 columns; -4, -8: x1 passes that write a
+ * transposed copy in tiles of 4 or 8 rows and an x2 pass on its contiguous rows, M+1 >=
+ * 128); 0 = default.  WC_E_ARG for other values.  Synchronises the plan's stream. */
+wc_status wc_plan_set_tiles(wc_plan *plan, int ts, int tx);
 
 /* Right-hand side of the transformed system (Section 1: f_tilde, g_tilde
  * with M = I; eqn:main_system / eqn:main_system_nonsym).
@@ -205,10 +213,16 @@ wc_status wc_profile(wc_plan *plan, int enable);
 int wc_profile_read(wc_plan *plan, wc_kernel_stat *out, int max);
 
 /* ---- serving ------------------------------------------------------------------
- * A server runs whole solves (wc_solve) for submitted requests on worker threads,
- * each with its own HIP stream on the device current at wc_server_create, so
- * requests of different sizes share the GPU at kernel granularity and a new
- * request starts as soon as a worker and memory are free.
+ * A server runs submitted requests on the device current at wc_server_create:
+ *  - GMRES(k)-P_S requests in the standard form (lowrank 0) on 2D grids with a == 1,
+ *    zeta == pi and n, M+1 in {64, 128, 256, 512} are continuously batched: one
+ *    batcher thread advances every active solve by one Krylov step per round, with the
+ *    preconditioner of all of them applied in one launch per pass (the batched applies
+ *    below); queued requests join at the next round boundary (up to 32 active) and a
+ *    solve leaves in the round it converges;
+ *  - every other request runs a whole solve (wc_solve) on one of the worker threads,
+ *    each with its own HIP stream, so requests of different sizes share the GPU at
+ *    kernel granularity.
  *
  * Admission by HBM footprint: a request needs wc_plan_footprint_bytes(prob,
  * opts) of device memory for its plan; requests start in submission order while
@@ -248,6 +262,9 @@ wc_status wc_server_wait(wc_server *srv, uint64_t ticket, wc_info *info, double 
 wc_status wc_server_cancel(wc_server *srv, uint64_t ticket);
 /* Device bytes the server holds in plans (running plus idle). */
 size_t wc_server_bytes_in_use(wc_server *srv);
+/* Continuous batching statistics: requests served by the batcher so far and the largest
+ * number of solves active in one of its rounds (either pointer may be NULL). */
+wc_status wc_server_stats(wc_server *srv, uint64_t *batched, int *max_active);
 
 /* ---- batches: many right-hand sides and instances in one launch per pass ---------
  * The preconditioner apply of the three-step decomposition (time transform, spatial

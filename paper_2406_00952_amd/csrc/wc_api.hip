@@ -76,6 +76,18 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   return WC_OK;
 }
 
+// A zero eigenvalue of S_n^(2) (remark on the singular S_n^(2), Section 1: theta = 1/2 with
+// omega^{1/n} e^{-2 pi i l/n} = -1 for some l, e.g. zeta = pi and n odd) with no remedy
+// value.  Host arithmetic only, so plan creation refuses it before touching the device.
+bool singular_s2_unremedied(const wc_problem *pr) {
+  if (pr->s2_remedy != 0.0) return false;
+  for (int l = 0; l < pr->n; ++l) {
+    const std::complex<double> e = std::polar(1.0, (pr->zeta - 2.0 * M_PI * l) / pr->n);
+    if (std::abs(pr->theta + (1.0 - pr->theta) * e) < 1e-13) return true;
+  }
+  return false;
+}
+
 // Whether the GPU preconditioner covers this problem: zeta == pi (real arithmetic, half
 // spectrum), n and M+1 powers of two in [4, 1024] (sine transforms for a == 1, a
 // multigrid hierarchy down to one point otherwise).
@@ -95,8 +107,12 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
 }
 
 struct Sizes {
-  size_t nvec, spec_bytes, partials, tables, vecs, mg, total;
+  size_t nvec, spec_bytes, spec_t_bytes, partials, tables, vecs, mg, total;
 };
+
+bool uses_spec_t(const wc_problem *pr, const wc_opts *op) {
+  return pr->dims == 2 && !pr->a_face_host && !op->lowrank && pr->M + 1 >= 128 && pc_path_ok(pr);
+}
 
 // Multigrid levels M_0 = M, M_{l+1} = (M_l - 1)/2, ..., 1; the first level whose remaining
 // pyramid fits the LDS budget of one workgroup; bytes of u and f of levels 1..ltop.
@@ -129,7 +145,12 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.nvec = 2 * (size_t)pr->n * m;
   const size_t es = op->precision == WC_MIXED ? 8 : 16;
   s.spec_bytes = (size_t)pr->n * m * es;  // n/2 frequencies x 2 halves x m complex
-  size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads), (size_t)32 * kRedBlocks);
+  // 2D a == 1 (standard form), N1 >= 128: the transposed copy of the x2 pass, rows of N1
+  s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es : 0;
+  // the Gram-Schmidt reduction of GMRES step j writes (j + 2) rows of kRedBlocks partials
+  // (j + 1 projections and the norm), j < kMaxRestart
+  size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads),
+                                  (size_t)(kMaxRestart + 2) * kRedBlocks);
   parts = std::max<size_t>(parts, (size_t)pc_partials_needed(pr->n, (int)m, op->precision));
   s.partials = parts + 64;
   s.tables = 1 << 20;
@@ -146,7 +167,7 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
            (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
            (size_t)pr->n * 6 * sizeof(double);
   }
-  s.total = s.spec_bytes + s.partials * sizeof(double) + s.tables + s.vecs +
+  s.total = s.spec_bytes + s.spec_t_bytes + s.partials * sizeof(double) + s.tables + s.vecs +
             S_COUNT * sizeof(double) + s.mg;
   return s;
 }
@@ -233,7 +254,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_lam64); dfree(p->d_lam32); dfree(p->d_dtw);
   dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
-  dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_partials); dfree(p->d_scal);
+  dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_specT); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
   dfree(p->d_lr_gr); dfree(p->d_lr_s0); dfree(p->d_lr_hat); dfree(p->d_lr_rho);
@@ -882,6 +903,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   *out = nullptr;
   wc_status vs = validate(prob, opts);
   if (vs != WC_OK) return vs;
+  if (singular_s2_unremedied(prob)) return WC_E_SINGULAR_S2;
   wc_plan *p = new (std::nothrow) wc_plan();
   if (!p) return WC_E_NOMEM;
   p->dims = prob->dims;
@@ -917,6 +939,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
     if (hipMalloc(ptr, bytes) != hipSuccess) oom = true;
   };
   alloc(&p->d_specA, sz.spec_bytes);
+  if (sz.spec_t_bytes && p->pc_ok) alloc(&p->d_specT, sz.spec_t_bytes);
   if (p->var_coeff) alloc(&p->d_specB, sz.spec_bytes);
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
@@ -997,12 +1020,16 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   const bool prof = p->prof.on;
   p->prof.on = false;
   WC_TRY(launch_fill(*p, v, 1.0, p->nvec));
-  const int tss[3] = {4, 8, 16}, txs[3] = {4, 8, 16};
-  const int ntx = (p->dims == 2 && !p->var_coeff) ? 3 : 1;
+  // time-FFT tile widths; x2 pass: column tiles of 4, 8, 16, or the transposed rows in
+  // x1 tiles of 4 or 8 rows (tx < 0, when the plan holds the transposed copy)
+  // time passes: packed tiles of 4, 8, 16 columns, or per-block-row tiles of 8, 16 (< 0)
+  const int tss[5] = {4, 8, 16, -8, -16}, txs[5] = {4, 8, 16, -4, -8};
+  const int nts = p->n >= 64 ? 5 : 3;
+  const int ntx = (p->dims == 2 && !p->var_coeff) ? (p->d_specT ? 5 : 3) : 1;
   float best = -1.f;
   int bts = p->ts_time, btx = p->tx_cols;
   hipError_t e = hipSuccess;
-  for (int it = 0; it < 3 && e == hipSuccess; ++it)
+  for (int it = 0; it < nts && e == hipSuccess; ++it)
     for (int ix = 0; ix < ntx && e == hipSuccess; ++ix) {
       p->ts_time = tss[it];
       p->tx_cols = ntx > 1 ? txs[ix] : 0;
@@ -1028,6 +1055,19 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   if (e != hipSuccess) return WC_E_HIP;
   if (ts_out) *ts_out = bts;
   if (tx_out) *tx_out = btx;
+  return WC_OK;
+}
+
+wc_status wc_plan_set_tiles(wc_plan *p, int ts, int tx) {
+  if (!p) return WC_E_ARG;
+  const bool ts_ok = ts == 0 || ts == 4 || ts == 8 || ts == 16 || ts == -8 || ts == -16;
+  const bool tx_ok = tx == 0 || tx == 4 || tx == 8 || tx == 16 ||
+                     ((tx == -4 || tx == -8) && p->d_specT);
+  if (!ts_ok || !tx_ok) return WC_E_ARG;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return WC_E_HIP;
+  p->ts_time = ts;
+  p->tx_cols = tx;
+  drop_graphs(p);  // captured launches hold the previous kernel choice
   return WC_OK;
 }
 

@@ -56,8 +56,10 @@ bool same_stream(const wc_batch &b) {
 // E = Ahat P^{-1} - I with classical Gram-Schmidt and a DGKS-gated second pass, the
 // restart test on the true residual b - Ahat x; the same steps as the single solve.
 struct Lane {
-  enum Phase { BETA, ARNOLDI, DONE };
+  enum Phase { INIT, BETA, ARNOLDI, DONE };
   wc_plan *p = nullptr;
+  uint64_t tag = 0;                       // caller's identifier (continuous batching)
+  double *yo = nullptr, *po = nullptr, *uo = nullptr;
   double *B = nullptr, *X = nullptr, *V = nullptr, *Zb = nullptr, *T = nullptr;
   int k = 0, total = 0, cycles = 0, reorth = 0, j = 0;
   bool flex = false;
@@ -154,6 +156,245 @@ hipError_t cycle_update(Lane &L, int jd) {
   return launch_lincomb3(p, L.X, L.X, L.Zb, nullptr, -1, 1.0, 1.0, 0.0);
 }
 
+// Lane set-up shared by the lockstep batch and the continuous engine: buffers from the
+// plan's Krylov vectors, the right-hand side and the request of ||b|| to the host.
+hipError_t lane_setup(Lane &L, wc_plan &p, const double *f, const double *g, const double *y0) {
+  L.p = &p;
+  L.k = p.opts.restart;
+  L.flex = p.opts.flexible || p.opts.precision == WC_MIXED;
+  L.V = p.vec(0);
+  L.Zb = p.vec(L.k + 1);
+  L.T = p.vec(L.k + 1 + (L.flex ? L.k : 1));
+  L.B = p.vec(p.nkvec - 2);
+  L.X = p.vec(p.nkvec - 1);
+  L.H.assign((size_t)(L.k + 1) * L.k, 0.0);
+  L.cs.assign(L.k, 0.0);
+  L.sn.assign(L.k, 0.0);
+  L.g.assign(L.k + 1, 0.0);
+  L.y.assign(L.k, 0.0);
+  L.nu.assign(L.k + 1, 0.0);
+  hipError_t e = launch_rhs(p, f, g, y0, L.B);
+  if (e == hipSuccess) e = launch_dot(p, L.B, L.B, S_DOT);
+  if (e == hipSuccess) e = read_async(&p, S_DOT, 1);
+  return e;
+}
+
+// After the synchronisation that follows lane_setup: ||b||, x = 0 and the first cycle.
+hipError_t lane_start(Lane &L) {
+  L.bnorm = std::sqrt(L.p->h_scal[S_DOT]);
+  hipError_t e = launch_fill(*L.p, L.X, 0.0, L.p->nvec);
+  if (e != hipSuccess) return e;
+  if (!std::isfinite(L.bnorm)) {
+    L.ph = Lane::DONE;
+    L.st = WC_E_NONFINITE;
+  } else if (L.bnorm == 0.0) {
+    L.ph = Lane::DONE;
+    L.st = WC_OK;
+    L.relres = L.relres_est = 0.0;
+  } else {
+    e = start_cycle(L, true);
+    L.ph = Lane::BETA;
+  }
+  return e;
+}
+
+// Host side of one round for a lane that was in phase `was` when the round's work was
+// enqueued (the restart test, or the Arnoldi step and possibly the cycle's end).
+hipError_t lane_advance(Lane &L, Lane::Phase was) {
+  wc_plan &p = *L.p;
+  if (was == Lane::INIT) return lane_start(L);
+  if (was == Lane::BETA) {
+    const double beta = std::sqrt(p.h_scal[S_NU2]);
+    L.relres = beta / L.bnorm;
+    if (!std::isfinite(L.relres)) {
+      L.ph = Lane::DONE;
+      L.st = WC_E_NONFINITE;
+    } else if (L.relres <= p.opts.tol) {
+      L.ph = Lane::DONE;
+      L.st = WC_OK;
+    } else if (L.total >= p.opts.maxit) {
+      L.ph = Lane::DONE;
+      L.st = WC_E_MAXIT;
+    } else {
+      L.nu[0] = beta;
+      std::fill(L.g.begin(), L.g.end(), 0.0);
+      L.g[0] = beta;
+      L.j = 0;
+      L.ph = Lane::ARNOLDI;
+    }
+    return hipSuccess;
+  }
+  if (was == Lane::ARNOLDI) {
+    if (!arnoldi_host(L, p.opts.tol, p.opts.maxit)) {
+      ++L.j;
+      return hipSuccess;
+    }
+    hipError_t e = cycle_update(L, L.j + 1);
+    if (e != hipSuccess) return e;
+    ++L.cycles;
+    e = start_cycle(L, false);
+    L.ph = Lane::BETA;
+    return e;
+  }
+  return hipSuccess;
+}
+
+wc_info lane_info(const Lane &L) {
+  wc_info in;
+  std::memset(&in, 0, sizeof(in));
+  in.status = L.st;
+  in.iters = L.total;
+  in.restarts = L.cycles;
+  in.relres = L.relres;
+  in.relres_est = L.relres_est;
+  in.reorth = L.reorth;
+  return in;
+}
+
+BatchInst batch_inst(const wc_plan &p) {
+  const bool f32 = p.opts.precision == WC_MIXED;
+  BatchInst I{};
+  I.n = p.n;
+  I.N1 = p.N1;
+  I.m = p.m;
+  I.kind = pc_kind(p);
+  I.tau = p.tau;
+  I.alpha = p.alpha;
+  I.cnorm = (1.0 / p.n) * (2.0 / p.N1) * (2.0 / p.N1);
+  I.W = p.d_specA;
+  I.dtw = p.d_dtw;
+  I.twt = f32 ? (const void *)p.d_twt32 : (const void *)p.d_twt64;
+  I.tws = f32 ? (const void *)p.d_tws32 : (const void *)p.d_tws64;
+  I.sin = f32 ? (const void *)p.d_sin32 : (const void *)p.d_sin64;
+  I.lam = f32 ? (const void *)p.d_lam32 : (const void *)p.d_lam64;
+  I.mu = f32 ? (const void *)p.d_mu32 : (const void *)p.d_mu64;
+  return I;
+}
+
+}  // namespace
+
+// ---- continuous batching ------------------------------------------------------------
+// The lanes of a lockstep GMRES(k)-P_S whose membership changes between rounds: a solve
+// joins (its right-hand side and ||b|| are enqueued at once and it starts its first cycle
+// after the next synchronisation) and leaves (its solution recovered) at any round
+// boundary, while the others keep iterating.  Each round applies the preconditioner of
+// every lane inside an Arnoldi cycle in one batched launch per pass and precision, then
+// each lane's matvec and Gram-Schmidt passes, and synchronises the host once.
+struct LockstepEngine {
+  hipStream_t st = nullptr;
+  std::vector<Lane> lanes;
+  BatchInst *d_tab = nullptr;  // kBatchMax entries, rebuilt when the lanes change
+  BatchInst *h_tab = nullptr;  // pinned staging of the table
+  bool dirty = true;
+};
+
+namespace wc {
+
+bool lockstep_eligible(const wc_problem *pr, const wc_opts *op) {
+  const auto p2 = [](int x) { return x == 64 || x == 128 || x == 256 || x == 512; };
+  return pr->dims == 2 && !pr->a_face_host && op->method == WC_GMRES_PS && !op->lowrank &&
+         std::fabs(pr->zeta - M_PI) <= 1e-12 && p2(pr->n) && p2(pr->M + 1);
+}
+
+LockstepEngine *lockstep_create(hipStream_t st) {
+  auto *eng = new (std::nothrow) LockstepEngine;
+  if (!eng) return nullptr;
+  eng->st = st;
+  if (hipMalloc((void **)&eng->d_tab, kBatchMax * sizeof(BatchInst)) != hipSuccess ||
+      hipHostMalloc((void **)&eng->h_tab, kBatchMax * sizeof(BatchInst), 0) != hipSuccess) {
+    (void)hipGetLastError();
+    lockstep_destroy(eng);
+    return nullptr;
+  }
+  return eng;
+}
+
+void lockstep_destroy(LockstepEngine *eng) {
+  if (!eng) return;
+  if (eng->st) (void)hipStreamSynchronize(eng->st);
+  if (eng->d_tab) (void)hipFree(eng->d_tab);
+  if (eng->h_tab) (void)hipHostFree(eng->h_tab);
+  delete eng;
+}
+
+int lockstep_active(const LockstepEngine *eng) { return (int)eng->lanes.size(); }
+
+hipError_t lockstep_add(LockstepEngine *eng, wc_plan *p, const double *f, const double *g,
+                        const double *y0, double *y, double *pout, double *u, uint64_t tag) {
+  if ((int)eng->lanes.size() >= kBatchMax || p->stream != eng->st || !p->pc_ok ||
+      p->dims != 2 || p->var_coeff || !batch_sizes_ok(p->n, p->N1))
+    return hipErrorInvalidValue;
+  Lane L;
+  L.tag = tag;
+  L.yo = y;
+  L.po = pout;
+  L.uo = u;
+  L.ph = Lane::INIT;
+  hipError_t e = lane_setup(L, *p, f, g, y0);
+  if (e != hipSuccess) return e;
+  eng->lanes.push_back(std::move(L));
+  eng->dirty = true;
+  return hipSuccess;
+}
+
+hipError_t lockstep_round(LockstepEngine *eng, std::vector<LockstepDone> &done) {
+  std::vector<Lane> &lanes = eng->lanes;
+  const int cnt = (int)lanes.size();
+  if (cnt == 0) return hipSuccess;
+  hipError_t e;
+  if (eng->dirty) {  // the previous round synchronised: the staging buffer is free
+    for (int i = 0; i < cnt; ++i) eng->h_tab[i] = batch_inst(*lanes[i].p);
+    e = hipMemcpyAsync(eng->d_tab, eng->h_tab, cnt * sizeof(BatchInst), hipMemcpyHostToDevice,
+                       eng->st);
+    if (e != hipSuccess) return e;
+    eng->dirty = false;
+  }
+  for (int fp32 = 0; fp32 < 2; ++fp32) {  // one batched apply per precision
+    std::vector<int> idx;
+    std::vector<const double *> vin;
+    std::vector<double *> wout;
+    for (int i = 0; i < cnt; ++i) {
+      const Lane &L = lanes[i];
+      if (L.ph != Lane::ARNOLDI || (L.p->opts.precision == WC_MIXED) != (fp32 == 1)) continue;
+      idx.push_back(i);
+      vin.push_back(L.V + (size_t)L.j * L.p->nvec);
+      wout.push_back(L.Zj());
+    }
+    if (idx.empty()) continue;
+    e = launch_pc_batch(eng->st, eng->d_tab, eng->h_tab, (int)idx.size(), idx.data(), vin.data(),
+                        wout.data(), fp32 == 1);
+    if (e != hipSuccess) return e;
+  }
+  for (Lane &L : lanes)
+    if (L.ph == Lane::ARNOLDI && (e = arnoldi_tail(L)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(eng->st)) != hipSuccess) return e;
+  std::vector<Lane::Phase> was(cnt);
+  for (int i = 0; i < cnt; ++i) was[i] = lanes[i].ph;
+  for (int i = 0; i < cnt; ++i)
+    if ((e = lane_advance(lanes[i], was[i])) != hipSuccess) return e;
+  bool any = false;
+  for (Lane &L : lanes) {
+    if (L.ph != Lane::DONE) continue;
+    any = true;
+    if (L.st == WC_OK || L.st == WC_E_MAXIT)
+      if ((e = launch_recover(*L.p, L.X, L.yo, L.po, L.uo)) != hipSuccess) return e;
+  }
+  if (!any) return hipSuccess;
+  if ((e = hipStreamSynchronize(eng->st)) != hipSuccess) return e;
+  std::vector<Lane> keep;
+  for (Lane &L : lanes) {
+    if (L.ph == Lane::DONE) done.push_back({L.tag, L.p, lane_info(L)});
+    else keep.push_back(std::move(L));
+  }
+  lanes.swap(keep);
+  eng->dirty = true;
+  return hipSuccess;
+}
+
+}  // namespace wc
+
+namespace {
+
 wc_status run_batch_gmres(wc_batch &b, const double *const *f, const double *const *g,
                           const double *const *y0, double *const *y, double *const *pout,
                           wc_info *infos) {
@@ -161,42 +402,11 @@ wc_status run_batch_gmres(wc_batch &b, const double *const *f, const double *con
   hipStream_t st = b.plans[0]->stream;
   std::vector<Lane> lanes(cnt);
   for (int i = 0; i < cnt; ++i) {
-    Lane &L = lanes[i];
-    wc_plan &p = *b.plans[i];
-    L.p = &p;
-    L.k = p.opts.restart;
-    L.flex = p.opts.flexible || p.opts.precision == WC_MIXED;
-    L.V = p.vec(0);
-    L.Zb = p.vec(L.k + 1);
-    L.T = p.vec(L.k + 1 + (L.flex ? L.k : 1));
-    L.B = p.vec(p.nkvec - 2);
-    L.X = p.vec(p.nkvec - 1);
-    L.H.assign((size_t)(L.k + 1) * L.k, 0.0);
-    L.cs.assign(L.k, 0.0);
-    L.sn.assign(L.k, 0.0);
-    L.g.assign(L.k + 1, 0.0);
-    L.y.assign(L.k, 0.0);
-    L.nu.assign(L.k + 1, 0.0);
-    WC_TRY(launch_rhs(p, f[i], g[i], y0[i], L.B));
-    WC_TRY(launch_dot(p, L.B, L.B, S_DOT));
-    WC_TRY(read_async(&p, S_DOT, 1));
+    lanes[i].ph = Lane::INIT;
+    WC_TRY(lane_setup(lanes[i], *b.plans[i], f[i], g[i], y0[i]));
   }
   if (hipStreamSynchronize(st) != hipSuccess) return WC_E_HIP;
-  for (Lane &L : lanes) {
-    L.bnorm = std::sqrt(L.p->h_scal[S_DOT]);
-    WC_TRY(launch_fill(*L.p, L.X, 0.0, L.p->nvec));
-    if (!std::isfinite(L.bnorm)) {
-      L.ph = Lane::DONE;
-      L.st = WC_E_NONFINITE;
-    } else if (L.bnorm == 0.0) {
-      L.ph = Lane::DONE;
-      L.st = WC_OK;
-      L.relres = L.relres_est = 0.0;
-    } else {
-      WC_TRY(start_cycle(L, true));
-      L.ph = Lane::BETA;
-    }
-  }
+  for (Lane &L : lanes) WC_TRY(lane_start(L));
   std::vector<Lane::Phase> was(cnt);
   for (;;) {
     // every lane in an Arnoldi cycle advances one step: one batched preconditioner apply
@@ -216,54 +426,13 @@ wc_status run_batch_gmres(wc_batch &b, const double *const *f, const double *con
     for (int i : idx) WC_TRY(arnoldi_tail(lanes[i]));
     if (hipStreamSynchronize(st) != hipSuccess) return WC_E_HIP;
     for (int i = 0; i < cnt; ++i) was[i] = lanes[i].ph;
-    for (int i = 0; i < cnt; ++i) {
-      Lane &L = lanes[i];
-      wc_plan &p = *L.p;
-      if (was[i] == Lane::BETA) {  // the restart test of the previous step's enqueue
-        const double beta = std::sqrt(p.h_scal[S_NU2]);
-        L.relres = beta / L.bnorm;
-        if (!std::isfinite(L.relres)) {
-          L.ph = Lane::DONE;
-          L.st = WC_E_NONFINITE;
-        } else if (L.relres <= p.opts.tol) {
-          L.ph = Lane::DONE;
-          L.st = WC_OK;
-        } else if (L.total >= p.opts.maxit) {
-          L.ph = Lane::DONE;
-          L.st = WC_E_MAXIT;
-        } else {
-          L.nu[0] = beta;
-          std::fill(L.g.begin(), L.g.end(), 0.0);
-          L.g[0] = beta;
-          L.j = 0;
-          L.ph = Lane::ARNOLDI;
-        }
-      } else if (was[i] == Lane::ARNOLDI) {
-        if (!arnoldi_host(L, p.opts.tol, p.opts.maxit)) {
-          ++L.j;
-          continue;
-        }
-        WC_TRY(cycle_update(L, L.j + 1));
-        ++L.cycles;
-        WC_TRY(start_cycle(L, false));
-        L.ph = Lane::BETA;
-      }
-    }
+    for (int i = 0; i < cnt; ++i) WC_TRY(lane_advance(lanes[i], was[i]));
   }
   for (int i = 0; i < cnt; ++i) {
     Lane &L = lanes[i];
     if (L.st == WC_OK || L.st == WC_E_MAXIT)
       WC_TRY(launch_recover(*L.p, L.X, y[i], pout[i], nullptr));
-    if (infos) {
-      wc_info &in = infos[i];
-      std::memset(&in, 0, sizeof(in));
-      in.status = L.st;
-      in.iters = L.total;
-      in.restarts = L.cycles;
-      in.relres = L.relres;
-      in.relres_est = L.relres_est;
-      in.reorth = L.reorth;
-    }
+    if (infos) infos[i] = lane_info(L);
   }
   if (hipStreamSynchronize(st) != hipSuccess) return WC_E_HIP;
   wc_status worst = WC_OK;
@@ -290,26 +459,7 @@ wc_status wc_batch_create(wc_plan *const *plans, int count, wc_batch **out) {
   auto *b = new (std::nothrow) wc_batch;
   if (!b) return WC_E_NOMEM;
   b->plans.assign(plans, plans + count);
-  for (wc_plan *pp : b->plans) {
-    const wc_plan &p = *pp;
-    const bool f32 = p.opts.precision == WC_MIXED;
-    BatchInst I{};
-    I.n = p.n;
-    I.N1 = p.N1;
-    I.m = p.m;
-    I.kind = pc_kind(p);
-    I.tau = p.tau;
-    I.alpha = p.alpha;
-    I.cnorm = (1.0 / p.n) * (2.0 / p.N1) * (2.0 / p.N1);
-    I.W = p.d_specA;
-    I.dtw = p.d_dtw;
-    I.twt = f32 ? (const void *)p.d_twt32 : (const void *)p.d_twt64;
-    I.tws = f32 ? (const void *)p.d_tws32 : (const void *)p.d_tws64;
-    I.sin = f32 ? (const void *)p.d_sin32 : (const void *)p.d_sin64;
-    I.lam = f32 ? (const void *)p.d_lam32 : (const void *)p.d_lam64;
-    I.mu = f32 ? (const void *)p.d_mu32 : (const void *)p.d_mu64;
-    b->h_tab.push_back(I);
-  }
+  for (wc_plan *pp : b->plans) b->h_tab.push_back(batch_inst(*pp));
   const size_t bytes = b->h_tab.size() * sizeof(BatchInst);
   if (hipMalloc((void **)&b->d_tab, bytes) != hipSuccess) {
     (void)hipGetLastError();

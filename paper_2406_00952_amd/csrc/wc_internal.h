@@ -111,8 +111,10 @@ struct wc_plan {
   bool var_coeff = false;
   bool pc_ok = false;            // the GPU preconditioner covers this problem
   int num_cu = 256;              // compute units of the plan's device
-  int ts_time = 0;               // time-FFT tile width (0: default)
-  int tx_cols = 0;               // x2-pass tile width (0: default)
+  int ts_time = 0;               // time passes: > 0 packed tile width, < 0 per-block-row
+                                 // tile width (n >= 64), 0: default
+  int tx_cols = 0;               // x2 pass: > 0 column tile width, < 0 transposed rows with
+                                 // -tx_cols rows per x1 tile (0: default)
   wc_opts opts{};
   hipStream_t stream = nullptr;
   size_t nvec = 0;          // 2*n*m
@@ -132,6 +134,8 @@ struct wc_plan {
   // workspaces
   void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
   void *d_specB = nullptr;       // n*m complex (P): multigrid fine solution (variable a)
+  void *d_specT = nullptr;       // 2D, a == 1, N1 >= 128: the spectrum after the x1 pass,
+                                 // transposed, [q][half][j1][x2] with row stride N1
   double *d_partials = nullptr;  // reduction partials
   double *d_scal = nullptr;      // Krylov scalars (wc::S_COUNT)
   double *h_scal = nullptr;      // pinned host mirror
@@ -331,4 +335,25 @@ hipError_t launch_pc_batch(hipStream_t st, const BatchInst *d_tab, const BatchIn
                            bool fp32);
 int pc_partials_needed(int n, int m, int precision);
 
+}  // namespace wc
+
+// ---- continuous batching (wc_batch.hip) -------------------------------------------------
+struct LockstepEngine;
+namespace wc {
+// GMRES(k)-P_S solves that can join a lockstep engine: 2D, a == 1, zeta == pi, standard
+// form, n and M + 1 in {64, 128, 256, 512}
+bool lockstep_eligible(const wc_problem *pr, const wc_opts *op);
+LockstepEngine *lockstep_create(hipStream_t st);
+void lockstep_destroy(LockstepEngine *eng);
+int lockstep_active(const LockstepEngine *eng);
+// a solve joins (its plan's stream must be the engine's); asynchronous
+hipError_t lockstep_add(LockstepEngine *eng, wc_plan *p, const double *f, const double *g,
+                        const double *y0, double *y, double *pout, double *u, uint64_t tag);
+struct LockstepDone {
+  uint64_t tag;
+  wc_plan *plan;
+  wc_info info;
+};
+// one round; the solves that finished in it (y, p, u written) are appended to done
+hipError_t lockstep_round(LockstepEngine *eng, std::vector<LockstepDone> &done);
 }  // namespace wc

@@ -16,6 +16,8 @@
 namespace wc {
 namespace {
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ double block_sum(double v, double *sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -463,12 +465,28 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const double *__restrict_
   double acc[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) acc[j] = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads) {
-    const double wi = w[i];
+  if ((nv & 1) == 0) {  // pairs of elements: 16-byte loads (every vector starts 16-aligned)
+    const size_t np = nv >> 1;
+    const d2v *w2 = reinterpret_cast<const d2v *>(w);
+    const d2v *b2 = reinterpret_cast<const d2v *>(basis);
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < np;
+         i += (size_t)gridDim.x * kThreads) {
+      const d2v wi = w2[i];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
-    if (SELF) acc[NS - 1] += wi * wi;
+      for (int j = 0; j < NB; ++j) {
+        const d2v b = __builtin_nontemporal_load(b2 + (size_t)j * np + i);
+        acc[j] += b.x * wi.x + b.y * wi.y;
+      }
+      if (SELF) acc[NS - 1] += wi.x * wi.x + wi.y * wi.y;
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+         i += (size_t)gridDim.x * kThreads) {
+      const double wi = w[i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[j] += basis[(size_t)j * nv + i] * wi;
+      if (SELF) acc[NS - 1] += wi * wi;
+    }
   }
   // every sum's wave reductions first, then thread 0 adds the waves' sums (block_sum's order)
   // and writes the partials: one barrier instead of two per sum
@@ -509,13 +527,31 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
 #pragma unroll
   for (int j = 0; j < NB; ++j) c[j] = sign * scal[slot + j];
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads) {
-    double v = w[i];
+  if ((nv & 1) == 0) {  // pairs of elements: 16-byte loads and stores
+    const size_t np = nv >> 1;
+    d2v *w2 = reinterpret_cast<d2v *>(w);
+    const d2v *b2 = reinterpret_cast<const d2v *>(basis);
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < np;
+         i += (size_t)gridDim.x * kThreads) {
+      d2v v = w2[i];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) v += c[j] * basis[(size_t)j * nv + i];
-    w[i] = v;
-    acc += v * v;
+      for (int j = 0; j < NB; ++j) {
+        const d2v b = __builtin_nontemporal_load(b2 + (size_t)j * np + i);
+        v.x += c[j] * b.x;
+        v.y += c[j] * b.y;
+      }
+      w2[i] = v;
+      acc += v.x * v.x + v.y * v.y;
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+         i += (size_t)gridDim.x * kThreads) {
+      double v = w[i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) v += c[j] * basis[(size_t)j * nv + i];
+      w[i] = v;
+      acc += v * v;
+    }
   }
   if (partials) {
     const double r = block_sum(acc, red);

@@ -661,6 +661,152 @@ __global__ __launch_bounds__((TimeCfg<P, N, TS, kTimeWavesInv>::NT)) void k_tfft
                                      xcd_tile(blockIdx.x, gridDim.x), buf, stw, red);
 }
 
+// ---- step 1a / 3b per block row: the time transform as an n/2-point FFT -----------------
+// At zeta = pi the kept coefficients are a real sequence's DFT at half-integer frequencies,
+// Y_p = sum_k v_k e^{-2 pi i k (p + 1/2)/n}, p < n/2 (frequency l = p + 1).  With
+// z_j = e^{-2 pi i j/n} (v_{2j} + i v_{2j+1}) and Z its n/2-point DFT,
+//   E_p = (Z_p + conj Z_{p'})/2,  O_p = (Z_p - conj Z_{p'})/(2i),  p' = n/2 - 1 - p,
+//   Y_p = E_p + c_p O_p,  Y_{p'} = conj(E_p - c_p O_p),  c_p = e^{-i pi (2p+1)/n}
+// (E and O are the DFTs of the twiddled even and odd samples, each conjugate symmetric
+// under p <-> p').  The inverse runs the same steps backwards:
+//   E_p = (Y_p + conj Y_{p'})/2,  O_p = conj(c_p) (Y_p - conj Y_{p'})/2,  Z_p = E_p + i O_p,
+//   Z_{p'} = conj E_p + i conj O_p,  v_{2j} + i v_{2j+1} = 2 e^{2 pi i j/n} IDFT(Z)_j
+// (unnormalised like the one-sequence form: the 1/n sits in step 2).  Each block row is
+// transformed on its own, so a tile of TS columns holds n/2 complex values per column: half
+// the LDS of the packed form at the same tile width, or twice the width (the real input
+// rows read TS * 8 bytes at a time) at the same LDS.
+template <typename P, int N, int TS, int WV = 4> struct TimeCfgH {
+  static constexpr int N2 = N / 2;
+  static constexpr int WAVES = TS < WV ? TS : WV;
+  static constexpr int NT = 64 * WAVES;
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 4;
+  static constexpr int PN = padded<PS>(N2);
+  static constexpr int S = TS + 1;
+  static constexpr int TILE = PN * S * CXB + N2 * CXB;
+};
+
+template <typename P, int N, int TS>
+__global__ __launch_bounds__((TimeCfgH<P, N, TS>::NT)) void k_tfft_fwd_h(
+    const double *__restrict__ v, cx<P> *__restrict__ W, const cx<double> *__restrict__ dtw,
+    const cx<double> *__restrict__ twt, int m, int ntile) {
+  using C = TimeCfgH<P, N, TS>;
+  constexpr int N2 = C::N2, S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
+  constexpr int LIT = (N2 * TS + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * S];
+  __shared__ cx<P> stw[N2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int h = t / ntile, s0 = (t % ntile) * TS;
+  const double *src = v + (size_t)h * N * m;
+  double ra[LIT], rb[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {  // every load issued before any is consumed
+    const int idx = tid + it * NT, j = idx / TS, gs = s0 + idx % TS;
+    ra[it] = 0.0;
+    rb[it] = 0.0;
+    if ((N2 * TS % NT == 0 || idx < N2 * TS) && gs < m) {
+      ra[it] = __builtin_nontemporal_load(src + (size_t)(2 * j) * m + gs);
+      rb[it] = __builtin_nontemporal_load(src + (size_t)(2 * j + 1) * m + gs);
+    }
+  }
+  for (int i = tid; i < N2; i += NT) {  // e^{-2 pi i p/(n/2)}
+    const cx<double> w = twt[2 * i];
+    stw[i] = cx<P>{(P)w.x, (P)w.y};
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (N2 * TS % NT == 0 || idx < N2 * TS) {
+      const int j = idx / TS, s = idx % TS;
+      const cx<double> w = twt[j];
+      buf[pk<PS>(j) * S + s] = cx<P>{(P)(ra[it] * w.x - rb[it] * w.y), (P)(ra[it] * w.y + rb[it] * w.x)};
+    }
+  }
+  __syncthreads();
+  wfft<P, N2, 1, CPW, S, PS, false, true>(buf + wv * CPW, stw, lane);
+  __syncthreads();
+  for (int idx = tid; idx < (N2 / 2) * TS; idx += NT) {
+    const int p = idx / TS, s = idx % TS, gs = s0 + s;
+    if (gs >= m) continue;
+    const int pp = N2 - 1 - p;
+    const cx<P> Zp = buf[pk<PS>(p) * S + s], Zq = buf[pk<PS>(pp) * S + s];
+    const cx<P> E = {(Zp.x + Zq.x) * (P)0.5, (Zp.y - Zq.y) * (P)0.5};
+    const cx<P> O = {(Zp.y + Zq.y) * (P)0.5, (Zq.x - Zp.x) * (P)0.5};  // (Zp - conj Zq)/(2i)
+    const cx<double> d = dtw[2 * p + 1];                                // c_p = conj(d)
+    const cx<P> cO = cmul(cx<P>{(P)d.x, (P)-d.y}, O);
+    W[((size_t)p * 2 + h) * m + gs] = cadd(E, cO);
+    W[((size_t)pp * 2 + h) * m + gs] = cx<P>{E.x - cO.x, cO.y - E.y};
+  }
+}
+
+template <typename P, int N, int TS>
+__global__ __launch_bounds__((TimeCfgH<P, N, TS>::NT)) void k_tfft_inv_h(
+    const cx<P> *__restrict__ W, double *__restrict__ out, const cx<double> *__restrict__ dtw,
+    const cx<double> *__restrict__ twt, int m, int ntile, const double *__restrict__ dotv,
+    double *__restrict__ partials) {
+  using C = TimeCfgH<P, N, TS>;
+  constexpr int N2 = C::N2, S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
+  constexpr int HT = (N2 / 2) * TS, LIT = (HT + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * S];
+  __shared__ cx<P> stw[N2];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int h = t / ntile, s0 = (t % ntile) * TS;
+  cx<P> ya[LIT], yb[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT, p = idx / TS, gs = s0 + idx % TS;
+    ya[it] = cx<P>{(P)0, (P)0};
+    yb[it] = cx<P>{(P)0, (P)0};
+    if ((HT % NT == 0 || idx < HT) && gs < m) {
+      ya[it] = W[((size_t)p * 2 + h) * m + gs];
+      yb[it] = W[((size_t)(N2 - 1 - p) * 2 + h) * m + gs];
+    }
+  }
+  for (int i = tid; i < N2; i += NT) {
+    const cx<double> w = twt[2 * i];
+    stw[i] = cx<P>{(P)w.x, (P)w.y};
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (HT % NT == 0 || idx < HT) {
+      const int p = idx / TS, s = idx % TS;
+      const cx<P> Yp = ya[it], Yq = yb[it];
+      const cx<P> E = {(Yp.x + Yq.x) * (P)0.5, (Yp.y - Yq.y) * (P)0.5};
+      const cx<P> Dh = {(Yp.x - Yq.x) * (P)0.5, (Yp.y + Yq.y) * (P)0.5};  // (Yp - conj Yq)/2
+      const cx<double> d = dtw[2 * p + 1];                                  // conj(c_p) = d
+      const cx<P> O = cmul(cx<P>{(P)d.x, (P)d.y}, Dh);
+      buf[pk<PS>(p) * S + s] = cx<P>{E.x - O.y, E.y + O.x};                  // E + i O
+      buf[pk<PS>(N2 - 1 - p) * S + s] = cx<P>{E.x + O.y, O.x - E.y};         // conj E + i conj O
+    }
+  }
+  __syncthreads();
+  wfft<P, N2, 1, CPW, S, PS, true, true>(buf + wv * CPW, stw, lane);
+  __syncthreads();
+  double acc = 0.0;
+  double *o = out + (size_t)h * N * m;
+  const double *dv = dotv ? dotv + (size_t)h * N * m : nullptr;
+  for (int idx = tid; idx < N2 * TS; idx += NT) {
+    const int j = idx / TS, s = idx % TS, gs = s0 + s;
+    if (gs >= m) continue;
+    const cx<P> z = buf[pk<PS>(j) * S + s];
+    const cx<double> w = twt[j];  // times 2 conj(w) = 2 e^{2 pi i j/n}
+    const double zx = (double)z.x, zy = (double)z.y;
+    const double r0 = 2.0 * (zx * w.x + zy * w.y), r1 = 2.0 * (zy * w.x - zx * w.y);
+    const size_t g = (size_t)(2 * j) * m + gs;
+    o[g] = r0;
+    o[g + m] = r1;
+    if (dv) acc += r0 * dv[g] + r1 * dv[g + m];
+  }
+  if (dotv) {
+    const double r = block_sum<NT>(acc, red);
+    if (tid == 0) partials[t] = r;
+  }
+}
+
 // ---- sine transform of contiguous rows, in place (2D x1 passes) ------------------
 // nlines rows of M complex each; every wave owns B rows at a time.
 template <typename P, int N1>
@@ -831,6 +977,196 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
     }
     wave_sync();
   }
+}
+
+// ---- 2D spatial step on a transposed copy (large N1) --------------------------------
+// The x2 transforms read columns of [q][h][x2][x1]; at N1 >= 128 a tile of columns of both
+// block rows takes so much LDS that one or two workgroups fit per CU.  Instead the
+// forward x1 pass writes its result transposed, T = [q][h][j1][x2] with row stride N1
+// (x2 contiguous, rows aligned), the x2 pass works on contiguous rows of T, one
+// (frequency, j1) unit per wave with its two block rows transformed one after the other
+// (one LDS line per wave), and the inverse x1 pass reads T and writes [q][h][x2][x1] rows
+// again.  The x1 passes use tiles of R consecutive rows (one per wave), so the transposed
+// accesses move R consecutive elements at a time.
+template <typename P, int N1, int R> struct TrCfg {
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 3;
+  static constexpr int PN = padded<PS>(N1);
+  static constexpr int NT = 64 * R;
+  static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);
+  static constexpr int BUF = R * PN * CXB;
+  // tables in LDS only where that does not cost a resident workgroup
+  static constexpr bool TAB_LDS = blocks_per_cu(BUF + TAB) == blocks_per_cu(BUF);
+};
+constexpr int kPairWaves = 4;  // waves per workgroup of the x2 row pass (two per unit)
+template <typename P, int N1> struct PairCfg {
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 3;
+  static constexpr int PN = padded<PS>(N1);
+  static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);
+  static constexpr int BUF = kPairWaves * PN * CXB;
+  // the pass holds about 160 VGPRs per lane in FP64 at N1 = 512 (three waves per SIMD,
+  // three workgroups per CU), so the tables go to LDS whenever three workgroups still fit
+  static constexpr bool TAB_LDS = 3 * (BUF + TAB) <= kCuLds;
+};
+
+template <typename P, int N1, bool TWL>
+__device__ __forceinline__ void stage_tables(const cx<P> *__restrict__ twg, const P *__restrict__ sing,
+                                             cx<P> *stw, P *ssin, int nt) {
+  if constexpr (TWL) {
+    for (int i = threadIdx.x; i < N1; i += nt) {
+      stw[i] = twg[i];
+      ssin[i] = sing[i];
+    }
+  }
+}
+
+// forward x1 sine transform of R rows of a slab (q, h) of A, written to the slab of T
+template <typename P, int N1, int R>
+__global__ __launch_bounds__(64 * R) void k_rows_fwd_t(const cx<P> *__restrict__ A,
+                                                       cx<P> *__restrict__ T,
+                                                       const cx<P> *__restrict__ twg,
+                                                       const P *__restrict__ sing) {
+  using C = TrCfg<P, N1, R>;
+  constexpr int M = N1 - 1, PS = C::PS, PN = C::PN, NT = C::NT, NRB = (M + R - 1) / R;
+  __shared__ cx<P> lds[R * PN];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int slab = t / NRB, rb = t % NRB, x2 = rb * R + wv;
+  const cx<P> *src = A + (size_t)slab * M * M;
+  cx<P> *buf = lds + wv * PN;
+  stage_tables<P, N1, C::TAB_LDS>(twg, sing, stw, ssin, NT);
+  if constexpr (C::TAB_LDS) __syncthreads();
+  const cx<P> *tw = C::TAB_LDS ? stw : twg;
+  const P *sn = C::TAB_LDS ? ssin : sing;
+  dst_pre_global<P, N1, 1, 1, PS>(buf, sn, lane, [&](int, int x) {
+    return x2 < M ? src[(size_t)x2 * M + x] : cx<P>{(P)0, (P)0};
+  });
+  wave_sync();
+  wdst_core<P, N1, 1, 1, PS>(buf, tw, lane);
+  __syncthreads();
+  cx<P> *dst = T + (size_t)slab * M * N1;
+  for (int idx = tid; idx < M * R; idx += NT) {
+    const int r = idx % R, j1 = idx / R, xx = rb * R + r;
+    if (xx < M) dst[(size_t)j1 * N1 + xx] = lds[r * PN + pk<PS>(j1 + 1)];
+  }
+}
+
+// inverse x1 sine transform: R consecutive x2 of every j1 row of a slab of T, written as R
+// rows of the slab of A
+template <typename P, int N1, int R>
+__global__ __launch_bounds__(64 * R) void k_rows_inv_t(const cx<P> *__restrict__ T,
+                                                       cx<P> *__restrict__ A,
+                                                       const cx<P> *__restrict__ twg,
+                                                       const P *__restrict__ sing) {
+  using C = TrCfg<P, N1, R>;
+  constexpr int M = N1 - 1, PS = C::PS, PN = C::PN, NT = C::NT, NRB = (M + R - 1) / R;
+  constexpr int LIT = (M * R + NT - 1) / NT;
+  __shared__ cx<P> lds[R * PN];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int slab = t / NRB, rb = t % NRB, x2 = rb * R + wv;
+  const cx<P> *src = T + (size_t)slab * M * N1;
+  cx<P> v[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {  // every load issued before any is consumed
+    const int idx = tid + it * NT, r = idx % R, j1 = idx / R, xx = rb * R + r;
+    v[it] = cx<P>{(P)0, (P)0};
+    if (idx < M * R && xx < M) v[it] = src[(size_t)j1 * N1 + xx];
+  }
+  stage_tables<P, N1, C::TAB_LDS>(twg, sing, stw, ssin, NT);
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (idx < M * R) lds[(idx % R) * PN + pk<PS>(idx / R + 1)] = v[it];
+  }
+  __syncthreads();
+  cx<P> *buf = lds + wv * PN;
+  wdst<P, N1, 1, 1, PS>(buf, C::TAB_LDS ? stw : twg, C::TAB_LDS ? ssin : sing, lane);
+  if (x2 < M) {
+    cx<P> *dst = A + (size_t)slab * M * M + (size_t)x2 * M;
+    for (int x = lane; x < M; x += 64) dst[x] = buf[pk<PS>(x + 1)];
+  }
+}
+
+// x2 sine transform, step 2 and inverse x2 sine transform on T, in place.  A (q, j1) unit
+// is two waves, one per block row, each transforming its line with the result in
+// registers; the per-mode operation couples the two through their LDS lines (each wave
+// publishes its modes in natural order, reads its partner's, keeps its own block row of
+// the 2x2 result), then each wave runs the inverse transform on its own line.
+template <typename P, int N1>
+__global__ __launch_bounds__(64 * kPairWaves) void k_pair_cols_t(
+    cx<P> *__restrict__ T, int nunits, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
+    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm) {
+  using C = PairCfg<P, N1>;
+  using L = DstLanes<P, N1, 1>;
+  constexpr int M = N1 - 1, PS = C::PS, PN = C::PN, CH = L::CH, UPB = kPairWaves / 2;
+  static_assert(L::G == 64, "one line per wave: every lane holds modes of it");
+  __shared__ cx<P> lds[kPairWaves * PN];
+  __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
+  __shared__ P ssin[C::TAB_LDS ? N1 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = wv & 1;
+  stage_tables<P, N1, C::TAB_LDS>(twg, sing, stw, ssin, 64 * kPairWaves);
+  if constexpr (C::TAB_LDS) __syncthreads();
+  const cx<P> *tw = C::TAB_LDS ? stw : twg;
+  const P *sn = C::TAB_LDS ? ssin : sing;
+  // units in XCD order (workgroups, then the workgroup's units)
+  // a unit past the end (the last workgroup when nunits is odd) repeats the last unit and
+  // stores nothing
+  const int u0 = xcd_tile(blockIdx.x, gridDim.x) * UPB + (wv >> 1);
+  const bool live = u0 < nunits;
+  const int unit = live ? u0 : nunits - 1;
+  const int q = unit / M, j1 = unit % M;
+  cx<P> *row = T + ((size_t)(2 * q + h) * M + j1) * N1;
+  cx<P> *buf = lds + wv * PN;
+  const cx<P> *pbuf = lds + (wv ^ 1) * PN;  // the other block row's line
+  cx<P> o[CH], e[CH];
+  int b, k0;
+  bool valid;
+  dst_pre_global<P, N1, 1, 1, PS>(buf, sn, lane, [&](int, int x) { return row[x]; });
+  wave_sync();
+  wdst_regs<P, N1, 1, 1, PS>(buf, tw, lane, o, e, b, k0, valid);
+  wave_sync();
+  // modes j2 = 2k (odd outputs) and 2k - 1 (even outputs, k >= 1): k0 > 0 except on lane 0
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int k = k0 + c;
+    buf[pk<PS>(2 * k + 1)] = o[c];
+    if (k > 0) buf[pk<PS>(2 * k)] = e[c];
+  }
+  __syncthreads();
+  const cx<P> l = lam[q];
+  const P muj1 = mu[j1];
+  const P sh = h ? (P)1 : (P)0;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int k = k0 + c;
+    {
+      const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
+      cx<P> a = h ? po : o[c], bb = h ? o[c] : po;
+      mode_op<P>(a, bb, l, muj1 + mu[2 * k], kind, tau, alpha, cnorm);
+      o[c] = cx<P>{a.x + sh * (bb.x - a.x), a.y + sh * (bb.y - a.y)};
+    }
+    const cx<P> pe = pbuf[pk<PS>(k > 0 ? 2 * k : 2 * k + 1)];
+    cx<P> a = h ? pe : e[c], bb = h ? e[c] : pe;
+    mode_op<P>(a, bb, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0], kind, tau, alpha, cnorm);
+    e[c] = cx<P>{a.x + sh * (bb.x - a.x), a.y + sh * (bb.y - a.y)};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int k = k0 + c;
+    buf[pk<PS>(2 * k + 1)] = o[c];
+    if (k > 0) buf[pk<PS>(2 * k)] = e[c];
+  }
+  wave_sync();
+  wdst<P, N1, 1, 1, PS>(buf, tw, sn, lane);
+  if (live)
+    for (int x = lane; x < M; x += 64) row[x] = buf[pk<PS>(x + 1)];
 }
 
 // ---- 2D: x2-DST, step 2, x2-iDST on tiles of TX x1-columns (both block rows) -------
@@ -1268,11 +1604,48 @@ hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *npa
   }
 }
 
+// time-pass choice: ts_time > 0 the packed one-sequence kernels with that tile width, < 0
+// the per-block-row kernels (n >= 64) with tile width -ts_time; 0 the default
+template <typename P, int N> constexpr int default_ts_h() {
+  return blocks_per_cu(TimeCfgH<P, N, 16>::TILE) >= 2 ? 16 : 8;
+}
+template <typename P, int N> int time_choice(const wc_plan &p) {
+  if (p.ts_time) return (p.ts_time < 0 && N < 64) ? default_ts<P, N>() : p.ts_time;
+  if constexpr (N >= 64) return -default_ts_h<P, N>();
+  return default_ts<P, N>();
+}
+
+template <typename P, int N, int TS>
+hipError_t tfft_fwd_h(const wc_plan &p, const double *v) {
+  const int ntile = (p.m + TS - 1) / TS;
+  ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
+  hipLaunchKernelGGL((k_tfft_fwd_h<P, N, TS>), dim3(2 * ntile), dim3(TimeCfgH<P, N, TS>::NT), 0,
+                     p.stream, v, (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw,
+                     (const cx<double> *)p.d_twt64, p.m, ntile);
+  return hipGetLastError();
+}
+
+template <typename P, int N, int TS>
+hipError_t tfft_inv_h(const wc_plan &p, double *w, const double *dotv, int *nparts) {
+  const int ntile = (p.m + TS - 1) / TS;
+  *nparts = 2 * ntile;
+  ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
+  hipLaunchKernelGGL((k_tfft_inv_h<P, N, TS>), dim3(2 * ntile), dim3(TimeCfgH<P, N, TS>::NT), 0,
+                     p.stream, (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw,
+                     (const cx<double> *)p.d_twt64, p.m, ntile, dotv, p.d_partials);
+  return hipGetLastError();
+}
+
 template <typename P, int N>
 hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen,
                         cx<P> *out = nullptr) {
+  if constexpr (N >= 64) {
+    const int tc = time_choice<P, N>(p);
+    if (tc < 0 && !gen && !out)
+      return tc == -8 ? tfft_fwd_h<P, N, 8>(p, v) : tfft_fwd_h<P, N, 16>(p, v);
+  }
   if (!out) out = (cx<P> *)p.d_specA;
-  switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
+  switch (p.ts_time > 0 ? p.ts_time : default_ts<P, N>()) {
     case 4: return tfft_fwd_ts<P, N, 4>(p, v, gen, out);
     case 8: return tfft_fwd_ts<P, N, 8>(p, v, gen, out);
     default: return tfft_fwd_ts<P, N, 16>(p, v, gen, out);
@@ -1281,7 +1654,13 @@ hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen,
 
 template <typename P, int N>
 hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts) {
-  switch (p.ts_time ? p.ts_time : default_ts<P, N>()) {
+  if constexpr (N >= 64) {
+    const int tc = time_choice<P, N>(p);
+    if (tc < 0)
+      return tc == -8 ? tfft_inv_h<P, N, 8>(p, w, dotv, nparts)
+                      : tfft_inv_h<P, N, 16>(p, w, dotv, nparts);
+  }
+  switch (p.ts_time > 0 ? p.ts_time : default_ts<P, N>()) {
     case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
     case 8: return tfft_inv_ts<P, N, 8>(p, w, dotv, nparts);
     default: return tfft_inv_ts<P, N, 16>(p, w, dotv, nparts);
@@ -1326,6 +1705,41 @@ hipError_t dst_rows_on(const wc_plan &p, cx<P> *buf, int nlines, int prof_id, do
   return hipGetLastError();
 }
 
+// rows per tile of the transposing x1 passes: 8 (128 B per transposed FP64 access) while
+// two workgroups stay resident per CU, else 4
+template <typename P, int N1> constexpr int default_tr() {
+  return blocks_per_cu(TrCfg<P, N1, 8>::BUF) >= 2 ? 8 : 4;
+}
+
+// the 2D spatial step through the transposed copy T (N1 >= 128)
+template <typename P, int N1, int R>
+hipError_t space_tr(const wc_plan &p, int kind, double c) {
+  constexpr int M = N1 - 1, NRB = (M + R - 1) / R;
+  cx<P> *A = (cx<P> *)p.d_specA;
+  cx<P> *T = (cx<P> *)p.d_specT;
+  const double bytes = 2.0 * p.nvec * sizeof(P);
+  hipError_t e;
+  {
+    ProfScope ps(p, K_DST_X1_FWD, bytes);
+    hipLaunchKernelGGL((k_rows_fwd_t<P, N1, R>), dim3(p.n * NRB), dim3(64 * R), 0, p.stream, A, T,
+                       Tabs<P>::tws(p), Tabs<P>::sin(p));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    const int nunits = (p.n / 2) * M, upb = kPairWaves / 2;
+    ProfScope ps(p, K_PAIR_MODE, bytes);
+    hipLaunchKernelGGL((k_pair_cols_t<P, N1>), dim3((nunits + upb - 1) / upb),
+                       dim3(64 * kPairWaves), 0, p.stream, T, nunits, Tabs<P>::tws(p),
+                       Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
+                       (P)p.alpha, (P)c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ProfScope ps(p, K_DST_X1_INV, bytes);
+  hipLaunchKernelGGL((k_rows_inv_t<P, N1, R>), dim3(p.n * NRB), dim3(64 * R), 0, p.stream, T, A,
+                     Tabs<P>::tws(p), Tabs<P>::sin(p));
+  return hipGetLastError();
+}
+
 template <typename P, int N1>
 hipError_t run_space(const wc_plan &p) {
   using R = RowCfg<P, N1>;
@@ -1344,11 +1758,18 @@ hipError_t run_space(const wc_plan &p) {
                        Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha, (P)c);
     return hipGetLastError();
   }
+  // x2-pass choice: tx_cols > 0 tiles of that many columns, < 0 the transposed rows with
+  // -tx_cols rows per x1 tile (needs the plan's transposed copy, N1 >= 128)
+  const int txc = p.tx_cols ? p.tx_cols : (p.d_specT ? -default_tr<P, N1>() : default_tx<P, N1>());
+  if constexpr (N1 >= 128) {
+    if (txc < 0 && p.d_specT)
+      return txc == -4 ? space_tr<P, N1, 4>(p, kind, c) : space_tr<P, N1, 8>(p, kind, c);
+  }
   const int nlines = p.n * M;  // n/2 frequencies x 2 block rows x M rows
   dim3 gr(row_grid((nlines + R::B - 1) / R::B, R::WPB));
   hipError_t e = dst_rows_on<P, N1>(p, W, nlines, K_DST_X1_FWD, bytes);
   if (e != hipSuccess) return e;
-  switch (p.tx_cols ? p.tx_cols : default_tx<P, N1>()) {
+  switch (txc > 0 ? txc : default_tx<P, N1>()) {
     case 4: e = cols_tx<P, N1, 4>(p, kind, c); break;
     case 16: e = cols_tx<P, N1, 16>(p, kind, c); break;
     default: e = cols_tx<P, N1, 8>(p, kind, c); break;
@@ -1933,10 +2354,11 @@ hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
 }
 
 int pc_partials_needed(int n, int m, int precision) {
-  // bound on the inverse time FFT's grid: every tile has at least 4 spatial columns
+  // bound on the inverse time FFT's grid: tiles of at least 4 spatial columns (packed
+  // form) or of at least 8 columns of each block row
   (void)n;
   (void)precision;
-  return (m + 3) / 4;
+  return (m + 3) / 4 + 2;
 }
 
 }  // namespace wc

@@ -1,17 +1,28 @@
-// Serving: a queue of whole solves run by worker threads, one HIP stream each, with
-// admission by the plans' HBM footprint and a cache of idle plans for reuse.
+// Serving: requests admitted by the HBM footprint of their plans, run with iteration-level
+// continuous batching where the batched preconditioner kernels apply and as whole solves on
+// worker threads otherwise, with a cache of idle plans for reuse.
 //
-// Scheduling.  Requests start in submission order.  The head of the queue starts when a
-// worker is free and either an idle plan of the same shape exists (same sizes, method,
-// precision and restart: it is retargeted to the new problem without allocating) or the
-// plans held by running requests plus the head's footprint fit the budget (idle plans
-// are freed, oldest first, to make room).  A running request keeps its plan until it is
-// done; the plan then goes to the idle cache, still counted against the budget.
+// Continuous batching.  GMRES(k)-P_S requests in the standard form on 2D grids with a = 1
+// (n and M + 1 in {64, ..., 512}) go to one batcher thread that runs a lockstep engine:
+// every round advances each active solve by one Krylov step, applying the preconditioner of
+// all of them in one launch per pass, and synchronises once.  Queued requests join at the
+// next round boundary as soon as memory allows (up to 32 active), finished ones leave at
+// the round in which they converge, so a request never waits for a batch to drain.
 //
-// Concurrency happens on the device: every worker enqueues its solve's kernels on its
-// own stream, so small and large solves overlap and a new request does not wait for the
-// ones in flight.  The solve itself is the library's ordinary wc_solve, so results do not
-// depend on what else runs (every reduction has a fixed order).
+// Whole solves.  Other requests (1D, variable a, MINRES, the low-rank form, other sizes)
+// run wc_solve on worker threads, one HIP stream each, so they overlap on the device with
+// each other and with the batcher.
+//
+// Admission.  Each queue starts its requests in submission order.  The head of a queue
+// starts when an idle plan of the same shape exists (same sizes, method, precision and
+// restart: it is retargeted to the new problem without allocating) or the plans held by
+// running requests plus the head's footprint fit the budget (idle plans are freed, oldest
+// first, to make room).  A running request keeps its plan until it is done; the plan then
+// goes to the idle cache, still counted against the budget.
+//
+// Results do not depend on what else runs: every reduction has a fixed order and each
+// batched kernel's work units read and write one instance only, so a request gives the same
+// bits alone and in any mix (on the same path).
 
 #include <hip/hip_runtime.h>
 
@@ -25,7 +36,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "wc.h"
+#include "wc_internal.h"
 
 namespace {
 
@@ -66,6 +77,7 @@ struct Req {
   double *y = nullptr, *p = nullptr, *u = nullptr;
   size_t bytes = 0;
   int state = QUEUED;
+  bool batched = false;  // served by the lockstep engine
   wc_info info{};
   Clock::time_point t_submit, t_start, t_end;
 };
@@ -83,7 +95,11 @@ struct wc_server {
   size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<uint64_t> queue;
+  std::deque<uint64_t> queue;   // whole solves (workers)
+  std::deque<uint64_t> bqueue;  // continuously batched solves (batcher)
+  std::thread batcher;
+  uint64_t n_batched = 0;       // requests that ran in the lockstep engine
+  int max_lanes = 0;            // largest number of solves active in one round
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next = 1;
   std::list<IdlePlan> idle;  // oldest first
@@ -104,40 +120,32 @@ struct wc_server {
   }
 
   // called with mu held
-  bool can_start() const {
-    if (queue.empty()) return false;
-    const Req &r = reqs.at(queue.front());
+  bool can_start(const std::deque<uint64_t> &q) const {
+    if (q.empty()) return false;
+    const Req &r = reqs.at(q.front());
     if (idle_match(r.key)) return true;
     return in_use - idle_bytes() + r.bytes <= budget;
   }
 
-  void worker();
-};
-
-void wc_server::worker() {
-  (void)hipSetDevice(device);
-  hipStream_t stream = nullptr;
-  if (hipStreamCreate(&stream) != hipSuccess) stream = nullptr;
-  std::unique_lock<std::mutex> lk(mu);
-  for (;;) {
-    cv.wait(lk, [&] { return stop || can_start(); });
-    if (stop) break;
-    const uint64_t id = queue.front();
-    queue.pop_front();
+  // called with mu held: pops the head of q and picks its plan (an idle one for the same
+  // problem, else one of the same shape to retarget, else none: memory is reserved and
+  // idle plans to free are returned in evict)
+  uint64_t take(std::deque<uint64_t> &q, wc_plan **plan, bool *exact,
+                std::vector<wc_plan *> &evict) {
+    const uint64_t id = q.front();
+    q.pop_front();
     Req &r = reqs.at(id);
-    // an idle plan for the same problem, else one of the same shape to retarget
-    wc_plan *plan = nullptr;
-    bool exact = false;
-    for (int pass = 0; pass < 2 && !plan; ++pass)
+    *plan = nullptr;
+    *exact = false;
+    for (int pass = 0; pass < 2 && !*plan; ++pass)
       for (auto it = idle.begin(); it != idle.end(); ++it)
         if (pass == 0 ? it->key == r.key : it->key.same_shape(r.key)) {
-          plan = it->plan;
-          exact = pass == 0;
+          *plan = it->plan;
+          *exact = pass == 0;
           idle.erase(it);
           break;
         }
-    std::vector<wc_plan *> evict;
-    if (!plan) {
+    if (!*plan) {
       while (in_use + r.bytes > budget && !idle.empty()) {
         evict.push_back(idle.front().plan);
         in_use -= idle.front().bytes;
@@ -147,31 +155,135 @@ void wc_server::worker() {
     }
     r.state = RUNNING;
     r.t_start = Clock::now();
-    lk.unlock();
-    for (wc_plan *e : evict) (void)wc_plan_destroy(e);
-    wc_status st = WC_OK;
+    return id;
+  }
+
+  // without mu: a plan for request r on stream (created, or retargeted unless exact)
+  static wc_status prepare(Req &r, wc_plan **plan, bool exact, hipStream_t stream) {
     wc_problem pr = r.key.prob;
     pr.a_face_host = r.key.aface.empty() ? nullptr : r.key.aface.data();
-    if (!stream) {
-      st = WC_E_HIP;
-    } else if (!plan) {
-      st = wc_plan_create(&pr, &r.key.opts, stream, &plan);
-    } else {
-      st = wc_plan_set_stream(plan, stream);
-      if (st == WC_OK && !exact) st = wc_plan_retarget(plan, &pr, &r.key.opts);
-    }
-    wc_info info{};
-    if (st == WC_OK) st = wc_solve(plan, r.f, r.g, r.y0, r.y, r.p, r.u, &info);
-    info.status = st;
-    lk.lock();
+    if (!stream) return WC_E_HIP;
+    if (!*plan) return wc_plan_create(&pr, &r.key.opts, stream, plan);
+    wc_status st = wc_plan_set_stream(*plan, stream);
+    if (st == WC_OK && !exact) st = wc_plan_retarget(*plan, &pr, &r.key.opts);
+    return st;
+  }
+
+  // with mu held: request id finished with info; its plan (or reservation) is released
+  void finish(uint64_t id, wc_plan *plan, const wc_info &info) {
+    Req &r = reqs.at(id);
     r.info = info;
     r.t_end = Clock::now();
     r.state = DONE;
     if (plan) idle.push_back({r.key, plan, r.bytes});
     else in_use -= r.bytes;
+  }
+
+  void worker();
+  void batch_loop();
+};
+
+void wc_server::worker() {
+  (void)hipSetDevice(device);
+  hipStream_t stream = nullptr;
+  if (hipStreamCreate(&stream) != hipSuccess) stream = nullptr;
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv.wait(lk, [&] { return stop || can_start(queue); });
+    if (stop) break;
+    wc_plan *plan = nullptr;
+    bool exact = false;
+    std::vector<wc_plan *> evict;
+    const uint64_t id = take(queue, &plan, &exact, evict);
+    Req &r = reqs.at(id);
+    lk.unlock();
+    for (wc_plan *e : evict) (void)wc_plan_destroy(e);
+    wc_status st = prepare(r, &plan, exact, stream);
+    wc_info info{};
+    if (st == WC_OK) st = wc_solve(plan, r.f, r.g, r.y0, r.y, r.p, r.u, &info);
+    info.status = st;
+    lk.lock();
+    finish(id, plan, info);
     cv.notify_all();
   }
   lk.unlock();
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+void wc_server::batch_loop() {
+  (void)hipSetDevice(device);
+  hipStream_t stream = nullptr;
+  if (hipStreamCreate(&stream) != hipSuccess) stream = nullptr;
+  LockstepEngine *eng = stream ? wc::lockstep_create(stream) : nullptr;
+  std::unordered_map<uint64_t, wc_plan *> lane_plans;  // the engine's solves and their plans
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    const int active = eng ? wc::lockstep_active(eng) : 0;
+    cv.wait(lk, [&] { return stop || active > 0 || can_start(bqueue); });
+    if (stop && active == 0) break;
+    // admission at this round boundary
+    struct Adm {
+      uint64_t id;
+      Req *req;  // element pointers of the map stay valid; the request is RUNNING
+      wc_plan *plan;
+      bool exact;
+    };
+    std::vector<Adm> adm;
+    std::vector<wc_plan *> evict;
+    while (!stop && active + (int)adm.size() < wc::kBatchMax && can_start(bqueue)) {
+      Adm a{};
+      a.id = take(bqueue, &a.plan, &a.exact, evict);
+      a.req = &reqs.at(a.id);
+      adm.push_back(a);
+    }
+    lk.unlock();
+    for (wc_plan *e : evict) (void)wc_plan_destroy(e);
+    std::vector<wc::LockstepDone> done;
+    for (Adm &a : adm) {
+      Req &r = *a.req;
+      wc_status st = eng ? prepare(r, &a.plan, a.exact, stream) : WC_E_HIP;
+      if (st == WC_OK &&
+          wc::lockstep_add(eng, a.plan, r.f, r.g, r.y0, r.y, r.p, r.u, a.id) != hipSuccess)
+        st = WC_E_HIP;
+      if (st != WC_OK) {
+        wc_info info{};
+        info.status = st;
+        done.push_back({a.id, a.plan, info});
+      } else {
+        lane_plans[a.id] = a.plan;
+      }
+    }
+    const int lanes = eng ? wc::lockstep_active(eng) : 0;
+    hipError_t e = hipSuccess;
+    if (lanes > 0) e = wc::lockstep_round(eng, done);
+    if (e != hipSuccess) {  // the engine's state is unusable: fail its solves, start afresh
+      (void)hipGetLastError();
+      wc::lockstep_destroy(eng);
+      for (auto &kv : lane_plans) (void)wc_plan_destroy(kv.second);
+      lk.lock();
+      for (const wc::LockstepDone &d : done)
+        if (!lane_plans.count(d.tag)) finish(d.tag, d.plan, d.info);
+      for (auto &kv : lane_plans) {
+        wc_info info{};
+        info.status = WC_E_HIP;
+        finish(kv.first, nullptr, info);
+      }
+      lane_plans.clear();
+      eng = wc::lockstep_create(stream);
+      cv.notify_all();
+      continue;
+    }
+    lk.lock();
+    if (lanes > max_lanes) max_lanes = lanes;
+    for (const wc::LockstepDone &d : done) {
+      finish(d.tag, d.plan, d.info);
+      lane_plans.erase(d.tag);
+      ++n_batched;
+    }
+    if (!done.empty()) cv.notify_all();
+  }
+  lk.unlock();
+  wc::lockstep_destroy(eng);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -197,6 +309,7 @@ wc_status wc_server_create(size_t hbm_budget, int max_concurrency, wc_server **o
   }
   s->budget = hbm_budget;
   for (int i = 0; i < max_concurrency; ++i) s->workers.emplace_back([s] { s->worker(); });
+  s->batcher = std::thread([s] { s->batch_loop(); });
   *out = s;
   return WC_OK;
 }
@@ -205,17 +318,20 @@ wc_status wc_server_destroy(wc_server *s) {
   if (!s) return WC_E_ARG;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    for (uint64_t id : s->queue) {
-      Req &r = s->reqs.at(id);
-      r.state = DONE;
-      r.info.status = WC_E_CANCELLED;
-      r.t_end = Clock::now();
+    for (auto *q : {&s->queue, &s->bqueue}) {
+      for (uint64_t id : *q) {
+        Req &r = s->reqs.at(id);
+        r.state = DONE;
+        r.info.status = WC_E_CANCELLED;
+        r.t_end = Clock::now();
+      }
+      q->clear();
     }
-    s->queue.clear();
     s->stop = true;
   }
   s->cv.notify_all();
   for (auto &t : s->workers) t.join();
+  if (s->batcher.joinable()) s->batcher.join();  // finishes the solves it is running
   for (auto &i : s->idle) (void)wc_plan_destroy(i.plan);
   delete s;
   return WC_OK;
@@ -243,8 +359,10 @@ wc_status wc_server_submit(wc_server *s, const wc_problem *prob, const wc_opts *
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return WC_E_CANCELLED;
     const uint64_t id = s->next++;
+    const bool batched = wc::lockstep_eligible(prob, opts);
+    r.batched = batched;
     s->reqs.emplace(id, std::move(r));
-    s->queue.push_back(id);
+    (batched ? s->bqueue : s->queue).push_back(id);
     *ticket = id;
   }
   s->cv.notify_all();
@@ -283,11 +401,12 @@ wc_status wc_server_cancel(wc_server *s, uint64_t ticket) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end() || it->second.state != QUEUED) return WC_E_ARG;
-  for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
-    if (*q == ticket) {
-      s->queue.erase(q);
-      break;
-    }
+  for (auto *qq : {&s->queue, &s->bqueue})
+    for (auto q = qq->begin(); q != qq->end(); ++q)
+      if (*q == ticket) {
+        qq->erase(q);
+        break;
+      }
   it->second.state = DONE;
   it->second.info.status = WC_E_CANCELLED;
   it->second.t_end = Clock::now();
@@ -299,6 +418,14 @@ size_t wc_server_bytes_in_use(wc_server *s) {
   if (!s) return 0;
   std::lock_guard<std::mutex> lk(s->mu);
   return s->in_use;
+}
+
+wc_status wc_server_stats(wc_server *s, uint64_t *batched, int *max_active) {
+  if (!s) return WC_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batched) *batched = s->n_batched;
+  if (max_active) *max_active = s->max_lanes;
+  return WC_OK;
 }
 
 }  // extern "C"

@@ -74,6 +74,8 @@ _lib.wc_plan_retarget.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(
 _lib.wc_plan_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_int)]
 _lib.wc_plan_set_stream.argtypes = [_vp, _vp]
+_lib.wc_plan_set_tiles.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+_lib.wc_plan_set_tiles.restype = ctypes.c_int
 _lib.wc_rhs.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.wc_matvec.argtypes = [_vp, _vp, _vp]
 _lib.wc_pc_apply.argtypes = [_vp, _vp, _vp]
@@ -94,6 +96,8 @@ _lib.wc_server_wait.argtypes = [_vp, _u64, ctypes.POINTER(_Info), ctypes.POINTER
 _lib.wc_server_cancel.argtypes = [_vp, _u64]
 _lib.wc_server_bytes_in_use.argtypes = [_vp]
 _lib.wc_server_bytes_in_use.restype = ctypes.c_size_t
+_lib.wc_server_stats.argtypes = [_vp, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_int)]
+_lib.wc_server_stats.restype = ctypes.c_int
 _vpp = ctypes.POINTER(_vp)
 _lib.wc_batch_create.argtypes = [_vpp, ctypes.c_int, ctypes.POINTER(_vp)]
 _lib.wc_batch_destroy.argtypes = [_vp]
@@ -109,10 +113,12 @@ for _f in ("wc_plan_retarget", "wc_plan_autotune", "wc_profile", "wc_plan_create
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_plan_create",
-            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
+            "wc_plan_destroy", "wc_plan_retarget", "wc_plan_autotune", "wc_plan_set_tiles",
+            "wc_plan_set_stream", "wc_rhs", "wc_matvec", "wc_pc_apply",
             "wc_recover", "wc_krylov", "wc_solve", "wc_version", "wc_profile", "wc_profile_read",
             "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
-            "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use", "wc_batch_create",
+            "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use", "wc_server_stats",
+            "wc_batch_create",
             "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve"]
 
 
@@ -237,6 +243,10 @@ class Plan:
         self._check(_lib.wc_plan_autotune(self._h, int(reps), ctypes.byref(ts), ctypes.byref(tx)),
                     "wc_plan_autotune")
         return ts.value, tx.value
+
+    def set_tiles(self, ts: int, tx: int):
+        """The preconditioner's kernel choices (values of wc_plan_set_tiles)."""
+        self._check(_lib.wc_plan_set_tiles(self._h, int(ts), int(tx)), "wc_plan_set_tiles")
 
     def set_stream(self, stream):
         self._stream = stream
@@ -398,3 +408,15 @@ class Server:
 
     def bytes_in_use(self) -> int:
         return int(_lib.wc_server_bytes_in_use(self._h))
+
+    def stats(self):
+        """(requests served by continuous batching, largest number active in one round)"""
+        b, mx = _u64(0), ctypes.c_int(0)
+        self._check_code(_lib.wc_server_stats(self._h, ctypes.byref(b), ctypes.byref(mx)),
+                         "wc_server_stats")
+        return int(b.value), int(mx.value)
+
+    @staticmethod
+    def _check_code(code, where):
+        if code != WC_OK:
+            raise WcError(code, where)

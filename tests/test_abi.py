@@ -137,3 +137,38 @@ def test_batch_null_arguments(wc):
     assert lib.wc_batch_destroy(None) == wc.WC_E_ARG
     assert lib.wc_batch_pc_apply(None, None, None) == wc.WC_E_ARG
     assert lib.wc_batch_solve(None, None, None, None, None, None, None) == wc.WC_E_ARG
+
+
+def _create_plan_host(wc, **kw):
+    """wc_plan_create through ctypes with no stream (only host-side refusals are checked)."""
+    args = dict(dims=1, M=7, n=7, T=1.0, theta=0.5, gamma=1e-4, zeta=np.pi, s2_remedy=0.0,
+                a_face=None)
+    args.update(kw)
+    pr, _keep = wc._problem(args["dims"], args["M"], args["n"], args["T"], args["theta"],
+                            args["gamma"], args["zeta"], args["s2_remedy"], args["a_face"])
+    op = wc._opts("gmres_ps", "fp64", 1e-8, 500, 30, False, 30, 1e-10)
+    h = ctypes.c_void_p(1)
+    code = wc._lib.wc_plan_create(ctypes.byref(pr), ctypes.byref(op), None, ctypes.byref(h))
+    return code, h.value
+
+
+@pytest.mark.parametrize("n,zeta", [(7, np.pi), (5, np.pi), (8, 0.0), (6, 0.0)])
+def test_singular_s2_without_remedy_refused(wc, n, zeta):
+    # remark on the singular S_n^(2) (Section 1): theta = 1/2 makes S^(2) singular when
+    # e^{i(zeta - 2 pi l)/n} = -1 for some l: n odd at zeta = pi, n even at zeta = 0.
+    # With s2_remedy = 0 plan creation fails before any device call and sets *out = NULL.
+    code, h = _create_plan_host(wc, n=n, zeta=zeta)
+    assert code == wc.WC_E_SINGULAR_S2 and h is None
+    # the same problem with a remedy value is a valid problem
+    assert wc.footprint_bytes(1, 7, n, theta=0.5, zeta=zeta, s2_remedy=1.0) > 0
+
+
+def test_footprint_partials_cover_restart_32(wc):
+    # GMRES step j < restart writes (j + 2) rows of 1024 reduction partials; with restart 32
+    # that is 34 rows.  On a tiny problem the partials dominate the non-table bytes, so the
+    # footprint is checked term by term (spectral array, partials, 1 MiB of tables,
+    # (restart+1) + 1 + 1 + 2 system vectors, 512 Krylov scalars).
+    M, n, k = 3, 4, 32
+    nvec = 2 * n * M
+    expect = n * M * 16 + (34 * 1024 + 64) * 8 + (1 << 20) + (k + 1 + 1 + 1 + 2) * nvec * 8 + 512 * 8
+    assert wc.footprint_bytes(1, M, n, restart=k) == expect

@@ -70,8 +70,10 @@ def test_autotune_keeps_parity(env, dims, M, n, method):
     plan = wc.Plan(dims, M, n, theta=0.5, gamma=1e-4, method=method)
     ts, tx = plan.autotune(reps=2)
     print("autotune", dims, M, n, method, "->", ts, tx, flush=True)
-    assert ts in (4, 8, 16)
-    assert tx in ((4, 8, 16) if dims == 2 else (0,))
+    # time passes: packed tiles (> 0) or per-block-row tiles (< 0, n >= 64); x2 pass
+    # (2D): column tiles (> 0) or the transposed rows (< 0, M + 1 >= 128)
+    assert ts in (4, 8, 16, -8, -16)
+    assert tx in ((4, 8, 16, -4, -8) if dims == 2 else (0,))
     v = datagen.random_vector(9, 2 * n * pr.m)
     kind = {"gmres_ps": "ps", "minres_abs_ps": "abs_ps", "minres_pms": "pms"}[method]
     ref = FastPreconditioner(pr, kind).apply(v)

@@ -1,7 +1,9 @@
 """GPU tests of the solve server (include/wc.h, serving): a request's result is the same
-whether it runs alone or in a concurrent mix (bitwise: every reduction has a fixed
-order), admission keeps the held plans within the memory budget, and queued requests
-can be cancelled."""
+whether it is served alone or in a concurrent mix (bitwise: every reduction has a fixed
+order and the batched kernels' work units read one instance each), it matches the
+standalone solve of the same problem, requests of the batchable kind really are
+continuously batched (several active in one round, joining while others run), admission
+keeps the held plans within the memory budget, and queued requests can be cancelled."""
 import numpy as np
 import pytest
 
@@ -59,42 +61,96 @@ def test_alone_equals_in_mix_lowrank(env):
     _alone_equals_in_mix(env, MIX_LR, True)
 
 
+def _serve(wc, torch, reqs, lowrank, idx=None):
+    """Submits reqs (all, or those listed in idx) to a fresh server at once; returns
+    [(y, p, info)] in order and the server's batching statistics."""
+    idx = range(len(reqs)) if idx is None else idx
+    srv = wc.Server(hbm_budget=0, max_concurrency=4)
+    outs, tickets = [], []
+    for k in idx:
+        kw, f, g, y0, m = reqs[k]
+        y = torch.full((kw["n"] * m,), float("nan"), dtype=torch.float64, device="cuda")
+        outs.append((y, torch.full_like(y, float("nan"))))
+    torch.cuda.synchronize()
+    for k, (y, p) in zip(idx, outs):
+        kw, f, g, y0, m = reqs[k]
+        tickets.append(srv.submit(f, g, y0, y, p, **dict(kw, lowrank=lowrank)))
+    res = []
+    for t, (y, p) in zip(tickets, outs):
+        info, q_ms, tot_ms = srv.wait(t)
+        assert tot_ms >= q_ms >= 0.0
+        res.append((y.cpu().numpy(), p.cpu().numpy(), info))
+    stats = srv.stats()
+    srv.close()
+    return res, stats
+
+
 def _alone_equals_in_mix(env, mix, lowrank):
     torch, wc = env
     reqs = [make_request(torch, k, s) for k, s in enumerate(mix)]
-    for r in reqs:
-        r[0]["lowrank"] = lowrank
-    alone = []
-    for kw, f, g, y0, m in reqs:
+    mixed, stats = _serve(wc, torch, reqs, lowrank)
+    print("batched requests, most active in one round:", stats, flush=True)
+    for k, (kw, f, g, y0, m) in enumerate(reqs):
+        alone, _ = _serve(wc, torch, reqs, lowrank, [k])
+        ya, pa, ia = alone[0]
+        ym, pm, im = mixed[k]
+        print("request", k, mix[k], "lowrank", lowrank, "iters", im.iters, flush=True)
+        assert im.status == wc.WC_OK and ia.status == wc.WC_OK and im.relres <= 1e-8
+        assert im.iters == ia.iters
+        assert np.array_equal(ym, ya), k
+        assert np.array_equal(pm, pa), k
+        # the same problem through a standalone plan (single-instance kernels)
         y = torch.empty(kw["n"] * m, dtype=torch.float64, device="cuda")
         p = torch.empty_like(y)
-        plan = wc.Plan(**kw)
+        plan = wc.Plan(**dict(kw, lowrank=lowrank))
         info = plan.solve(f, g, y0, y, p)
-        assert info.relres <= 1e-8
-        alone.append((y.cpu().numpy(), p.cpu().numpy(), info.iters))
         plan.close()
-    torch.cuda.synchronize()
-    srv = wc.Server(hbm_budget=0, max_concurrency=4)
+        assert info.iters == im.iters
+        sc = max(np.abs(ym).max(), np.abs(pm).max())
+        assert np.abs(y.cpu().numpy() - ym).max() <= 1e-10 * sc
+        assert np.abs(p.cpu().numpy() - pm).max() <= 1e-10 * sc
+
+
+# requests the server batches continuously (2D, a = 1, standard GMRES(k)-P_S, n and M+1 in
+# {64, ..., 512}), mixed sizes and precisions
+MIX_CB = [
+    (2, 63, 64, 0.5, 1e-4, "gmres_ps", "fp64", "const"),
+    (2, 127, 128, 1.0, 1e-3, "gmres_ps", "mixed", "const"),
+    (2, 63, 128, 0.5, 1e-6, "gmres_ps", "fp64", "const"),
+    (2, 255, 64, 0.5, 1e-2, "gmres_ps", "fp64", "const"),
+    (2, 127, 64, 1.0, 1e-5, "gmres_ps", "mixed", "const"),
+    (2, 63, 64, 1.0, 1e-3, "gmres_ps", "fp64", "const"),
+]
+
+
+def test_continuous_batching(env):
+    """Requests arrive while others iterate: they join the running lockstep rounds, several
+    solves are active in one round, every batchable request is served by the batcher, and
+    each result is bitwise the one served alone."""
+    torch, wc = env
+    reqs = [make_request(torch, 20 + k, s) for k, s in enumerate(MIX_CB)]
+    alone = [_serve(wc, torch, reqs, False, [k])[0][0] for k in range(len(reqs))]
+    srv = wc.Server(hbm_budget=0, max_concurrency=2)
     outs, tickets = [], []
-    for kw, f, g, y0, m in reqs:
+    import time
+    for k, (kw, f, g, y0, m) in enumerate(reqs):
         y = torch.full((kw["n"] * m,), float("nan"), dtype=torch.float64, device="cuda")
         p = torch.full_like(y, float("nan"))
         outs.append((y, p))
-    torch.cuda.synchronize()
-    for (kw, f, g, y0, m), (y, p) in zip(reqs, outs):
+        torch.cuda.synchronize()
         tickets.append(srv.submit(f, g, y0, y, p, **kw))
+        time.sleep(0.002)  # staggered arrivals: later requests join running rounds
     for k, t in enumerate(tickets):
         info, q_ms, tot_ms = srv.wait(t)
-        print("request", k, mix[k], "lowrank", lowrank, "iters", info.iters, "queue ms",
-              round(q_ms, 2),
-              "total ms", round(tot_ms, 2), flush=True)
-        assert info.status == wc.WC_OK
-        assert info.iters == alone[k][2]
-        assert tot_ms >= q_ms >= 0.0
-    torch.cuda.synchronize()
-    for k, (y, p) in enumerate(outs):
+        y, p = outs[k]
+        assert info.status == wc.WC_OK and info.relres <= 1e-8
+        assert info.iters == alone[k][2].iters
         assert np.array_equal(y.cpu().numpy(), alone[k][0]), k
         assert np.array_equal(p.cpu().numpy(), alone[k][1]), k
+    batched, most = srv.stats()
+    print("batched", batched, "most active in one round", most, flush=True)
+    assert batched == len(reqs)
+    assert most >= 2
     srv.close()
 
 
