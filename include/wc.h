@@ -303,6 +303,28 @@ wc_status wc_batch_solve(wc_batch *batch, const double *const *f, const double *
                          const double *const *y0, double *const *y, double *const *p,
                          wc_info *infos);
 
+/* ---- preconditioner apply that allocates nothing ---------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): w = P^{-1} v as wc_pc_apply computes
+ * it, with no plan.  The tables and the spectral workspace live in a static device array
+ * of wc_pc_apply_noalloc_limit() bytes (256 MiB) that each device the library runs on
+ * holds until the process ends; the tables are rebuilt on the device at every call.
+ * No hipMalloc, hipFree or other allocating routine is called.
+ *
+ * prob: as for wc_plan_create (a_face_host must be NULL: a == 1); method: wc_method;
+ * precision: wc_precision; v, w: device pointers, 2*n*m doubles each (may alias);
+ * stream: hipStream_t or NULL.  Asynchronous, stream-ordered.
+ * Errors: WC_E_ARG for invalid arguments or a problem whose tables plus spectral array
+ * (n*m complex of the precision) exceed the limit; WC_E_UNSUPPORTED where wc_pc_apply's
+ * GPU path does not apply (variable a, zeta != pi, n or M+1 not a power of two in
+ * [4, 1024]); WC_E_SINGULAR_S2 as for wc_plan_create.
+ * Every call on a device shares that device's array and keeps the last call's contents:
+ * calls that overlap on one GPU (different streams, or host threads without ordering)
+ * race and must be serialised by the caller. */
+wc_status wc_pc_apply_noalloc(const wc_problem *prob, int method, int precision,
+                              const double *v, double *w, void *stream);
+size_t wc_pc_apply_noalloc_limit(void);
+
 /* Library build identification (static string). */
 const char *wc_version(void);
 

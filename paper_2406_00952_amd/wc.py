@@ -103,6 +103,9 @@ _lib.wc_batch_create.argtypes = [_vpp, ctypes.c_int, ctypes.POINTER(_vp)]
 _lib.wc_batch_destroy.argtypes = [_vp]
 _lib.wc_batch_pc_apply.argtypes = [_vp, _vpp, _vpp]
 _lib.wc_batch_solve.argtypes = [_vp, _vpp, _vpp, _vpp, _vpp, _vpp, ctypes.POINTER(_Info)]
+_lib.wc_pc_apply_noalloc.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.wc_pc_apply_noalloc.restype = ctypes.c_int
+_lib.wc_pc_apply_noalloc_limit.restype = ctypes.c_size_t
 for _f in ("wc_batch_create", "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve"):
     getattr(_lib, _f).restype = ctypes.c_int
 for _f in ("wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
@@ -119,7 +122,8 @@ EXPORTED = ["wc_status_str", "wc_opts_default", "wc_plan_footprint_bytes", "wc_p
             "wc_server_create", "wc_server_destroy", "wc_server_submit", "wc_server_poll",
             "wc_server_wait", "wc_server_cancel", "wc_server_bytes_in_use", "wc_server_stats",
             "wc_batch_create",
-            "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve"]
+            "wc_batch_destroy", "wc_batch_pc_apply", "wc_batch_solve", "wc_pc_apply_noalloc",
+            "wc_pc_apply_noalloc_limit"]
 
 
 def status_str(code: int) -> str:
@@ -292,6 +296,23 @@ class Plan:
             raise WcError(code, "wc_solve")
         return Info(inf.status, inf.iters, inf.restarts, inf.relres, inf.relres_est, inf.ms,
                     inf.mg_cycles_max, inf.reorth)
+
+
+def pc_apply_noalloc(v, w, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi,
+                     s2_remedy=1.0, method="gmres_ps", precision="fp64", stream=None) -> None:
+    """w = P^{-1} v without a plan and without device allocation (wc_pc_apply_noalloc)."""
+    import torch
+    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    code = _lib.wc_pc_apply_noalloc(ctypes.byref(pr), METHODS[method], PRECISIONS[precision],
+                                    _ptr(v), _ptr(w), _vp(stream.cuda_stream))
+    if code != WC_OK:
+        raise WcError(code, "wc_pc_apply_noalloc")
+
+
+def pc_apply_noalloc_limit() -> int:
+    return int(_lib.wc_pc_apply_noalloc_limit())
 
 
 def _info(inf) -> Info:
