@@ -3,8 +3,13 @@
 Notation follows the paper: M interior points per dimension, m = M**dims
 spatial unknowns, h = 1/(M+1), n time steps, tau = T/n, alpha = tau/sqrt(gamma)
 (eqn:matrix_A), theta in [1/2, 1] (theta = 1 backward Euler, 1/2 Crank-Nicolson).
-Finite differences: mass matrix M_m = I, stiffness K_m = -L_m where L_m is the
-(variable-coefficient) five-point Laplacian with homogeneous Dirichlet data.
+Finite differences (disc = "fd"): mass matrix M_m = I, stiffness K_m = -L_m where
+L_m is the (variable-coefficient) five-point Laplacian with homogeneous Dirichlet
+data.  Finite elements (disc = "fem", a = 1): M_m and K_m are the consistent mass
+and stiffness matrices of continuous piecewise-linear (1D) / bilinear (2D)
+elements on the same grid; the system is the same with M_m in place of I
+(eqn:matrix_A_before) and K_m -> M_m^{-1/2} K_m M_m^{-1/2} after the change of
+variables (eqn:main_system).
 
 Vectors are time major: a block vector [v^(1); ...; v^(n)] is an (n, m) array,
 spatial index x1 fastest.
@@ -30,10 +35,15 @@ class Problem:
     zeta: float = np.pi
     a_face: Optional[np.ndarray] = None  # None => a == 1
     s2_remedy: float = 1.0
+    disc: str = "fd"                       # "fd" or "fem"
 
     def __post_init__(self):
         if self.dims not in (1, 2):
             raise ValueError("dims must be 1 or 2")
+        if self.disc not in ("fd", "fem"):
+            raise ValueError("disc must be fd or fem")
+        if self.disc == "fem" and self.a_face is not None:
+            raise ValueError("the finite element form is built for a = 1")
         if not (0.5 <= self.theta <= 1.0):
             raise ValueError("theta must lie in [1/2, 1] (Section 1)")
         if self.gamma <= 0:
@@ -103,6 +113,52 @@ def stiffness(dims: int, M: int, a_face: Optional[np.ndarray] = None) -> sp.csr_
     return sp.csr_matrix((vals, (rows, cols)), shape=(M * M, M * M))
 
 
+def fem_matrices(dims: int, M: int):
+    """(M_m, K_m) of continuous piecewise-linear (1D) or bilinear (2D) Lagrange elements
+    on the uniform grid with interior nodes x_i = i h, h = 1/(M+1), a = 1, homogeneous
+    Dirichlet data.  Element integrals of the hat functions:
+    1D mass h/6 [1 4 1], stiffness 1/h [-1 2 -1]; the bilinear basis is the tensor
+    product, so M = M1 kron M1 and K = K1 kron M1 + M1 kron K1 (x2 index outer)."""
+    h = 1.0 / (M + 1)
+    e = np.ones(M)
+    M1 = sp.diags([4.0 * e, e[:-1], e[:-1]], [0, -1, 1]) * (h / 6.0)
+    K1 = sp.diags([2.0 * e, -e[:-1], -e[:-1]], [0, -1, 1]) / h
+    if dims == 1:
+        return M1.tocsr(), K1.tocsr()
+    return sp.kron(M1, M1).tocsr(), (sp.kron(K1, M1) + sp.kron(M1, K1)).tocsr()
+
+
+def mass_stiffness(prob: "Problem"):
+    """(M_m, K_m) of the problem's discretisation (Section 1)."""
+    if prob.disc == "fem":
+        return fem_matrices(prob.dims, prob.M)
+    return sp.identity(prob.m, format="csr"), stiffness(prob.dims, prob.M, prob.a_face)
+
+
+def mass_power(prob: "Problem", X: np.ndarray, power: float) -> np.ndarray:
+    """Rows of X times M_m^power (power = +-1/2 in the change of variables of
+    eqn:main_system).  M_m = I for finite differences; for the bilinear elements with
+    a = 1 the orthonormal sine basis U (dense) diagonalises the 1D mass matrix,
+    U M1 U = diag(h/3 (2 + cos(j pi h))), so M_m^power = (U kron U) diag(...)^power (U kron U)."""
+    if prob.disc == "fd":
+        return X
+    M, h = prob.M, prob.h
+    i = np.arange(1, M + 1)
+    U = np.sqrt(2.0 / (M + 1)) * np.sin(np.outer(i, i) * np.pi / (M + 1))
+    m1 = (h / 3.0) * (2.0 + np.cos(i * np.pi * h))
+    shp = X.shape
+    if prob.dims == 1:
+        Y = X.reshape(-1, M) @ U.T
+        Y = Y * m1 ** power
+        return (Y @ U.T).reshape(shp)
+    Y = X.reshape(-1, M, M) @ U.T          # along x1
+    Y = np.matmul(U, Y)                    # along x2
+    Y = Y * (np.outer(m1, m1) ** power)[None, :, :]
+    Y = Y @ U.T
+    Y = np.matmul(U, Y)
+    return Y.reshape(shp)
+
+
 def B1(n: int) -> sp.csr_matrix:
     """B_n^(1): unit lower bidiagonal, 1 on the diagonal, -1 below (Section 1)."""
     return sp.diags([np.ones(n), -np.ones(n - 1)], [0, -1], format="csr")
@@ -129,13 +185,12 @@ def Bn_closed_form(n: int, theta: float) -> np.ndarray:
 def assemble_Atilde(prob: Problem) -> sp.csr_matrix:
     """The 2nm x 2nm matrix of eqn:matrix_A_before with M_m = I, K_m = K."""
     n, m, tau, th, gam = prob.n, prob.m, prob.tau, prob.theta, prob.gamma
-    K = stiffness(prob.dims, prob.M, prob.a_face)
-    I = sp.identity(m, format="csr")
+    Mm, K = mass_stiffness(prob)
     b1, b2 = B1(n), B2(n, th)
-    A11 = tau * sp.kron(b2, I)
-    A12 = sp.kron(b1.T, I) + tau * sp.kron(b2.T, K)
-    A21 = sp.kron(b1, I) + tau * sp.kron(b2, K)
-    A22 = -(tau / gam) * sp.kron(b2.T, I)
+    A11 = tau * sp.kron(b2, Mm)
+    A12 = sp.kron(b1.T, Mm) + tau * sp.kron(b2.T, K)
+    A21 = sp.kron(b1, Mm) + tau * sp.kron(b2, K)
+    A22 = -(tau / gam) * sp.kron(b2.T, Mm)
     return sp.bmat([[A11, A12], [A21, A22]], format="csr")
 
 
@@ -152,36 +207,42 @@ class AllAtOnce:
 
     def __init__(self, prob: Problem):
         self.prob = prob
-        self.K = stiffness(prob.dims, prob.M, prob.a_face)
+        self.Mm, self.K = mass_stiffness(prob)
         n = prob.n
         self.b1 = B1(n).toarray()
         self.b2 = B2(n, prob.theta).toarray()
 
     def Atilde(self, y: np.ndarray, p: np.ndarray):
         """Return the two block rows of A_tilde [y; p] for (n, m) arrays y, p."""
-        pr, K = self.prob, self.K
+        pr, K, Mm = self.prob, self.K, self.Mm
         tau, gam = pr.tau, pr.gamma
         b1, b2 = self.b1, self.b2
         KY = (K @ y.T).T  # I_n kron K applied to y
         KP = (K @ p.T).T
-        r1 = tau * (b2 @ y) + b1.T @ p + tau * (b2.T @ KP)
-        r2 = b1 @ y + tau * (b2 @ KY) - (tau / gam) * (b2.T @ p)
+        MY = (Mm @ y.T).T
+        MP = (Mm @ p.T).T
+        r1 = tau * (b2 @ MY) + b1.T @ MP + tau * (b2.T @ KP)
+        r2 = b1 @ MY + tau * (b2 @ KY) - (tau / gam) * (b2.T @ MP)
         return r1, r2
 
     def to_yp(self, x1: np.ndarray, x2: np.ndarray):
-        """[x1; x2] = [sqrt(gamma) y_tilde; p_tilde] -> (y, p)."""
+        """[x1; x2] = [sqrt(gamma) y_tilde; p_tilde] -> (y, p), with
+        y_tilde = (B^(2) kron M^{1/2}) y and p_tilde = ((B^(2))^T kron M^{1/2}) p."""
         g = np.sqrt(self.prob.gamma)
-        y = sla.solve_triangular(self.b2, x1 / g, lower=True)
-        p = sla.solve_triangular(self.b2.T, x2, lower=False)
+        y = sla.solve_triangular(self.b2, mass_power(self.prob, x1, -0.5) / g, lower=True)
+        p = sla.solve_triangular(self.b2.T, mass_power(self.prob, x2, -0.5), lower=False)
         return y, p
 
     def A(self, x: np.ndarray) -> np.ndarray:
-        """Symmetric operator of eqn:matrix_A applied to a flat 2nm vector."""
+        """Symmetric operator of eqn:matrix_A applied to a flat 2nm vector: the change of
+        variables of eqn:main_system around A_tilde (rows scaled by M^{-1/2})."""
         n, m = self.prob.n, self.prob.m
         x1 = x[: n * m].reshape(n, m)
         x2 = x[n * m:].reshape(n, m)
         y, p = self.to_yp(x1, x2)
         r1, r2 = self.Atilde(y, p)
+        r1 = mass_power(self.prob, r1, -0.5)
+        r2 = mass_power(self.prob, r2, -0.5)
         return np.concatenate([r1.ravel(), np.sqrt(self.prob.gamma) * r2.ravel()])
 
     def Ahat(self, x: np.ndarray) -> np.ndarray:
@@ -198,23 +259,26 @@ def rhs_tilde(prob: Problem, f: np.ndarray, g: np.ndarray, y0: np.ndarray):
     each (n, m).
     """
     n, tau, th = prob.n, prob.tau, prob.theta
-    K = stiffness(prob.dims, prob.M, prob.a_face)
+    Mm, K = mass_stiffness(prob)
     f = np.asarray(f, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
     y0 = np.asarray(y0, dtype=np.float64)
     ft = np.empty((n, prob.m))
     gt = np.empty((n, prob.m))
     for k in range(1, n + 1):  # block row k uses levels k-1 and k
-        ft[k - 1] = th * tau * f[k] + (1 - th) * tau * f[k - 1]
-        gt[k - 1] = tau * (th * g[k - 1] + (1 - th) * g[k])
-    ft[0] += y0 - (1 - th) * tau * (K @ y0)
-    gt[0] -= tau * (1 - th) * y0
+        ft[k - 1] = Mm @ (th * tau * f[k] + (1 - th) * tau * f[k - 1])
+        gt[k - 1] = tau * (Mm @ (th * g[k - 1] + (1 - th) * g[k]))
+    ft[0] += Mm @ y0 - (1 - th) * tau * (K @ y0)
+    gt[0] -= tau * (1 - th) * (Mm @ y0)
     return gt, ft
 
 
 def transformed_rhs(prob: Problem, gt: np.ndarray, ft: np.ndarray, symmetric: bool) -> np.ndarray:
-    """[g; sqrt(gamma) f] (eqn:main_system) or [sqrt(gamma) f; g] (eqn:main_system_nonsym)."""
+    """[g; sqrt(gamma) f] (eqn:main_system) or [sqrt(gamma) f; g] (eqn:main_system_nonsym),
+    f = (I kron M^{-1/2}) f_tilde, g = (I kron M^{-1/2}) g_tilde."""
     sg = np.sqrt(prob.gamma)
+    ft = mass_power(prob, ft, -0.5)
+    gt = mass_power(prob, gt, -0.5)
     if symmetric:
         return np.concatenate([gt.ravel(), sg * ft.ravel()])
     return np.concatenate([sg * ft.ravel(), gt.ravel()])

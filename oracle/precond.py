@@ -23,7 +23,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import circulant, spatial
-from .discretization import Problem, stiffness, AllAtOnce
+from .discretization import Problem, stiffness, AllAtOnce, mass_stiffness
 
 
 # ----------------------------------------------------------------------------
@@ -37,10 +37,22 @@ def _herm_sqrt(H: np.ndarray) -> np.ndarray:
     return (V * np.sqrt(w)) @ V.conj().T
 
 
+def dense_khat(prob: Problem) -> np.ndarray:
+    """The spatial operator of the transformed system, M_m^{-1/2} K_m M_m^{-1/2}
+    (eqn:matrix_A; -L_m for finite differences), with the inverse square root of the
+    mass matrix from a dense symmetric eigendecomposition."""
+    Mm, K = mass_stiffness(prob)
+    if prob.disc == "fd":
+        return K.toarray()
+    w, V = np.linalg.eigh(Mm.toarray())
+    Mis = (V / np.sqrt(w)) @ V.T
+    return Mis @ K.toarray() @ Mis
+
+
 def dense_calS(prob: Problem) -> np.ndarray:
     """S = S_n kron I_m + tau I_n kron (-L_m) (eqn:matrix_S)."""
     S = circulant.Sn(prob.n, prob.theta, prob.zeta, prob.s2_remedy)
-    K = stiffness(prob.dims, prob.M, prob.a_face).toarray()
+    K = dense_khat(prob)
     return np.kron(S, np.eye(prob.m)) + prob.tau * np.kron(np.eye(prob.n), K)
 
 
@@ -61,7 +73,7 @@ def dense_absPS(prob: Problem) -> np.ndarray:
 def dense_PMS(prob: Problem) -> np.ndarray:
     """P_MS: sqrt(S_n^* S_n + alpha^2) kron I + tau I kron (-L) (and S S^* below)."""
     S = circulant.Sn(prob.n, prob.theta, prob.zeta, prob.s2_remedy)
-    K = stiffness(prob.dims, prob.M, prob.a_face).toarray()
+    K = dense_khat(prob)
     a2 = prob.alpha ** 2
     In, Im = np.eye(prob.n), np.eye(prob.m)
     top = np.kron(_herm_sqrt(S.conj().T @ S + a2 * In), Im) + prob.tau * np.kron(In, K)
@@ -143,7 +155,8 @@ class FastPreconditioner:
         W1 = np.empty_like(H1)
         W2 = np.empty_like(H2)
         if pr.a_face is None:                 # step 2, all frequencies at once
-            mu = spatial.eigenvalues(pr.dims, pr.M)
+            mu = (spatial.fem_eigenvalues(pr.dims, pr.M) if pr.disc == "fem"
+                  else spatial.eigenvalues(pr.dims, pr.M))
             T1 = spatial.sine_transform(pr.dims, pr.M, H1)
             T2 = spatial.sine_transform(pr.dims, pr.M, H2)
             Lam = self.lam[:, None] + pr.tau * mu[None, :]

@@ -12,7 +12,7 @@ import scipy.sparse.linalg as spla
 import scipy.linalg as sla
 
 from .discretization import (Problem, AllAtOnce, rhs_tilde, transformed_rhs,
-                             assemble_Atilde, B2)
+                             assemble_Atilde, B2, mass_power)
 from .precond import FastPreconditioner
 from . import krylov
 
@@ -23,12 +23,13 @@ METHODS = {"minres_abs_ps": ("abs_ps", True), "minres_pms": ("pms", True),
 def recover(prob: Problem, x: np.ndarray):
     """x = [sqrt(gamma) y_tilde; p_tilde] -> y (levels 1..n), p (levels 0..n-1), u = p/gamma.
 
-    y_tilde = B^(2) y and p_tilde = (B^(2))^T p (eqn:main_system).
+    y_tilde = (B^(2) kron M^{1/2}) y and p_tilde = ((B^(2))^T kron M^{1/2}) p
+    (eqn:main_system; M = I for finite differences).
     """
     n, m = prob.n, prob.m
     b2 = B2(n, prob.theta).toarray()
-    yt = x[: n * m].reshape(n, m) / np.sqrt(prob.gamma)
-    pt = x[n * m:].reshape(n, m)
+    yt = mass_power(prob, x[: n * m].reshape(n, m), -0.5) / np.sqrt(prob.gamma)
+    pt = mass_power(prob, x[n * m:].reshape(n, m), -0.5)
     y = sla.solve_triangular(b2, yt, lower=True)
     p = sla.solve_triangular(b2.T, pt, lower=False)
     return y, p, p / prob.gamma

@@ -44,3 +44,16 @@ def sine_transform(dims: int, M: int, X: np.ndarray) -> np.ndarray:
     Y = Y @ U.T                        # along x1
     Y = np.matmul(U, Y)                # along x2
     return Y.reshape(shp)
+
+
+def fem_eigenvalues(dims: int, M: int) -> np.ndarray:
+    """Eigenvalues of M_m^{-1/2} K_m M_m^{-1/2} for the linear / bilinear elements (a = 1):
+    the sine basis diagonalises the 1D mass and stiffness matrices with
+    m_j = h/3 (2 + cos(j pi h)) and k_j = 2/h (1 - cos(j pi h)), so in 1D mu_j = k_j/m_j and
+    in 2D (k1 m2 + m1 k2)/(m1 m2) = mu_j1 + mu_j2, in the (x2, x1) row-major order."""
+    h = 1.0 / (M + 1)
+    j = np.arange(1, M + 1)
+    mu = (2.0 / h) * (1.0 - np.cos(j * np.pi * h)) / ((h / 3.0) * (2.0 + np.cos(j * np.pi * h)))
+    if dims == 1:
+        return mu
+    return (mu[:, None] + mu[None, :]).ravel()
