@@ -66,6 +66,19 @@ typedef enum { WC_MINRES_ABS_PS = 0, WC_MINRES_PMS = 1, WC_GMRES_PS = 2 } wc_met
  * products, the all-at-once matvec and all tables are FP64 in both modes. */
 typedef enum { WC_FP64 = 0, WC_MIXED = 1 } wc_precision;
 
+/* Spatial discretisation (Section 1: mass M_m and stiffness K_m).  WC_FD: finite
+ * differences, M_m = I, K_m = -L_h (any a).  WC_FEM: continuous linear (1D) / bilinear (2D)
+ * elements on the same grid with a == 1, consistent mass M_m and stiffness K_m; the system
+ * is solved after the change of variables of eqn:main_system, whose spatial operator is
+ * M_m^{-1/2} K_m M_m^{-1/2}.  Both matrices are diagonal in the orthonormal sine basis U
+ * (U M1 U = diag(h/3 (2 + cos(j pi h))), U K1 U = diag(2/h (1 - cos(j pi h)))), so a
+ * WC_FEM plan works in sine coordinates: the system vectors of wc_rhs (its output),
+ * wc_matvec, wc_pc_apply, wc_krylov and wc_recover (its input) are (I (x) U) times the
+ * physical ones, the preconditioner apply is its time transform, the per-mode solves and
+ * the inverse time transform, and wc_rhs / wc_recover transform the data and the solution
+ * (f, g, y0 in and y, p, u out stay physical nodal values). */
+typedef enum { WC_FD = 0, WC_FEM = 1 } wc_disc;
+
 /* The discrete problem (Section 1 and the Section 4 protocol). */
 typedef struct {
   int dims;           /* 1 or 2 */
@@ -82,6 +95,8 @@ typedef struct {
                          [x2 node][x1 face] followed by faces normal to x2 as
                          an (M+1, M) array [x2 face][x1 node].  Copied at plan
                          creation. */
+  int disc;           /* wc_disc (0 = finite differences); WC_FEM needs a_face_host NULL
+                         and no low-rank form */
 } wc_problem;
 
 typedef struct {
@@ -133,7 +148,9 @@ size_t wc_plan_footprint_bytes(const wc_problem *prob, const wc_opts *opts);
 
 /* Validate, build the FP64 eigenvalue / twiddle tables (Section 1 remark on
  * S_n^(2) and Section 3.4), upload them, allocate workspaces.  *out is set to
- * NULL on failure.  stream: hipStream_t or NULL. */
+ * NULL on failure.  stream: hipStream_t or NULL.  WC_FEM problems need the
+ * preconditioner's coverage (zeta == pi, n and M+1 powers of two in [4, 1024]),
+ * else WC_E_UNSUPPORTED. */
 wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stream,
                          wc_plan **out);
 wc_status wc_plan_destroy(wc_plan *plan);
@@ -274,8 +291,8 @@ wc_status wc_server_stats(wc_server *srv, uint64_t *batched, int *max_active);
  * FP64 or mixed), whatever their grid M and steps n.  Many right-hand sides of one
  * problem are several plans of that problem.
  *
- * wc_batch_create: plans[0..count) (1 <= count <= 32), distinct plans, each 2D with
- * a == 1 (a_face NULL), n and M+1 in {64, 128, 256, 512}; otherwise WC_E_ARG (null,
+ * wc_batch_create: plans[0..count) (1 <= count <= 32), distinct plans, each 2D finite
+ * differences with a == 1 (a_face NULL), n and M+1 in {64, 128, 256, 512}; otherwise WC_E_ARG (null,
  * repeated plan, count out of range) or WC_E_UNSUPPORTED.  The batch borrows the plans
  * (their spectral workspaces and tables): they must outlive it and must not be
  * retargeted while it exists.  Every call runs on the plans' stream, which must be the
@@ -287,7 +304,8 @@ wc_status wc_server_stats(wc_server *srv, uint64_t *batched, int *max_active);
  *
  * wc_batch_solve: wc_solve for every instance (f, g, y0, y, p arrays of device
  * pointers, one per plan, sizes as for wc_solve) by GMRES(k)-P_S in the standard
- * form (each plan's method must be WC_GMRES_PS and lowrank 0, else WC_E_UNSUPPORTED),
+ * form (each plan's method must be WC_GMRES_PS, lowrank 0 and disc WC_FD, else
+ * WC_E_UNSUPPORTED),
  * advanced in lockstep: each round applies the preconditioner of every instance still
  * iterating in one batched apply and synchronises the host once.  Each instance keeps
  * its own tolerance, restart length, precision and iteration count, and stops on its
@@ -311,13 +329,13 @@ wc_status wc_batch_solve(wc_batch *batch, const double *const *f, const double *
  * holds until the process ends; the tables are rebuilt on the device at every call.
  * No hipMalloc, hipFree or other allocating routine is called.
  *
- * prob: as for wc_plan_create (a_face_host must be NULL: a == 1); method: wc_method;
+ * prob: as for wc_plan_create (a_face_host must be NULL: a == 1; disc WC_FD); method: wc_method;
  * precision: wc_precision; v, w: device pointers, 2*n*m doubles each (may alias);
  * stream: hipStream_t or NULL.  Asynchronous, stream-ordered.
  * Errors: WC_E_ARG for invalid arguments or a problem whose tables plus spectral array
  * (n*m complex of the precision) exceed the limit; WC_E_UNSUPPORTED where wc_pc_apply's
  * GPU path does not apply (variable a, zeta != pi, n or M+1 not a power of two in
- * [4, 1024]); WC_E_SINGULAR_S2 as for wc_plan_create.
+ * [4, 1024]) and for WC_FEM; WC_E_SINGULAR_S2 as for wc_plan_create.
  * Every call on a device shares that device's array and keeps the last call's contents:
  * calls that overlap on one GPU (different streams, or host threads without ordering)
  * race and must be serialised by the caller. */

@@ -60,6 +60,8 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   if (!(op->tol > 0) || op->maxit < 1) return WC_E_ARG;
   if (op->method == WC_GMRES_PS && (op->restart < 1 || op->restart > kMaxRestart)) return WC_E_ARG;
   if (op->method == WC_MINRES_ABS_PS && pr->a_face_host) return WC_E_ARG;  // |P_S| needs a == 1
+  if (pr->disc != WC_FD && pr->disc != WC_FEM) return WC_E_ARG;
+  if (pr->disc == WC_FEM && (pr->a_face_host || op->lowrank)) return WC_E_ARG;
   // low-rank GMRES: a == 1; the FP32 preconditioner (restarts on the FP64 true residual
   // correct what FP32 leaves, like iterative refinement) in 2D only
   if (op->lowrank && (op->method != WC_GMRES_PS || pr->a_face_host ||
@@ -107,11 +109,12 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
 }
 
 struct Sizes {
-  size_t nvec, spec_bytes, spec_t_bytes, partials, tables, vecs, mg, total;
+  size_t nvec, spec_bytes, spec_t_bytes, fem_bytes, partials, tables, vecs, mg, total;
 };
 
 bool uses_spec_t(const wc_problem *pr, const wc_opts *op) {
-  return pr->dims == 2 && !pr->a_face_host && !op->lowrank && pr->M + 1 >= 128 && pc_path_ok(pr);
+  return pr->dims == 2 && !pr->a_face_host && !op->lowrank && pr->disc == WC_FD &&
+         pr->M + 1 >= 128 && pc_path_ok(pr);
 }
 
 // Multigrid levels M_0 = M, M_{l+1} = (M_l - 1)/2, ..., 1; the first level whose remaining
@@ -147,6 +150,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.spec_bytes = (size_t)pr->n * m * es;  // n/2 frequencies x 2 halves x m complex
   // 2D a == 1 (standard form), N1 >= 128: the transposed copy of the x2 pass, rows of N1
   s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es : 0;
+  // finite elements: the FP64 complex sine transforms of the data and the solution
+  s.fem_bytes = pr->disc == WC_FEM ? (size_t)pr->n * m * 16 : 0;
   // the Gram-Schmidt reduction of GMRES step j writes (j + 2) rows of kRedBlocks partials
   // (j + 1 projections and the norm), j < kMaxRestart
   size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads),
@@ -167,8 +172,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
            (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
            (size_t)pr->n * 6 * sizeof(double);
   }
-  s.total = s.spec_bytes + s.spec_t_bytes + s.partials * sizeof(double) + s.tables + s.vecs +
-            S_COUNT * sizeof(double) + s.mg;
+  s.total = s.spec_bytes + s.spec_t_bytes + s.fem_bytes + s.partials * sizeof(double) +
+            s.tables + s.vecs + S_COUNT * sizeof(double) + s.mg;
   return s;
 }
 
@@ -254,6 +259,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_lam64); dfree(p->d_lam32); dfree(p->d_dtw);
   dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
+  dfree(p->d_mass64); dfree(p->d_femW);
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_specT); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
@@ -678,7 +684,7 @@ void set_scalars(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
 wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   // ---- FP64 tables ----
   const int n = p->n, N1 = p->N1, M = p->M;
-  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M);
+  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M), mass(M);
   for (int l = 0; l < n; ++l) {  // check every frequency of S^(2) for a zero eigenvalue
     const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
     const std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
@@ -706,8 +712,14 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
     sn[k] = std::sin(M_PI * k / N1);
   }
   for (int j = 0; j < M; ++j) {
-    const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
-    mu[j] = 4.0 * p->inv_h2 * sv * sv;
+    if (p->fem) {  // linear elements: U M1 U and U K1 U diagonal; mu = their ratio
+      const double c = std::cos((j + 1) * M_PI * p->h);
+      mass[j] = p->h / 3.0 * (2.0 + c);
+      mu[j] = (2.0 / p->h * (1.0 - c)) / mass[j];
+    } else {
+      const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
+      mu[j] = 4.0 * p->inv_h2 * sv * sv;
+    }
   }
   hipError_t e = hipSuccess;
   const std::vector<float> lam32 = to_f32(lam), twt32 = to_f32(twt), tws32 = to_f32(tws),
@@ -718,6 +730,7 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   WC_UP(d_sin64, sn) WC_UP(d_mu64, mu)
   WC_UP(d_lam32, lam32) WC_UP(d_twt32, twt32) WC_UP(d_tws32, tws32)
   WC_UP(d_sin32, sn32) WC_UP(d_mu32, mu32)
+  if (p->fem) WC_UP(d_mass64, mass)
 #undef WC_UP
   // low-rank GMRES: S_n - B_n = -omega g r^T with omega = e^{i zeta} = -1 (zeta = pi):
   // g = e_1 + (1 - theta) B_n e_1, r_k = q^{n-k} / (theta + omega (1 - theta) q^{n-1}),
@@ -904,6 +917,8 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   wc_status vs = validate(prob, opts);
   if (vs != WC_OK) return vs;
   if (singular_s2_unremedied(prob)) return WC_E_SINGULAR_S2;
+  // finite elements work in sine coordinates: the data transforms need the sine sizes
+  if (prob->disc == WC_FEM && !pc_path_ok(prob)) return WC_E_UNSUPPORTED;
   wc_plan *p = new (std::nothrow) wc_plan();
   if (!p) return WC_E_NOMEM;
   p->dims = prob->dims;
@@ -914,6 +929,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   p->h = 1.0 / (prob->M + 1);
   p->inv_h2 = 1.0 / (p->h * p->h);
   p->var_coeff = prob->a_face_host != nullptr;
+  p->fem = prob->disc == WC_FEM;
   p->stream = (hipStream_t)stream;
   p->nvec = 2 * (size_t)p->n * p->m;
   set_scalars(p, prob, opts);
@@ -941,6 +957,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   alloc(&p->d_specA, sz.spec_bytes);
   if (sz.spec_t_bytes && p->pc_ok) alloc(&p->d_specT, sz.spec_t_bytes);
   if (p->var_coeff) alloc(&p->d_specB, sz.spec_bytes);
+  if (sz.fem_bytes) alloc((void **)&p->d_femW, sz.fem_bytes);
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
   p->nkvec = krylov_vectors(prob, opts);
@@ -998,7 +1015,8 @@ wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *op
   if (vs != WC_OK) return vs;
   const wc_opts &o = p->opts;
   if (prob->dims != p->dims || prob->M != p->M || prob->n != p->n ||
-      (prob->a_face_host != nullptr) != p->var_coeff || opts->method != o.method ||
+      (prob->a_face_host != nullptr) != p->var_coeff || (prob->disc == WC_FEM) != p->fem ||
+      opts->method != o.method ||
       opts->precision != o.precision || opts->restart != o.restart ||
       opts->flexible != o.flexible || opts->lowrank != o.lowrank)
     return WC_E_ARG;
@@ -1025,7 +1043,8 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   // time passes: packed tiles of 4, 8, 16 columns, or per-block-row tiles of 8, 16 (< 0)
   const int tss[5] = {4, 8, 16, -8, -16}, txs[5] = {4, 8, 16, -4, -8};
   const int nts = p->n >= 64 ? 5 : 3;
-  const int ntx = (p->dims == 2 && !p->var_coeff) ? (p->d_specT ? 5 : 3) : 1;
+  // (finite elements: no sine passes in the preconditioner, only the time tiles matter)
+  const int ntx = (p->dims == 2 && !p->var_coeff && !p->fem) ? (p->d_specT ? 5 : 3) : 1;
   float best = -1.f;
   int bts = p->ts_time, btx = p->tx_cols;
   hipError_t e = hipSuccess;

@@ -109,6 +109,7 @@ struct wc_plan {
   double T = 1, theta = 1, gamma = 1, zeta = 0, s2_remedy = 1;
   double tau = 0, alpha = 0, h = 0, inv_h2 = 0;
   bool var_coeff = false;
+  bool fem = false;              // finite elements (a == 1): the system in sine coordinates
   bool pc_ok = false;            // the GPU preconditioner covers this problem
   int num_cu = 256;              // compute units of the plan's device
   int ts_time = 0;               // time passes: > 0 packed tile width, < 0 per-block-row
@@ -129,8 +130,11 @@ struct wc_plan {
   float *d_tws32 = nullptr;
   double *d_sin64 = nullptr;     // N1 reals: sin(pi i/N1)
   float *d_sin32 = nullptr;
-  double *d_mu64 = nullptr;      // M reals: eigenvalues of the 1D -L_h (a == 1)
-  float *d_mu32 = nullptr;
+  double *d_mu64 = nullptr;      // M reals: eigenvalues of the 1D -L_h (a == 1), or of
+  float *d_mu32 = nullptr;       //   M1^{-1/2} K1 M1^{-1/2} (finite elements)
+  double *d_mass64 = nullptr;    // finite elements: M eigenvalues of the 1D mass matrix
+  double *d_femW = nullptr;      // finite elements: n*m complex FP64, the sine transforms
+                                 // of the data and of the solution
   // workspaces
   void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
   void *d_specB = nullptr;       // n*m complex (P): multigrid fine solution (variable a)
@@ -257,6 +261,12 @@ hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *p
 hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
                       double *b);
 hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u);
+// finite elements: b holds the right-hand side combinations of the two block rows without
+// the y0 terms (physical); into sine coordinates with M^{-1/2} M = M^{1/2}, plus the y0 terms
+hipError_t launch_fem_rhs_finish(const wc_plan &p, const double *y0, double *b);
+// finite elements: y, p hold the recovered solution in sine coordinates without the
+// M^{-1/2} scaling; into physical nodal values (and u = p/gamma when u is not null)
+hipError_t launch_fem_recover_finish(const wc_plan &p, double *y, double *pp, double *u);
 
 int red_blocks(size_t n);
 // dst[i] = c0*a + c1*b + c2*c, coefficient k read from d_scal[slot + k] (slot < 0: host c*)

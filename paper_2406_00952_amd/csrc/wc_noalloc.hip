@@ -140,8 +140,9 @@ wc_status wc_pc_apply_noalloc(const wc_problem *prob, int method, int precision,
   if (!std::isfinite(prob->zeta) || !std::isfinite(prob->s2_remedy)) return WC_E_ARG;
   if (method < WC_MINRES_ABS_PS || method > WC_GMRES_PS) return WC_E_ARG;
   if (precision != WC_FP64 && precision != WC_MIXED) return WC_E_ARG;
-  // the same coverage as wc_pc_apply for a == 1
-  if (prob->a_face_host) return WC_E_UNSUPPORTED;
+  if (prob->disc != WC_FD && prob->disc != WC_FEM) return WC_E_ARG;
+  // the same coverage as wc_pc_apply for finite differences with a == 1
+  if (prob->a_face_host || prob->disc != WC_FD) return WC_E_UNSUPPORTED;
   if (std::fabs(prob->zeta - M_PI) > 1e-12 || !pow2_in(prob->n, 4, 1024) ||
       !pow2_in(prob->M + 1, 4, 1024))
     return WC_E_UNSUPPORTED;

@@ -38,9 +38,18 @@ struct Stencil {
   int ow, oe, os, on;          // neighbour offsets (0 when absent: coefficient is 0)
 };
 
+// K_m for finite differences (the 3/5-point stencil), or, with diag (finite elements in
+// sine coordinates), the diagonal operator M^{-1/2} K M^{-1/2}: diag[j1] (+ diag[j2]).
 __device__ __forceinline__ Stencil make_stencil(int s, int M, int dims, double inv_h2,
-                                                const double *__restrict__ aface) {
+                                                const double *__restrict__ aface,
+                                                const double *__restrict__ diag = nullptr) {
   Stencil st;
+  if (diag) {
+    st.cc = dims == 1 ? diag[s] : diag[s % M] + diag[s / M];
+    st.cw = st.ce = st.cs = st.cn = 0.0;
+    st.ow = st.oe = st.os = st.on = 0;
+    return st;
+  }
   if (dims == 1) {
     const double aw = aface ? aface[s] : 1.0;
     const double ae = aface ? aface[s + 1] : 1.0;
@@ -80,11 +89,17 @@ __device__ __forceinline__ double apply_stencil(const Stencil &st, const double 
   return st.cc * xk[s] - st.cw * xk[s + st.ow] - st.ce * xk[s + st.oe] - st.cs * xk[s + st.os] -
          st.cn * xk[s + st.on];
 }
+// the same, without the neighbour loads when the operator is diagonal
+__device__ __forceinline__ double apply_op(const Stencil &st, const double *__restrict__ xk,
+                                           int s, bool diag) {
+  return diag ? st.cc * xk[s] : apply_stencil(st, xk, s);
+}
 
 struct MvArgs {
   int n, M, dims, m, sym;
   double theta, tau, alpha, inv_h2;
   const double *aface;
+  const double *diag;  // finite elements: the 1D eigenvalues of M^{-1/2} K M^{-1/2}
   double ssign;  // with sub: y = ssign * (A x - sub)
 };
 
@@ -110,7 +125,8 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
     const size_t ooff = a.sym ? (dir == 0 ? nm : 0) : (dir == 0 ? 0 : nm);
     double *yo = y + ooff;
     const double *so = sub ? sub + ooff : nullptr;
-    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
+    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface, a.diag);
+    const bool dg = a.diag != nullptr;
     const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
     double zprev = 0.0, xprev = 0.0;
     // the loads of KB time levels are issued before the recurrence consumes them
@@ -126,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
         const int k = dir == 0 ? kk : a.n - 1 - kk;
         const double *xk = xs + (size_t)k * a.m;
         xc[u] = xk[s];
-        kx[u] = apply_stencil(st, xk, s);
+        kx[u] = apply_op(st, xk, s, dg);
         xok[u] = xo[(size_t)k * a.m + s];
         sk[u] = so ? so[(size_t)k * a.m + s] : 0.0;
       }
@@ -165,6 +181,7 @@ struct RhsArgs {
   int n, M, dims, m, sym;
   double theta, tau, sqrt_gamma, inv_h2;
   const double *aface;
+  int y0_terms;  // 0: leave out the y0 terms (finite elements add them in sine coordinates)
 };
 
 // f_tilde, g_tilde of Section 1 with M = I, then b = [g; sqrt(gamma) f] (sym) or
@@ -181,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const double *__restrict__ f,
   const double th = a.theta, omt = 1.0 - th;
   double ft = a.tau * (th * f[(size_t)(k + 1) * a.m + s] + omt * f[(size_t)k * a.m + s]);
   double gt = a.tau * (th * g[(size_t)k * a.m + s] + omt * g[(size_t)(k + 1) * a.m + s]);
-  if (k == 0) {
+  if (k == 0 && a.y0_terms) {
     const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
     ft += y0[s] - omt * a.tau * apply_stencil(st, y0, s);
     gt -= a.tau * omt * y0[s];
@@ -540,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_multiaxpy(double *__restrict__ w,
         v.x += c[j] * b.x;
         v.y += c[j] * b.y;
       }
-      w2[i] = v;
+      __builtin_nontemporal_store(v, w2 + i);
       acc += v.x * v.x + v.y * v.y;
     }
   } else {
@@ -673,7 +690,8 @@ int red_blocks(size_t n) {
 hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *partials,
                          int *nblocks_out, const double *sub, bool negate) {
   MvArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
-           p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface, negate ? -1.0 : 1.0};
+           p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface, p.fem ? p.d_mu64 : nullptr,
+           negate ? -1.0 : 1.0};
   dim3 grid((p.m + kThreads - 1) / kThreads, 2);
   ProfScope ps(p, K_MATVEC, (sub ? 24.0 : 16.0) * p.nvec);
   hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, sub, a, partials);
@@ -684,20 +702,26 @@ hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *p
 hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
                       double *b) {
   RhsArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
-            p.theta, p.tau, sqrt(p.gamma), p.inv_h2, p.d_aface};
+            p.theta, p.tau, sqrt(p.gamma), p.inv_h2, p.d_aface, p.fem ? 0 : 1};
   const size_t nm = (size_t)p.n * p.m;
   dim3 grid((unsigned)((nm + kThreads - 1) / kThreads));
-  ProfScope ps(p, K_RHS, 8.0 * (2.0 * (p.n + 1) * p.m + p.m + p.nvec));
-  hipLaunchKernelGGL(k_rhs, grid, dim3(kThreads), 0, p.stream, f, g, y0, b, a);
-  return hipGetLastError();
+  {
+    ProfScope ps(p, K_RHS, 8.0 * (2.0 * (p.n + 1) * p.m + p.m + p.nvec));
+    hipLaunchKernelGGL(k_rhs, grid, dim3(kThreads), 0, p.stream, f, g, y0, b, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !p.fem) return e;
+  }
+  return launch_fem_rhs_finish(p, y0, b);
 }
 
 hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *pp, double *u) {
   dim3 grid((p.m + kThreads - 1) / kThreads, 2);
   ProfScope ps(p, K_RECOVER, 8.0 * (p.nvec + p.nvec + (u ? p.nvec / 2 : 0)));
-  hipLaunchKernelGGL(k_recover, grid, dim3(kThreads), 0, p.stream, x, y, pp, u, p.n, p.m,
-                     p.theta, 1.0 / sqrt(p.gamma), 1.0 / p.gamma);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_recover, grid, dim3(kThreads), 0, p.stream, x, y, pp,
+                     p.fem ? nullptr : u, p.n, p.m, p.theta, 1.0 / sqrt(p.gamma), 1.0 / p.gamma);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !p.fem) return e;
+  return launch_fem_recover_finish(p, y, pp, u);
 }
 
 hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,

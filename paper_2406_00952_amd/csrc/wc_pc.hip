@@ -491,6 +491,29 @@ __device__ __forceinline__ void mode_op(cx<P> &a, cx<P> &b, cx<P> l, P musum, in
   }
 }
 
+// The same operation, only the block row h of the result (the x2 row pass: each wave keeps
+// its own block row).
+template <typename P>
+__device__ __forceinline__ cx<P> mode_op_row(cx<P> a, cx<P> b, int h, cx<P> l, P musum, int kind,
+                                             P tau, P alpha, P cnorm) {
+  if (kind == 0) {
+    const cx<P> Lm = {l.x + tau * musum, l.y};
+    const P c = cnorm / (Lm.x * Lm.x + Lm.y * Lm.y + alpha * alpha);
+    if (h == 0)  // (conj(L) a + alpha b) c
+      return cscale(cx<P>{Lm.x * a.x + Lm.y * a.y + alpha * b.x, Lm.x * a.y - Lm.y * a.x + alpha * b.y}, c);
+    const cx<P> lb = cmul(Lm, b);  // (L b - alpha a) c
+    return cscale(cx<P>{lb.x - alpha * a.x, lb.y - alpha * a.y}, c);
+  }
+  P s;
+  if (kind == 1) {
+    const P re = l.x + tau * musum;
+    s = cnorm / sqrt(re * re + l.y * l.y + alpha * alpha);
+  } else {
+    s = cnorm / (sqrt(l.x * l.x + l.y * l.y + alpha * alpha) + tau * musum);
+  }
+  return cscale(h ? b : a, s);
+}
+
 // ---- step 1a: time transform of both block rows ------------------------------
 // v: 2 x (n, m) FP64.  W: [q][half][s] complex, q = 0..n/2-1 <-> frequency l = q+1.
 template <typename P, int N, int TS, bool GEN, bool TWL>
@@ -1141,20 +1164,15 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_cols_t(
   __syncthreads();
   const cx<P> l = lam[q];
   const P muj1 = mu[j1];
-  const P sh = h ? (P)1 : (P)0;
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int k = k0 + c;
-    {
-      const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
-      cx<P> a = h ? po : o[c], bb = h ? o[c] : po;
-      mode_op<P>(a, bb, l, muj1 + mu[2 * k], kind, tau, alpha, cnorm);
-      o[c] = cx<P>{a.x + sh * (bb.x - a.x), a.y + sh * (bb.y - a.y)};
-    }
+    const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
+    o[c] = mode_op_row<P>(h ? po : o[c], h ? o[c] : po, h, l, muj1 + mu[2 * k], kind, tau,
+                          alpha, cnorm);
     const cx<P> pe = pbuf[pk<PS>(k > 0 ? 2 * k : 2 * k + 1)];
-    cx<P> a = h ? pe : e[c], bb = h ? e[c] : pe;
-    mode_op<P>(a, bb, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0], kind, tau, alpha, cnorm);
-    e[c] = cx<P>{a.x + sh * (bb.x - a.x), a.y + sh * (bb.y - a.y)};
+    e[c] = mode_op_row<P>(h ? pe : e[c], h ? e[c] : pe, h, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0],
+                          kind, tau, alpha, cnorm);
   }
   __syncthreads();
 #pragma unroll
@@ -1865,6 +1883,24 @@ hipError_t lr_update_t(const wc_plan &p, const GenIn &gen) {
   }
 }
 
+// step 2 in sine coordinates: the per-mode operation of every (frequency, mode)
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_mode_pointwise(cx<P> *__restrict__ W, int nq, int m,
+                                                            int M, int dims,
+                                                            const cx<P> *__restrict__ lam,
+                                                            const P *__restrict__ mu, int kind,
+                                                            P tau, P alpha, P cnorm) {
+  const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= (size_t)nq * m) return;
+  const int q = (int)(idx / (size_t)m), s = (int)(idx - (size_t)q * m);
+  const P musum = dims == 1 ? mu[s] : mu[s % M] + mu[s / M];
+  cx<P> *w0 = W + (size_t)(2 * q) * m + s;
+  cx<P> a = *w0, b = w0[m];
+  mode_op<P>(a, b, lam[q], musum, kind, tau, alpha, cnorm);
+  *w0 = a;
+  w0[m] = b;
+}
+
 template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
@@ -1896,7 +1932,16 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (p.var_coeff) {
+    if (p.fem) {  // sine coordinates: step 2 is pointwise
+      const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
+      const size_t cnt = (size_t)(p.n / 2) * p.m;
+      ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
+      hipLaunchKernelGGL((k_mode_pointwise<P>), dim3((unsigned)((cnt + kThreads - 1) / kThreads)),
+                         dim3(kThreads), 0, p.stream, (cx<P> *)p.d_specA, p.n / 2, p.m, p.M,
+                         p.dims, Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha,
+                         (P)(1.0 / p.n));
+      e = hipGetLastError();
+    } else if (p.var_coeff) {
       e = mg_space_apply(p);
     } else {
       switch (p.N1) {
@@ -2299,14 +2344,16 @@ hipError_t launch_pc_lowrank(const wc_plan &p, const double *r0, const double *h
 namespace {
 // x2 sine transform of the whole spectrum (the cycle's Yhat0 for the pointwise step)
 template <typename P, int N1>
-hipError_t cols_dst_t(const wc_plan &p, const cx<P> *in, cx<P> *out) {
+hipError_t cols_dst_t(const wc_plan &p, const cx<P> *in, cx<P> *out, int npairs = 0) {
   constexpr int TX = default_tx<P, N1>();
   if constexpr (!ColCfg<P, N1, TX>::FITS) {
     return hipErrorInvalidValue;
   } else {
+    // slab pairs (2q, 2q + 1) transformed: all n/2 of the spectrum by default
+    const int nq = npairs > 0 ? npairs : p.n / 2;
     const int ncx = (N1 - 2 + TX) / TX;
-    ProfScope ps(p, K_DST_X2_FWD, 2.0 * p.nvec * sizeof(P));
-    hipLaunchKernelGGL((k_cols_dst<P, N1, TX>), dim3(ncx * (p.n / 2)),
+    ProfScope ps(p, K_DST_X2_FWD, 2.0 * (2.0 * nq * p.m * sizeof(cx<P>)));
+    hipLaunchKernelGGL((k_cols_dst<P, N1, TX>), dim3(ncx * nq),
                        dim3(ColCfg<P, N1, TX>::NT), 0, p.stream, in, out, Tabs<P>::tws(p),
                        Tabs<P>::sin(p));
     return hipGetLastError();
@@ -2351,6 +2398,141 @@ hipError_t launch_lr_spectrum(const wc_plan &p, const double *r0) {
   if (!p.lr_2d) return hipErrorInvalidValue;
   return p.opts.precision == WC_MIXED ? lr_spectrum_t<float>(p, r0)
                                       : lr_spectrum_t<double>(p, r0);
+}
+
+// ---- finite elements (a == 1) in sine coordinates --------------------------------------
+// The mass and stiffness matrices of the linear / bilinear elements are diagonal in the
+// orthonormal sine basis: mass m_j1 (m_j2), M^{-1/2} K M^{-1/2} mu_j1 (+ mu_j2), so the
+// system is solved in sine coordinates, where step 2 of the preconditioner is one
+// pointwise pass and the data and the solution are transformed once per solve.
+__device__ __forceinline__ double fem_mass(const double *__restrict__ m1, int s, int M,
+                                           int dims) {
+  return dims == 1 ? m1[s] : m1[s % M] * m1[s / M];
+}
+
+// W[k m + s] = (A + i B)[k m + s] * mass_s^power, k < nslab (B may be null: zero)
+__global__ __launch_bounds__(kThreads) void k_fem_pack(const double *__restrict__ A,
+                                                       const double *__restrict__ B,
+                                                       cx<double> *__restrict__ W, size_t cnt,
+                                                       int m, int M, int dims,
+                                                       const double *__restrict__ m1,
+                                                       double power) {
+  const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= cnt) return;
+  const int s = (int)(idx % (size_t)m);
+  const double w = power == 0.0 ? 1.0 : pow(fem_mass(m1, s, M, dims), power);
+  W[idx] = cx<double>{A[idx] * w, B ? B[idx] * w : 0.0};
+}
+
+// A = scale mass^power Re W, B likewise with Im W, U = ucoef B when U is not null
+__global__ __launch_bounds__(kThreads) void k_fem_unpack(const cx<double> *__restrict__ W,
+                                                         double *__restrict__ A,
+                                                         double *__restrict__ B,
+                                                         double *__restrict__ U, size_t cnt, int m,
+                                                         int M, int dims,
+                                                         const double *__restrict__ m1,
+                                                         double power, double scale, double ucoef) {
+  const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= cnt) return;
+  const int s = (int)(idx % (size_t)m);
+  const double w = scale * (power == 0.0 ? 1.0 : pow(fem_mass(m1, s, M, dims), power));
+  const cx<double> z = W[idx];
+  A[idx] = w * z.x;
+  B[idx] = w * z.y;
+  if (U) U[idx] = ucoef * w * z.y;
+}
+
+// the y0 terms of the first block rows in sine coordinates, y0' = scale Re W[0 .. m):
+// f_1 += M^{-1/2} (M - (1 - theta) tau K) y0 = sqrt(mass) (1 - (1 - theta) tau mu) y0'
+// (times sqrt(gamma) in the system's right-hand side), g_1 -= tau (1 - theta) sqrt(mass) y0'
+__global__ __launch_bounds__(kThreads) void k_fem_y0(const cx<double> *__restrict__ W,
+                                                     double *__restrict__ bf,
+                                                     double *__restrict__ bg, int m, int M,
+                                                     int dims, const double *__restrict__ m1,
+                                                     const double *__restrict__ mu, double scale,
+                                                     double sqrt_gamma, double tau, double theta) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= m) return;
+  const double y = scale * W[s].x, sm = sqrt(fem_mass(m1, s, M, dims));
+  const double musum = dims == 1 ? mu[s] : mu[s % M] + mu[s / M];
+  bf[s] += sqrt_gamma * sm * (1.0 - (1.0 - theta) * tau * musum) * y;
+  bg[s] -= tau * (1.0 - theta) * sm * y;
+}
+
+namespace {
+// unnormalised sine transform of the first nslab slabs of d_femW (2D: both directions)
+template <int N1> hipError_t fem_dst_t(const wc_plan &p, int nslab) {
+  constexpr int M = N1 - 1;
+  cx<double> *W = (cx<double> *)p.d_femW;
+  hipError_t e = dst_rows_on<double, N1>(p, W, p.dims == 2 ? nslab * M : nslab, K_DST_X1_FWD,
+                                         2.0 * nslab * p.m * sizeof(cx<double>));
+  if (e != hipSuccess || p.dims == 1) return e;
+  return cols_dst_t<double, N1>(p, W, W, (nslab + 1) / 2);
+}
+hipError_t fem_dst(const wc_plan &p, int nslab) {
+  switch (p.N1) {
+#define CASE_S(NN) case NN: return fem_dst_t<NN>(p, nslab);
+    WC_POW2_CASES(CASE_S)
+#undef CASE_S
+    default: return hipErrorInvalidValue;
+  }
+}
+unsigned blocks_of(size_t cnt) { return (unsigned)((cnt + kThreads - 1) / kThreads); }
+// orthonormal sine basis = (2/N1)^{dims/2} times the unnormalised transform
+double fem_scale(const wc_plan &p) { return std::pow(2.0 / p.N1, 0.5 * p.dims); }
+}  // namespace
+
+hipError_t launch_fem_rhs_finish(const wc_plan &p, const double *y0, double *b) {
+  if (!p.fem || !p.d_femW || p.n % 2) return hipErrorInvalidValue;
+  const size_t nm = (size_t)p.n * p.m;
+  cx<double> *W = (cx<double> *)p.d_femW;
+  hipError_t e;
+  {  // both block rows into sine coordinates, times M^{-1/2} M = M^{1/2}
+    ProfScope ps(p, K_RHS, 16.0 * nm + 16.0 * nm);
+    hipLaunchKernelGGL(k_fem_pack, dim3(blocks_of(nm)), dim3(kThreads), 0, p.stream, b, b + nm, W,
+                       nm, p.m, p.M, p.dims, p.d_mass64, 0.0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = fem_dst(p, p.n)) != hipSuccess) return e;
+  {
+    ProfScope ps(p, K_RHS, 16.0 * nm + 16.0 * nm);
+    hipLaunchKernelGGL(k_fem_unpack, dim3(blocks_of(nm)), dim3(kThreads), 0, p.stream, W, b, b + nm,
+                       nullptr, nm, p.m, p.M, p.dims, p.d_mass64, 0.5, fem_scale(p), 0.0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {  // y0 into sine coordinates (slab 0), then its terms in the first block rows
+    ProfScope ps(p, K_RHS, 24.0 * p.m);
+    hipLaunchKernelGGL(k_fem_pack, dim3(blocks_of(p.m)), dim3(kThreads), 0, p.stream, y0, nullptr,
+                       W, (size_t)p.m, p.m, p.M, p.dims, p.d_mass64, 0.0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = fem_dst(p, 1)) != hipSuccess) return e;
+  // GMRES: b = [sqrt(gamma) f; g]; MINRES: b = [g; sqrt(gamma) f]
+  const bool sym = p.opts.method != WC_GMRES_PS;
+  double *bf = sym ? b + nm : b, *bg = sym ? b : b + nm;
+  ProfScope ps(p, K_RHS, 40.0 * p.m);
+  hipLaunchKernelGGL(k_fem_y0, dim3(blocks_of(p.m)), dim3(kThreads), 0, p.stream, W, bf, bg, p.m,
+                     p.M, p.dims, p.d_mass64, p.d_mu64, fem_scale(p), std::sqrt(p.gamma), p.tau,
+                     p.theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_fem_recover_finish(const wc_plan &p, double *y, double *pp, double *u) {
+  if (!p.fem || !p.d_femW || p.n % 2) return hipErrorInvalidValue;
+  const size_t nm = (size_t)p.n * p.m;
+  cx<double> *W = (cx<double> *)p.d_femW;
+  hipError_t e;
+  {  // M^{-1/2} in sine coordinates, then back to nodal values
+    ProfScope ps(p, K_RECOVER, 16.0 * nm + 16.0 * nm);
+    hipLaunchKernelGGL(k_fem_pack, dim3(blocks_of(nm)), dim3(kThreads), 0, p.stream, y, pp, W, nm,
+                       p.m, p.M, p.dims, p.d_mass64, -0.5);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = fem_dst(p, p.n)) != hipSuccess) return e;
+  ProfScope ps(p, K_RECOVER, 16.0 * nm + (u ? 24.0 : 16.0) * nm);
+  hipLaunchKernelGGL(k_fem_unpack, dim3(blocks_of(nm)), dim3(kThreads), 0, p.stream, W, y, pp, u,
+                     nm, p.m, p.M, p.dims, p.d_mass64, 0.0, fem_scale(p), 1.0 / p.gamma);
+  return hipGetLastError();
 }
 
 int pc_partials_needed(int n, int m, int precision) {

@@ -28,6 +28,7 @@ WC_OK, WC_E_ARG, WC_E_SINGULAR_S2, WC_E_NOMEM, WC_E_MAXIT, WC_E_BREAKDOWN = 0, 1
 WC_E_NONFINITE, WC_E_CANCELLED, WC_E_ADMISSION, WC_E_UNSUPPORTED, WC_E_HIP, WC_E_INTERNAL = 6, 7, 8, 9, 10, 11
 METHODS = {"minres_abs_ps": 0, "minres_pms": 1, "gmres_ps": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+DISCS = {"fd": 0, "fem": 1}
 
 
 class WcError(RuntimeError):
@@ -40,7 +41,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int), ("M", ctypes.c_int), ("n", ctypes.c_int),
                 ("T", ctypes.c_double), ("theta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("s2_remedy", ctypes.c_double),
-                ("a_face_host", ctypes.POINTER(ctypes.c_double))]
+                ("a_face_host", ctypes.POINTER(ctypes.c_double)), ("disc", ctypes.c_int)]
 
 
 class _Opts(ctypes.Structure):
@@ -146,8 +147,9 @@ class Info:
     reorth: int = 0
 
 
-def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face):
-    pr = _Problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None)
+def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc="fd"):
+    pr = _Problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None,
+                  DISCS[disc] if isinstance(disc, str) else int(disc))
     keep = None
     if a_face is not None:
         keep = np.ascontiguousarray(a_face, dtype=np.float64)
@@ -171,8 +173,8 @@ def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_to
 def footprint_bytes(dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                     a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
                     restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10,
-                    lowrank=False) -> int:
-    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
+                    lowrank=False, disc="fd") -> int:
+    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
     op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol,
                lowrank=lowrank)
     return int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
@@ -195,9 +197,9 @@ class Plan:
     def __init__(self, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                  a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
                  restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10, stream=None,
-                 graphs=True, lowrank=False):
+                 graphs=True, lowrank=False, disc="fd"):
         import torch
-        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
+        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
         op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
                    lowrank)
         if stream is None:
@@ -215,6 +217,7 @@ class Plan:
         self.method, self.precision = method, precision
         self.restart, self.flexible, self.graphs = restart, flexible, graphs
         self.lowrank = lowrank
+        self.disc = disc
         self.footprint = int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
     def close(self):
@@ -235,7 +238,8 @@ class Plan:
     def retarget(self, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0, a_face=None,
                  tol=1e-8, maxit=500, mg_max_cycles=30, mg_tol=1e-10):
         """Same sizes and method/precision/restart: new problem data, no allocation."""
-        pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face)
+        pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face,
+                             self.disc)
         op = _opts(self.method, self.precision, tol, maxit, self.restart, self.flexible,
                    mg_max_cycles, mg_tol, self.graphs, self.lowrank)
         self._check(_lib.wc_plan_retarget(self._h, ctypes.byref(pr), ctypes.byref(op)),
@@ -299,10 +303,11 @@ class Plan:
 
 
 def pc_apply_noalloc(v, w, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi,
-                     s2_remedy=1.0, method="gmres_ps", precision="fp64", stream=None) -> None:
+                     s2_remedy=1.0, method="gmres_ps", precision="fp64", stream=None,
+                     disc="fd") -> None:
     """w = P^{-1} v without a plan and without device allocation (wc_pc_apply_noalloc)."""
     import torch
-    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None)
+    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None, disc)
     if stream is None:
         stream = torch.cuda.current_stream()
     code = _lib.wc_pc_apply_noalloc(ctypes.byref(pr), METHODS[method], PRECISIONS[precision],
@@ -392,9 +397,9 @@ class Server:
     def submit(self, f, g, y0, y, p, u=None, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4,
                zeta=np.pi, s2_remedy=1.0, a_face=None, method="gmres_ps", precision="fp64",
                tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
-               mg_tol=1e-10, graphs=True, lowrank=False) -> int:
+               mg_tol=1e-10, graphs=True, lowrank=False, disc="fd") -> int:
         """Queue one solve; the tensors must stay alive and untouched until it is done."""
-        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face)
+        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
         op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
                    lowrank)
         t = _u64()

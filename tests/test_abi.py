@@ -71,6 +71,24 @@ def test_footprint_grows_with_restart_and_precision(wc):
     assert 10 * nvec < fmin < 10 * nvec + 2 * 256 * 255 * 255 * 16 * 2 + (64 << 20)
 
 
+def test_fem_options_and_footprint(wc):
+    """Finite elements (wc_disc): a == 1, no low-rank form; the plan holds one more FP64
+    complex array of n*m for the sine transforms of the data and the solution, and no
+    transposed copy of the spectral array (the preconditioner has no sine passes)."""
+    fd = wc.footprint_bytes(2, 63, 64)
+    fe = wc.footprint_bytes(2, 63, 64, disc="fem")
+    assert fe - fd == 64 * 63 * 63 * 16
+    fd = wc.footprint_bytes(2, 255, 256)
+    fe = wc.footprint_bytes(2, 255, 256, disc="fem")
+    # (finite differences at N1 >= 128 hold the transposed copy, n*M*N1 complex)
+    assert fe - fd == 256 * 255 * 255 * 16 - 256 * 255 * 256 * 16
+    a = np.ones(2 * 7 * 8)
+    assert wc.footprint_bytes(2, 7, 8, a_face=a, method="minres_pms", disc="fem") == 0
+    assert wc.footprint_bytes(2, 7, 8, lowrank=True, disc="fem") == 0
+    assert wc.footprint_bytes(2, 7, 8, disc=2) == 0
+    assert wc.footprint_bytes(1, 7, 8, method="minres_abs_ps", disc="fem") > 0
+
+
 def test_multigrid_options_and_footprint(wc):
     a = np.ones(2 * 31 * 32)
     base = wc.footprint_bytes(2, 31, 32, method="gmres_ps")

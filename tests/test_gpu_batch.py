@@ -129,8 +129,12 @@ def test_batch_solve_matches_single(env):
             assert bi.status == wc.WC_OK and bi.relres <= 1e-8
             assert bi.iters == si.iters and bi.restarts == si.restarts
             sc = max(np.abs(sy).max(), np.abs(sp).max())
-            assert np.abs(ys[i].cpu().numpy() - sy).max() <= 1e-11 * sc
-            assert np.abs(ps[i].cpu().numpy() - sp).max() <= 1e-11 * sc
+            # FP64: the same arithmetic in another order; mixed: the batched and single FP32
+            # applies round differently (1e-7 per apply), so the two solutions agree to about
+            # the solve tolerance
+            bound = (1e-11 if case[4] == "fp64" else 1e-8) * sc
+            assert np.abs(ys[i].cpu().numpy() - sy).max() <= bound
+            assert np.abs(ps[i].cpu().numpy() - sp).max() <= bound
     batch.close()
 
 
@@ -149,11 +153,13 @@ def test_batch_many_rhs(env):
         ref_p = torch.empty_like(ys[s])
         ri = plans[s].solve(*data[s], ref_y, ref_p)
         assert infos[s].relres <= 1e-8 and infos[s].iters == ri.iters
-        # the batched passes may round differently from the single ones (ulp level)
+        # the batched passes round differently from the single ones (at N1 >= 128 the single
+        # plan's x2 pass works on the transposed copy): ulp-level differences per apply,
+        # carried through the iterations as in test_batch_solve_matches_single
         sc = max(float(ref_y.abs().max()), float(ref_p.abs().max()))
         dy = float((ys[s] - ref_y).abs().max()) / sc
         dp = float((ps[s] - ref_p).abs().max()) / sc
-        assert dy <= 1e-13 and dp <= 1e-13, (s, dy, dp)
+        assert dy <= 1e-11 and dp <= 1e-11, (s, dy, dp)
     print("  many rhs iters", [i.iters for i in infos], "ms", infos[0].ms, flush=True)
     batch.close()
 
