@@ -164,6 +164,21 @@ def example2(M: int, n: int, gamma: float, T: float = 1.0):
     return dict(f=F, g=G, y0=Y[0].copy(), y_exact=Y, p_exact=P, a_face=a_face)
 
 
+def example3(M: int, n: int, T: float = 1.0, kappa: float = 1e-3):
+    """The paper's Example 3 (2D, homogeneous Neumann data, a = 1e-3, Section 4) on the
+    M x M grid of nodes x_j = j/(M-1) that includes the boundary nodes:
+    f = (8 pi^2 a - 1) e^{-t} cos(2 pi x1) cos(2 pi x2), g = e^{-t} cos(2 pi x1) cos(2 pi x2),
+    exact y = g, p = 0."""
+    x = np.arange(M, dtype=np.float64) / (M - 1)
+    X2, X1 = np.meshgrid(x, x, indexing="ij")
+    c = (np.cos(2 * np.pi * X1) * np.cos(2 * np.pi * X2)).ravel()
+    t = times(n, T)
+    g = np.exp(-t)[:, None] * c[None, :]
+    f = (8 * np.pi ** 2 * kappa - 1) * g
+    return dict(f=f, g=g, y0=g[0].copy(), y_exact=g.copy(), p_exact=np.zeros_like(g),
+                kappa=kappa)
+
+
 # Workload recipes.  Each returns the problem parameters and FP64 arrays that
 # both the oracle and the GPU path consume unchanged.
 CONFIGS = {

@@ -10,6 +10,11 @@ and stiffness matrices of continuous piecewise-linear (1D) / bilinear (2D)
 elements on the same grid; the system is the same with M_m in place of I
 (eqn:matrix_A_before) and K_m -> M_m^{-1/2} K_m M_m^{-1/2} after the change of
 variables (eqn:main_system).
+Homogeneous Neumann data (bc = "neumann", Example 3, finite differences, constant
+coefficient kappa): M nodes per dimension including both boundary nodes,
+x_j = j h, h = 1/(M-1); the boundary rows use a mirrored ghost node, so K_m is not
+symmetric, and the same K_m appears in the state and the adjoint block rows of
+eqn:matrix_A_before (the system is then not symmetric: GMRES-P_S only).
 
 Vectors are time major: a block vector [v^(1); ...; v^(n)] is an (n, m) array,
 spatial index x1 fastest.
@@ -36,14 +41,24 @@ class Problem:
     a_face: Optional[np.ndarray] = None  # None => a == 1
     s2_remedy: float = 1.0
     disc: str = "fd"                       # "fd" or "fem"
+    bc: str = "dirichlet"                  # "dirichlet" or "neumann"
+    kappa: float = 1.0                     # constant a when a_face is None
 
     def __post_init__(self):
         if self.dims not in (1, 2):
             raise ValueError("dims must be 1 or 2")
         if self.disc not in ("fd", "fem"):
             raise ValueError("disc must be fd or fem")
+        if self.bc not in ("dirichlet", "neumann"):
+            raise ValueError("bc must be dirichlet or neumann")
         if self.disc == "fem" and self.a_face is not None:
             raise ValueError("the finite element form is built for a = 1")
+        if self.a_face is not None and self.kappa != 1.0:
+            raise ValueError("a variable coefficient carries its own scale (kappa = 1)")
+        if not self.kappa > 0:
+            raise ValueError("kappa must be positive")
+        if self.bc == "neumann" and (self.disc != "fd" or self.a_face is not None or self.M < 2):
+            raise ValueError("the Neumann form is finite differences with constant a, M >= 2")
         if not (0.5 <= self.theta <= 1.0):
             raise ValueError("theta must lie in [1/2, 1] (Section 1)")
         if self.gamma <= 0:
@@ -51,7 +66,7 @@ class Problem:
 
     @property
     def h(self):
-        return 1.0 / (self.M + 1)
+        return 1.0 / (self.M - 1) if self.bc == "neumann" else 1.0 / (self.M + 1)
 
     @property
     def m(self):
@@ -113,6 +128,25 @@ def stiffness(dims: int, M: int, a_face: Optional[np.ndarray] = None) -> sp.csr_
     return sp.csr_matrix((vals, (rows, cols)), shape=(M * M, M * M))
 
 
+def stiffness_neumann(dims: int, M: int, kappa: float = 1.0) -> sp.csr_matrix:
+    """kappa times minus the three-point (1D) / five-point (2D) Laplacian on the M nodes
+    x_j = j h, h = 1/(M-1), of a uniform grid that includes both boundary nodes, with
+    homogeneous Neumann data imposed by a mirrored ghost node (u_{-1} = u_1,
+    u_M = u_{M-2}): (K1 u)_0 = 2(u_0 - u_1)/h^2, (K1 u)_{M-1} = 2(u_{M-1} - u_{M-2})/h^2,
+    interior rows (2 u_j - u_{j-1} - u_{j+1})/h^2.  2D: K1 along x1 plus K1 along x2."""
+    h2 = (1.0 / (M - 1)) ** 2
+    main = 2.0 * np.ones(M)
+    lo = -np.ones(M - 1)
+    up = -np.ones(M - 1)
+    up[0] = -2.0          # row 0: the ghost u_{-1} = u_1 doubles the east weight
+    lo[-1] = -2.0         # row M-1: the ghost u_M = u_{M-2} doubles the west weight
+    K1 = sp.diags([main, lo, up], [0, -1, 1]) * (kappa / h2)
+    if dims == 1:
+        return K1.tocsr()
+    I = sp.identity(M)
+    return (sp.kron(I, K1) + sp.kron(K1, I)).tocsr()
+
+
 def fem_matrices(dims: int, M: int):
     """(M_m, K_m) of continuous piecewise-linear (1D) or bilinear (2D) Lagrange elements
     on the uniform grid with interior nodes x_i = i h, h = 1/(M+1), a = 1, homogeneous
@@ -130,9 +164,12 @@ def fem_matrices(dims: int, M: int):
 
 def mass_stiffness(prob: "Problem"):
     """(M_m, K_m) of the problem's discretisation (Section 1)."""
+    if prob.bc == "neumann":
+        return sp.identity(prob.m, format="csr"), stiffness_neumann(prob.dims, prob.M, prob.kappa)
     if prob.disc == "fem":
-        return fem_matrices(prob.dims, prob.M)
-    return sp.identity(prob.m, format="csr"), stiffness(prob.dims, prob.M, prob.a_face)
+        Mm, K = fem_matrices(prob.dims, prob.M)
+        return Mm, K * prob.kappa
+    return sp.identity(prob.m, format="csr"), stiffness(prob.dims, prob.M, prob.a_face) * prob.kappa
 
 
 def mass_power(prob: "Problem", X: np.ndarray, power: float) -> np.ndarray:

@@ -57,11 +57,16 @@ def dense_calS(prob: Problem) -> np.ndarray:
 
 
 def dense_PS(prob: Problem) -> np.ndarray:
-    """P_S = [[S, -alpha I], [alpha I, S^*]]."""
+    """P_S = [[S, -alpha I], [alpha I, S_n^* kron I + tau I kron K]]: the time factor B_n of
+    the two block rows replaced by S_n and its adjoint; the spatial operator is the one of
+    A_hat's blocks (for a symmetric K the (2,2) block is S^*)."""
     S = dense_calS(prob)
+    Sn = circulant.Sn(prob.n, prob.theta, prob.zeta, prob.s2_remedy)
+    K = dense_khat(prob)
+    S2 = np.kron(Sn.conj().T, np.eye(prob.m)) + prob.tau * np.kron(np.eye(prob.n), K)
     a = prob.alpha
     I = np.eye(S.shape[0])
-    return np.block([[S, -a * I], [a * I, S.conj().T]])
+    return np.block([[S, -a * I], [a * I, S2]])
 
 
 def dense_absPS(prob: Problem) -> np.ndarray:
@@ -115,12 +120,14 @@ class FastPreconditioner:
             raise ValueError(kind)
         if kind == "abs_ps" and prob.a_face is not None:
             raise ValueError("|P_S| needs a fast-diagonalisable -L (a = 1)")
+        if kind != "ps" and prob.bc == "neumann":
+            raise ValueError("the Neumann system is not symmetric: P_S (GMRES) only")
         self.prob, self.kind = prob, kind
         n = prob.n
         self.Phi = circulant.transform(n, prob.zeta)
         self.Phiinv = circulant.inverse_transform(n, prob.zeta)
         _, _, self.lam = circulant.eigen_tables(n, prob.theta, prob.zeta, prob.s2_remedy)
-        self.K = stiffness(prob.dims, prob.M, prob.a_face).tocsc()
+        self.K = mass_stiffness(prob)[1].tocsc()
         self._lu = {}
 
     # step 2 for one frequency l (variable a), spatial data v1, v2 (complex m-vectors)
@@ -155,10 +162,16 @@ class FastPreconditioner:
         W1 = np.empty_like(H1)
         W2 = np.empty_like(H2)
         if pr.a_face is None:                 # step 2, all frequencies at once
-            mu = (spatial.fem_eigenvalues(pr.dims, pr.M) if pr.disc == "fem"
-                  else spatial.eigenvalues(pr.dims, pr.M))
-            T1 = spatial.sine_transform(pr.dims, pr.M, H1)
-            T2 = spatial.sine_transform(pr.dims, pr.M, H2)
+            neu = pr.bc == "neumann"
+            if neu:
+                mu = spatial.neumann_eigenvalues(pr.dims, pr.M, pr.kappa)
+                T1 = spatial.cosine_transform(pr.dims, pr.M, H1, inverse=True)
+                T2 = spatial.cosine_transform(pr.dims, pr.M, H2, inverse=True)
+            else:
+                mu = pr.kappa * (spatial.fem_eigenvalues(pr.dims, pr.M) if pr.disc == "fem"
+                                 else spatial.eigenvalues(pr.dims, pr.M))
+                T1 = spatial.sine_transform(pr.dims, pr.M, H1)
+                T2 = spatial.sine_transform(pr.dims, pr.M, H2)
             Lam = self.lam[:, None] + pr.tau * mu[None, :]
             a = pr.alpha
             if self.kind == "abs_ps":
@@ -170,8 +183,12 @@ class FastPreconditioner:
             else:
                 det = np.abs(Lam) ** 2 + a * a
                 T1, T2 = (np.conj(Lam) * T1 + a * T2) / det, (-a * T1 + Lam * T2) / det
-            W1 = spatial.sine_transform(pr.dims, pr.M, T1)
-            W2 = spatial.sine_transform(pr.dims, pr.M, T2)
+            if neu:
+                W1 = spatial.cosine_transform(pr.dims, pr.M, T1, inverse=False)
+                W2 = spatial.cosine_transform(pr.dims, pr.M, T2, inverse=False)
+            else:
+                W1 = spatial.sine_transform(pr.dims, pr.M, T1)
+                W2 = spatial.sine_transform(pr.dims, pr.M, T2)
         else:
             for l in range(n):
                 W1[l], W2[l] = self._solve_frequency(l, H1[l], H2[l])

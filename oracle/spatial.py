@@ -5,6 +5,13 @@ uniform grid with h = 1/(M+1): the orthonormal sine matrix
 U[i, j] = sqrt(2/(M+1)) sin(i j pi/(M+1)), i, j = 1..M, is symmetric and its
 own inverse, and U (-L_h) U = diag(mu) with mu_j = 4 h^-2 sin^2(j pi h / 2)
 (1D); in 2D the basis is U kron U with eigenvalues mu_j1 + mu_j2.
+
+Homogeneous Neumann data on the M nodes x_j = j h, h = 1/(M-1) (both boundary nodes
+included, mirrored ghost nodes): the cosine matrix C[j, k] = cos(j k pi/(M-1)),
+j, k = 0..M-1, holds eigenvectors of the three-point operator K1 (its columns), with
+eigenvalues 4 h^-2 sin^2(k pi h / 2); C is not orthogonal, and its inverse is
+(2/(M-1)) W C W with W = diag(1/2, 1, ..., 1, 1/2) (the trapezoidal weights under which
+the cosines are orthogonal).
 """
 from __future__ import annotations
 
@@ -57,3 +64,37 @@ def fem_eigenvalues(dims: int, M: int) -> np.ndarray:
     if dims == 1:
         return mu
     return (mu[:, None] + mu[None, :]).ravel()
+
+
+def cosine_matrix(M: int) -> np.ndarray:
+    k = np.arange(M)
+    return np.cos(np.outer(k, k) * np.pi / (M - 1))
+
+
+def cosine_inverse(M: int) -> np.ndarray:
+    w = np.ones(M)
+    w[0] = w[-1] = 0.5
+    return (2.0 / (M - 1)) * (w[:, None] * cosine_matrix(M) * w[None, :])
+
+
+def neumann_eigenvalues(dims: int, M: int, kappa: float = 1.0) -> np.ndarray:
+    """Eigenvalues of the Neumann operator kappa K1 (1D) or kappa (K1 along x1 + K1 along
+    x2) in the (x2, x1) row-major order of the cosine basis."""
+    h = 1.0 / (M - 1)
+    k = np.arange(M)
+    mu = kappa * 4.0 / h ** 2 * np.sin(k * np.pi * h / 2) ** 2
+    if dims == 1:
+        return mu
+    return (mu[:, None] + mu[None, :]).ravel()
+
+
+def cosine_transform(dims: int, M: int, X: np.ndarray, inverse: bool) -> np.ndarray:
+    """Rows of X (spatial vectors) times C^{-1} (inverse=True: into the cosine basis) or
+    C (back to nodal values); 2D along x1 and x2."""
+    A = cosine_inverse(M) if inverse else cosine_matrix(M)
+    if dims == 1:
+        return X @ A.T
+    shp = X.shape
+    Y = X.reshape(-1, M, M) @ A.T      # along x1
+    Y = np.matmul(A, Y)                # along x2
+    return Y.reshape(shp)
