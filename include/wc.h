@@ -79,6 +79,16 @@ typedef enum { WC_FP64 = 0, WC_MIXED = 1 } wc_precision;
  * (f, g, y0 in and y, p, u out stay physical nodal values). */
 typedef enum { WC_FD = 0, WC_FEM = 1 } wc_disc;
 
+/* Boundary data (Section 1: homogeneous Dirichlet; Section 4, Example 3: homogeneous
+ * Neumann).  WC_NEUMANN: finite differences with constant a (= kappa), on M nodes per
+ * dimension that include both boundary nodes (x_j = j h, h = 1/(M-1), m = M^dims);
+ * Neumann data by mirrored ghost nodes, so K_m is not symmetric and the same K_m sits
+ * in the state and adjoint block rows: the system is solved by GMRES-P_S only.  K_m is
+ * diagonalised by the cosine matrix C[j][k] = cos(j k pi/(M-1)), not orthogonal, with
+ * C^{-1} = (2/(M-1)) W C W (W the trapezoidal weights); the preconditioner's spatial
+ * step applies C^{-1} and C as dense transforms along x1 and x2 (any M from 2 to 1024). */
+typedef enum { WC_DIRICHLET = 0, WC_NEUMANN = 1 } wc_bc;
+
 /* The discrete problem (Section 1 and the Section 4 protocol). */
 typedef struct {
   int dims;           /* 1 or 2 */
@@ -97,6 +107,9 @@ typedef struct {
                          creation. */
   int disc;           /* wc_disc (0 = finite differences); WC_FEM needs a_face_host NULL
                          and no low-rank form */
+  int bc;             /* wc_bc (0 = Dirichlet) */
+  double kappa;       /* constant a (K_m scaled by kappa) when a_face_host is NULL; 0 is
+                         read as 1; must be 0 or 1 with a_face_host */
 } wc_problem;
 
 typedef struct {

@@ -62,6 +62,13 @@ wc_status validate(const wc_problem *pr, const wc_opts *op) {
   if (op->method == WC_MINRES_ABS_PS && pr->a_face_host) return WC_E_ARG;  // |P_S| needs a == 1
   if (pr->disc != WC_FD && pr->disc != WC_FEM) return WC_E_ARG;
   if (pr->disc == WC_FEM && (pr->a_face_host || op->lowrank)) return WC_E_ARG;
+  if (pr->bc != WC_DIRICHLET && pr->bc != WC_NEUMANN) return WC_E_ARG;
+  if (!(pr->kappa >= 0) || !std::isfinite(pr->kappa)) return WC_E_ARG;
+  if (pr->a_face_host && pr->kappa != 0.0 && pr->kappa != 1.0) return WC_E_ARG;
+  // Neumann data: finite differences, constant a, the nonsymmetric system (GMRES-P_S)
+  if (pr->bc == WC_NEUMANN && (pr->disc != WC_FD || pr->a_face_host || pr->M < 2 ||
+                               op->method != WC_GMRES_PS || op->lowrank))
+    return WC_E_ARG;
   // low-rank GMRES: a == 1; the FP32 preconditioner (restarts on the FP64 true residual
   // correct what FP32 leaves, like iterative refinement) in 2D only
   if (op->lowrank && (op->method != WC_GMRES_PS || pr->a_face_host ||
@@ -95,6 +102,8 @@ bool singular_s2_unremedied(const wc_problem *pr) {
 // multigrid hierarchy down to one point otherwise).
 bool pc_path_ok(const wc_problem *pr) {
   if (std::fabs(pr->zeta - M_PI) > 1e-12) return false;
+  if (pr->bc == WC_NEUMANN)  // dense cosine steps: any M up to 1024
+    return pow2_in(pr->n, 4, 1024) && pr->M >= 2 && pr->M <= 1024;
   return pow2_in(pr->n, 4, 1024) && pow2_in(pr->M + 1, 4, 1024);
 }
 
@@ -109,12 +118,12 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
 }
 
 struct Sizes {
-  size_t nvec, spec_bytes, spec_t_bytes, fem_bytes, partials, tables, vecs, mg, total;
+  size_t nvec, spec_bytes, spec_t_bytes, fem_bytes, neu_bytes, partials, tables, vecs, mg, total;
 };
 
 bool uses_spec_t(const wc_problem *pr, const wc_opts *op) {
   return pr->dims == 2 && !pr->a_face_host && !op->lowrank && pr->disc == WC_FD &&
-         pr->M + 1 >= 128 && pc_path_ok(pr);
+         pr->bc == WC_DIRICHLET && pr->M + 1 >= 128 && pc_path_ok(pr);
 }
 
 // Multigrid levels M_0 = M, M_{l+1} = (M_l - 1)/2, ..., 1; the first level whose remaining
@@ -152,6 +161,10 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es : 0;
   // finite elements: the FP64 complex sine transforms of the data and the solution
   s.fem_bytes = pr->disc == WC_FEM ? (size_t)pr->n * m * 16 : 0;
+  // Neumann: the second spectral array of the out-of-place dense steps, C and C^{-1}
+  s.neu_bytes = pr->bc == WC_NEUMANN
+                    ? s.spec_bytes + 2 * (size_t)pr->M * pr->M * (sizeof(double) + sizeof(float))
+                    : 0;
   // the Gram-Schmidt reduction of GMRES step j writes (j + 2) rows of kRedBlocks partials
   // (j + 1 projections and the norm), j < kMaxRestart
   size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads),
@@ -172,8 +185,8 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
            (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
            (size_t)pr->n * 6 * sizeof(double);
   }
-  s.total = s.spec_bytes + s.spec_t_bytes + s.fem_bytes + s.partials * sizeof(double) +
-            s.tables + s.vecs + S_COUNT * sizeof(double) + s.mg;
+  s.total = s.spec_bytes + s.spec_t_bytes + s.fem_bytes + s.neu_bytes +
+            s.partials * sizeof(double) + s.tables + s.vecs + S_COUNT * sizeof(double) + s.mg;
   return s;
 }
 
@@ -259,7 +272,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_lam64); dfree(p->d_lam32); dfree(p->d_dtw);
   dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
-  dfree(p->d_mass64); dfree(p->d_femW);
+  dfree(p->d_mass64); dfree(p->d_femW); dfree(p->d_cos64); dfree(p->d_cos32);
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_specT); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
@@ -675,6 +688,8 @@ void set_scalars(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
   p->s2_remedy = prob->s2_remedy;
   p->tau = prob->T / prob->n;
   p->alpha = p->tau / std::sqrt(prob->gamma);
+  p->kappa = prob->kappa == 0.0 ? 1.0 : prob->kappa;
+  p->inv_h2 = p->kappa / (p->h * p->h);  // K_m scaled by the constant a
   p->pc_ok = pc_path_ok(prob);
   p->opts = *opts;
 }
@@ -684,7 +699,7 @@ void set_scalars(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
 wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   // ---- FP64 tables ----
   const int n = p->n, N1 = p->N1, M = p->M;
-  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M), mass(M);
+  std::vector<double> lam(n), dtw(2 * n), twt(2 * n), tws(2 * N1), sn(N1), mu(M), mass(M), cs;
   for (int l = 0; l < n; ++l) {  // check every frequency of S^(2) for a zero eigenvalue
     const std::complex<double> e = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
     const std::complex<double> l2 = p->theta + (1.0 - p->theta) * e;
@@ -715,7 +730,10 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
     if (p->fem) {  // linear elements: U M1 U and U K1 U diagonal; mu = their ratio
       const double c = std::cos((j + 1) * M_PI * p->h);
       mass[j] = p->h / 3.0 * (2.0 + c);
-      mu[j] = (2.0 / p->h * (1.0 - c)) / mass[j];
+      mu[j] = p->kappa * (2.0 / p->h * (1.0 - c)) / mass[j];
+    } else if (p->neumann) {  // cosine k = j: 4 kappa h^-2 sin^2(k pi h/2), k = 0..M-1
+      const double sv = std::sin(j * M_PI * p->h / 2.0);
+      mu[j] = 4.0 * p->inv_h2 * sv * sv;
     } else {
       const double sv = std::sin((j + 1) * M_PI * p->h / 2.0);
       mu[j] = 4.0 * p->inv_h2 * sv * sv;
@@ -731,6 +749,21 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   WC_UP(d_lam32, lam32) WC_UP(d_twt32, twt32) WC_UP(d_tws32, tws32)
   WC_UP(d_sin32, sn32) WC_UP(d_mu32, mu32)
   if (p->fem) WC_UP(d_mass64, mass)
+  std::vector<float> cs32;
+  if (p->neumann) {  // C[j][k] = cos(j k pi/(M-1)), then C^{-1} = (2/(M-1)) W C W
+    const int L = M - 1;
+    cs.resize(2 * (size_t)M * M);
+    for (int j = 0; j < M; ++j)
+      for (int k = 0; k < M; ++k) {
+        const long r = ((long)j * k) % (2L * L);  // exact angle reduction
+        const double c = std::cos(M_PI * (double)r / L);
+        const double w = (j == 0 || j == L ? 0.5 : 1.0) * (k == 0 || k == L ? 0.5 : 1.0);
+        cs[(size_t)j * M + k] = c;
+        cs[(size_t)M * M + (size_t)j * M + k] = 2.0 / L * w * c;
+      }
+    cs32 = to_f32(cs);
+    WC_UP(d_cos64, cs) WC_UP(d_cos32, cs32)
+  }
 #undef WC_UP
   // low-rank GMRES: S_n - B_n = -omega g r^T with omega = e^{i zeta} = -1 (zeta = pi):
   // g = e_1 + (1 - theta) B_n e_1, r_k = q^{n-k} / (theta + omega (1 - theta) q^{n-1}),
@@ -927,9 +960,10 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   p->m = prob->dims == 1 ? prob->M : prob->M * prob->M;
   p->N1 = prob->M + 1;
   p->h = 1.0 / (prob->M + 1);
-  p->inv_h2 = 1.0 / (p->h * p->h);
   p->var_coeff = prob->a_face_host != nullptr;
   p->fem = prob->disc == WC_FEM;
+  p->neumann = prob->bc == WC_NEUMANN;
+  if (p->neumann) p->h = 1.0 / (prob->M - 1);  // M nodes including both boundary nodes
   p->stream = (hipStream_t)stream;
   p->nvec = 2 * (size_t)p->n * p->m;
   set_scalars(p, prob, opts);
@@ -958,6 +992,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   if (sz.spec_t_bytes && p->pc_ok) alloc(&p->d_specT, sz.spec_t_bytes);
   if (p->var_coeff) alloc(&p->d_specB, sz.spec_bytes);
   if (sz.fem_bytes) alloc((void **)&p->d_femW, sz.fem_bytes);
+  if (p->neumann) alloc(&p->d_specB, sz.spec_bytes);
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
   p->nkvec = krylov_vectors(prob, opts);
@@ -1016,6 +1051,7 @@ wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *op
   const wc_opts &o = p->opts;
   if (prob->dims != p->dims || prob->M != p->M || prob->n != p->n ||
       (prob->a_face_host != nullptr) != p->var_coeff || (prob->disc == WC_FEM) != p->fem ||
+      (prob->bc == WC_NEUMANN) != p->neumann ||
       opts->method != o.method ||
       opts->precision != o.precision || opts->restart != o.restart ||
       opts->flexible != o.flexible || opts->lowrank != o.lowrank)
@@ -1044,7 +1080,7 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   const int tss[5] = {4, 8, 16, -8, -16}, txs[5] = {4, 8, 16, -4, -8};
   const int nts = p->n >= 64 ? 5 : 3;
   // (finite elements: no sine passes in the preconditioner, only the time tiles matter)
-  const int ntx = (p->dims == 2 && !p->var_coeff && !p->fem) ? (p->d_specT ? 5 : 3) : 1;
+  const int ntx = (p->dims == 2 && !p->var_coeff && !p->fem && !p->neumann) ? (p->d_specT ? 5 : 3) : 1;
   float best = -1.f;
   int bts = p->ts_time, btx = p->tx_cols;
   hipError_t e = hipSuccess;

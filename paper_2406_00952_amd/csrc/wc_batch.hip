@@ -292,7 +292,8 @@ namespace wc {
 
 bool lockstep_eligible(const wc_problem *pr, const wc_opts *op) {
   const auto p2 = [](int x) { return x == 64 || x == 128 || x == 256 || x == 512; };
-  return pr->dims == 2 && !pr->a_face_host && pr->disc == WC_FD && op->method == WC_GMRES_PS &&
+  return pr->dims == 2 && !pr->a_face_host && pr->disc == WC_FD && pr->bc == WC_DIRICHLET &&
+         op->method == WC_GMRES_PS &&
          !op->lowrank &&
          std::fabs(pr->zeta - M_PI) <= 1e-12 && p2(pr->n) && p2(pr->M + 1);
 }
@@ -454,7 +455,8 @@ wc_status wc_batch_create(wc_plan *const *plans, int count, wc_batch **out) {
     for (int k = 0; k < i; ++k)
       if (plans[k] == plans[i]) return WC_E_ARG;  // each instance needs its own workspace
     const wc_plan &p = *plans[i];
-    if (p.dims != 2 || p.var_coeff || p.fem || !p.pc_ok || !batch_sizes_ok(p.n, p.N1))
+    if (p.dims != 2 || p.var_coeff || p.fem || p.neumann || !p.pc_ok ||
+        !batch_sizes_ok(p.n, p.N1))
       return WC_E_UNSUPPORTED;
   }
   auto *b = new (std::nothrow) wc_batch;

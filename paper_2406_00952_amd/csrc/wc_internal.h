@@ -110,6 +110,8 @@ struct wc_plan {
   double tau = 0, alpha = 0, h = 0, inv_h2 = 0;
   bool var_coeff = false;
   bool fem = false;              // finite elements (a == 1): the system in sine coordinates
+  bool neumann = false;          // Neumann data: M nodes incl. the boundary, dense cosine steps
+  double kappa = 1;              // constant a (folded into inv_h2 and the eigenvalue tables)
   bool pc_ok = false;            // the GPU preconditioner covers this problem
   int num_cu = 256;              // compute units of the plan's device
   int ts_time = 0;               // time passes: > 0 packed tile width, < 0 per-block-row
@@ -135,6 +137,8 @@ struct wc_plan {
   double *d_mass64 = nullptr;    // finite elements: M eigenvalues of the 1D mass matrix
   double *d_femW = nullptr;      // finite elements: n*m complex FP64, the sine transforms
                                  // of the data and of the solution
+  double *d_cos64 = nullptr;     // Neumann: 2 M*M reals, C then C^{-1} (row-major [j][k])
+  float *d_cos32 = nullptr;
   // workspaces
   void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
   void *d_specB = nullptr;       // n*m complex (P): multigrid fine solution (variable a)

@@ -141,8 +141,11 @@ wc_status wc_pc_apply_noalloc(const wc_problem *prob, int method, int precision,
   if (method < WC_MINRES_ABS_PS || method > WC_GMRES_PS) return WC_E_ARG;
   if (precision != WC_FP64 && precision != WC_MIXED) return WC_E_ARG;
   if (prob->disc != WC_FD && prob->disc != WC_FEM) return WC_E_ARG;
-  // the same coverage as wc_pc_apply for finite differences with a == 1
-  if (prob->a_face_host || prob->disc != WC_FD) return WC_E_UNSUPPORTED;
+  if (prob->bc != WC_DIRICHLET && prob->bc != WC_NEUMANN) return WC_E_ARG;
+  if (!(prob->kappa >= 0) || !std::isfinite(prob->kappa)) return WC_E_ARG;
+  // the same coverage as wc_pc_apply for finite differences, Dirichlet data, constant a
+  if (prob->a_face_host || prob->disc != WC_FD || prob->bc != WC_DIRICHLET)
+    return WC_E_UNSUPPORTED;
   if (std::fabs(prob->zeta - M_PI) > 1e-12 || !pow2_in(prob->n, 4, 1024) ||
       !pow2_in(prob->M + 1, 4, 1024))
     return WC_E_UNSUPPORTED;
@@ -178,7 +181,8 @@ wc_status wc_pc_apply_noalloc(const wc_problem *prob, int method, int precision,
   p.zeta = prob->zeta;
   p.s2_remedy = prob->s2_remedy;
   p.h = 1.0 / N1;
-  p.inv_h2 = (double)N1 * N1;
+  p.kappa = prob->kappa == 0.0 ? 1.0 : prob->kappa;
+  p.inv_h2 = p.kappa * N1 * N1;
   p.tau = prob->T / n;
   p.alpha = p.tau / std::sqrt(prob->gamma);
   p.var_coeff = false;

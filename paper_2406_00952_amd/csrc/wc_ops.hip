@@ -40,10 +40,31 @@ struct Stencil {
 
 // K_m for finite differences (the 3/5-point stencil), or, with diag (finite elements in
 // sine coordinates), the diagonal operator M^{-1/2} K M^{-1/2}: diag[j1] (+ diag[j2]).
+// neumann: M nodes per dimension including the boundary nodes, the missing neighbour of
+// a boundary node mirrored onto the inner one (its weight doubles); constant a.
 __device__ __forceinline__ Stencil make_stencil(int s, int M, int dims, double inv_h2,
                                                 const double *__restrict__ aface,
-                                                const double *__restrict__ diag = nullptr) {
+                                                const double *__restrict__ diag = nullptr,
+                                                bool neumann = false) {
   Stencil st;
+  if (neumann) {
+    const int i = dims == 1 ? s : s % M, j = dims == 1 ? 0 : s / M;
+    st.cw = i > 0 ? inv_h2 * (i == M - 1 ? 2.0 : 1.0) : 0.0;
+    st.ce = i < M - 1 ? inv_h2 * (i == 0 ? 2.0 : 1.0) : 0.0;
+    st.ow = i > 0 ? -1 : 0;
+    st.oe = i < M - 1 ? 1 : 0;
+    st.cc = 2.0 * inv_h2;
+    st.cs = st.cn = 0.0;
+    st.os = st.on = 0;
+    if (dims == 2) {
+      st.cs = j > 0 ? inv_h2 * (j == M - 1 ? 2.0 : 1.0) : 0.0;
+      st.cn = j < M - 1 ? inv_h2 * (j == 0 ? 2.0 : 1.0) : 0.0;
+      st.os = j > 0 ? -M : 0;
+      st.on = j < M - 1 ? M : 0;
+      st.cc = 4.0 * inv_h2;
+    }
+    return st;
+  }
   if (diag) {
     st.cc = dims == 1 ? diag[s] : diag[s % M] + diag[s / M];
     st.cw = st.ce = st.cs = st.cn = 0.0;
@@ -101,6 +122,7 @@ struct MvArgs {
   const double *aface;
   const double *diag;  // finite elements: the 1D eigenvalues of M^{-1/2} K M^{-1/2}
   double ssign;  // with sub: y = ssign * (A x - sub)
+  int neumann;   // Neumann data (nodes including the boundary)
 };
 
 // blockIdx.y == 0: T x1 - alpha x2 (forward in time); 1: T^T x2 + alpha x1 (backward).
@@ -125,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ 
     const size_t ooff = a.sym ? (dir == 0 ? nm : 0) : (dir == 0 ? 0 : nm);
     double *yo = y + ooff;
     const double *so = sub ? sub + ooff : nullptr;
-    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface, a.diag);
+    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface, a.diag, a.neumann);
     const bool dg = a.diag != nullptr;
     const double omt = 1.0 - a.theta, ith = 1.0 / a.theta;
     double zprev = 0.0, xprev = 0.0;
@@ -182,6 +204,7 @@ struct RhsArgs {
   double theta, tau, sqrt_gamma, inv_h2;
   const double *aface;
   int y0_terms;  // 0: leave out the y0 terms (finite elements add them in sine coordinates)
+  int neumann;   // Neumann data (nodes including the boundary)
 };
 
 // f_tilde, g_tilde of Section 1 with M = I, then b = [g; sqrt(gamma) f] (sym) or
@@ -199,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const double *__restrict__ f,
   double ft = a.tau * (th * f[(size_t)(k + 1) * a.m + s] + omt * f[(size_t)k * a.m + s]);
   double gt = a.tau * (th * g[(size_t)k * a.m + s] + omt * g[(size_t)(k + 1) * a.m + s]);
   if (k == 0 && a.y0_terms) {
-    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface);
+    const Stencil st = make_stencil(s, a.M, a.dims, a.inv_h2, a.aface, nullptr, a.neumann);
     ft += y0[s] - omt * a.tau * apply_stencil(st, y0, s);
     gt -= a.tau * omt * y0[s];
   }
@@ -691,7 +714,7 @@ hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *p
                          int *nblocks_out, const double *sub, bool negate) {
   MvArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
            p.theta, p.tau, p.alpha, p.inv_h2, p.d_aface, p.fem ? p.d_mu64 : nullptr,
-           negate ? -1.0 : 1.0};
+           negate ? -1.0 : 1.0, p.neumann ? 1 : 0};
   dim3 grid((p.m + kThreads - 1) / kThreads, 2);
   ProfScope ps(p, K_MATVEC, (sub ? 24.0 : 16.0) * p.nvec);
   hipLaunchKernelGGL(k_matvec, grid, dim3(kThreads), 0, p.stream, x, y, sub, a, partials);
@@ -702,7 +725,7 @@ hipError_t launch_matvec(const wc_plan &p, const double *x, double *y, double *p
 hipError_t launch_rhs(const wc_plan &p, const double *f, const double *g, const double *y0,
                       double *b) {
   RhsArgs a{p.n, p.M, p.dims, p.m, p.opts.method == WC_GMRES_PS ? 0 : 1,
-            p.theta, p.tau, sqrt(p.gamma), p.inv_h2, p.d_aface, p.fem ? 0 : 1};
+            p.theta, p.tau, sqrt(p.gamma), p.inv_h2, p.d_aface, p.fem ? 0 : 1, p.neumann ? 1 : 0};
   const size_t nm = (size_t)p.n * p.m;
   dim3 grid((unsigned)((nm + kThreads - 1) / kThreads));
   {

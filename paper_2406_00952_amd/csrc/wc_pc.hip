@@ -1557,6 +1557,7 @@ template <> struct Tabs<double> {
   static const double *sin(const wc_plan &p) { return p.d_sin64; }
   static const cx<double> *lam(const wc_plan &p) { return (const cx<double> *)p.d_lam64; }
   static const double *mu(const wc_plan &p) { return p.d_mu64; }
+  static const double *cos(const wc_plan &p) { return p.d_cos64; }
 };
 template <> struct Tabs<float> {
   static const cx<float> *twt(const wc_plan &p) { return (const cx<float> *)p.d_twt32; }
@@ -1564,6 +1565,7 @@ template <> struct Tabs<float> {
   static const float *sin(const wc_plan &p) { return p.d_sin32; }
   static const cx<float> *lam(const wc_plan &p) { return (const cx<float> *)p.d_lam32; }
   static const float *mu(const wc_plan &p) { return p.d_mu32; }
+  static const float *cos(const wc_plan &p) { return p.d_cos32; }
 };
 
 int row_grid(int wave_groups, int wpb) {
@@ -1901,6 +1903,119 @@ __global__ __launch_bounds__(kThreads) void k_mode_pointwise(cx<P> *__restrict__
   w0[m] = b;
 }
 
+// ---- dense spatial steps (Neumann data: the cosine basis is not orthogonal and M is any
+// size, so the steps are the dense products with C^{-1} and C) -----------------------
+// Y(j, c) = sum_k A[j][k] X(k, c) for every slab of the spectral array.  ROWS: along x1,
+// X(k, c) = entry k of line c (all lines of all slabs, one batch); else along x2, X(k, c)
+// = row k, column c of slab blockIdx.z (M x M).  64 x 64 output tiles, k in chunks of 16
+// through LDS; thread t owns the 4 x 4 outputs (j0 + tj + 16 a, c0 + tc + 16 b), with
+// the output index that is contiguous in memory fastest across the lanes.
+constexpr int kDenseT = 64, kDenseK = 16;
+template <typename P, bool ROWS>
+__global__ __launch_bounds__(256) void k_dense_apply(const cx<P> *__restrict__ X,
+                                                     cx<P> *__restrict__ Y,
+                                                     const P *__restrict__ A, int N, int C) {
+  __shared__ P As[kDenseK][kDenseT + 1];
+  __shared__ cx<P> Xs[kDenseK][kDenseT + 1];
+  const int tid = threadIdx.x;
+  const int tj = ROWS ? tid % 16 : tid / 16, tc = ROWS ? tid / 16 : tid % 16;
+  const int j0 = blockIdx.y * kDenseT, c0 = blockIdx.x * kDenseT;
+  const size_t slab = ROWS ? 0 : (size_t)blockIdx.z * N * N;
+  const cx<P> *Xb = X + slab;
+  cx<P> *Yb = Y + slab;
+  cx<P> acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cx<P>{(P)0, (P)0};
+  for (int k0 = 0; k0 < N; k0 += kDenseK) {
+    for (int e = tid; e < kDenseK * kDenseT; e += 256) {  // A rows are contiguous in k
+      const int kk = e % kDenseK, jj = e / kDenseK, j = j0 + jj, k = k0 + kk;
+      As[kk][jj] = (j < N && k < N) ? A[(size_t)j * N + k] : (P)0;
+    }
+    for (int e = tid; e < kDenseK * kDenseT; e += 256) {  // along the contiguous index
+      const int kk = ROWS ? e % kDenseK : e / kDenseT, cc = ROWS ? e / kDenseK : e % kDenseT;
+      const int k = k0 + kk, c = c0 + cc;
+      cx<P> v{(P)0, (P)0};
+      if (k < N && c < C) v = ROWS ? Xb[(size_t)c * N + k] : Xb[(size_t)k * N + c];
+      Xs[kk][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kDenseK; ++kk) {
+      P a[4];
+      cx<P> x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[kk][tj + 16 * i];
+        x[i] = Xs[kk][tc + 16 * i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[i][b].x += a[i] * x[b].x;
+          acc[i][b].y += a[i] * x[b].y;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + tj + 16 * i, c = c0 + tc + 16 * b;
+      if (j < N && c < C) {
+        if (ROWS) Yb[(size_t)c * N + j] = acc[i][b];
+        else Yb[(size_t)j * N + c] = acc[i][b];
+      }
+    }
+}
+
+namespace {
+// Neumann data, step 2 between the time transforms: into the cosine basis (C^{-1} along
+// x1, then x2), the per-mode solves, back (C along x2, then x1); d_specA -> d_specA via
+// d_specB
+template <typename P> hipError_t neumann_space(const wc_plan &p) {
+  const int M = p.M;
+  cx<P> *A = (cx<P> *)p.d_specA, *B = (cx<P> *)p.d_specB;
+  const P *Cf = Tabs<P>::cos(p), *Ci = Cf + (size_t)M * M;
+  const int lines = p.dims == 2 ? p.n * M : p.n;
+  const int gj = (M + kDenseT - 1) / kDenseT;
+  const dim3 grows((lines + kDenseT - 1) / kDenseT, gj), gcols(gj, gj, p.n);
+  const double bytes = 2.0 * p.nvec * sizeof(P);
+  hipError_t e;
+  auto rows = [&](const cx<P> *in, cx<P> *out, const P *mat, int id) {
+    ProfScope ps(p, id, bytes);
+    hipLaunchKernelGGL((k_dense_apply<P, true>), grows, dim3(256), 0, p.stream, in, out, mat, M,
+                       lines);
+    return hipGetLastError();
+  };
+  auto cols = [&](const cx<P> *in, cx<P> *out, const P *mat, int id) {
+    ProfScope ps(p, id, bytes);
+    hipLaunchKernelGGL((k_dense_apply<P, false>), gcols, dim3(256), 0, p.stream, in, out, mat, M,
+                       M);
+    return hipGetLastError();
+  };
+  if ((e = rows(A, B, Ci, K_DST_X1_FWD)) != hipSuccess) return e;
+  cx<P> *W = B;
+  if (p.dims == 2) {
+    if ((e = cols(B, A, Ci, K_DST_X1_FWD)) != hipSuccess) return e;
+    W = A;
+  }
+  {
+    const size_t cnt = (size_t)(p.n / 2) * p.m;
+    ProfScope ps(p, K_PAIR_MODE, bytes);
+    hipLaunchKernelGGL((k_mode_pointwise<P>), dim3((unsigned)((cnt + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, p.stream, W, p.n / 2, p.m, M, p.dims, Tabs<P>::lam(p),
+                       Tabs<P>::mu(p), 0, (P)p.tau, (P)p.alpha, (P)(1.0 / p.n));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (p.dims == 2 && (e = cols(A, B, Cf, K_DST_X1_INV)) != hipSuccess) return e;
+  return rows(B, A, Cf, K_DST_X1_INV);
+}
+}  // namespace
+
 template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
@@ -1932,7 +2047,9 @@ hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double
       default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (p.fem) {  // sine coordinates: step 2 is pointwise
+    if (p.neumann) {
+      e = neumann_space<P>(p);
+    } else if (p.fem) {  // sine coordinates: step 2 is pointwise
       const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
       const size_t cnt = (size_t)(p.n / 2) * p.m;
       ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));

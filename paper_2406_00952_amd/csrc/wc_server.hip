@@ -51,7 +51,8 @@ struct Key {
     const wc_problem &a = prob, &b = o.prob;
     const bool pe = a.dims == b.dims && a.M == b.M && a.n == b.n && a.T == b.T &&
                     a.theta == b.theta && a.gamma == b.gamma && a.zeta == b.zeta &&
-                    a.s2_remedy == b.s2_remedy && a.disc == b.disc;
+                    a.s2_remedy == b.s2_remedy && a.disc == b.disc && a.bc == b.bc &&
+                    a.kappa == b.kappa;
     const wc_opts &c = opts, &d = o.opts;
     const bool oe = c.method == d.method && c.precision == d.precision && c.tol == d.tol &&
                     c.maxit == d.maxit && c.restart == d.restart && c.flexible == d.flexible &&
@@ -63,7 +64,7 @@ struct Key {
   // same device footprint and buffers: a plan for one can be retargeted to the other
   bool same_shape(const Key &o) const {
     return prob.dims == o.prob.dims && prob.M == o.prob.M && prob.n == o.prob.n &&
-           prob.disc == o.prob.disc &&
+           prob.disc == o.prob.disc && prob.bc == o.prob.bc &&
            opts.method == o.opts.method && opts.precision == o.opts.precision &&
            opts.restart == o.opts.restart && opts.flexible == o.opts.flexible &&
            opts.lowrank == o.opts.lowrank && aface.empty() == o.aface.empty();

@@ -29,6 +29,7 @@ WC_E_NONFINITE, WC_E_CANCELLED, WC_E_ADMISSION, WC_E_UNSUPPORTED, WC_E_HIP, WC_E
 METHODS = {"minres_abs_ps": 0, "minres_pms": 1, "gmres_ps": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 DISCS = {"fd": 0, "fem": 1}
+BCS = {"dirichlet": 0, "neumann": 1}
 
 
 class WcError(RuntimeError):
@@ -41,7 +42,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int), ("M", ctypes.c_int), ("n", ctypes.c_int),
                 ("T", ctypes.c_double), ("theta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("zeta", ctypes.c_double), ("s2_remedy", ctypes.c_double),
-                ("a_face_host", ctypes.POINTER(ctypes.c_double)), ("disc", ctypes.c_int)]
+                ("a_face_host", ctypes.POINTER(ctypes.c_double)), ("disc", ctypes.c_int),
+                ("bc", ctypes.c_int), ("kappa", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -147,9 +149,11 @@ class Info:
     reorth: int = 0
 
 
-def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc="fd"):
+def _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc="fd", bc="dirichlet",
+             kappa=1.0):
     pr = _Problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None,
-                  DISCS[disc] if isinstance(disc, str) else int(disc))
+                  DISCS[disc] if isinstance(disc, str) else int(disc),
+                  BCS[bc] if isinstance(bc, str) else int(bc), float(kappa))
     keep = None
     if a_face is not None:
         keep = np.ascontiguousarray(a_face, dtype=np.float64)
@@ -173,8 +177,8 @@ def _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_to
 def footprint_bytes(dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                     a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
                     restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10,
-                    lowrank=False, disc="fd") -> int:
-    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
+                    lowrank=False, disc="fd", bc="dirichlet", kappa=1.0) -> int:
+    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc, bc, kappa)
     op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol,
                lowrank=lowrank)
     return int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
@@ -197,9 +201,10 @@ class Plan:
     def __init__(self, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0,
                  a_face=None, method="gmres_ps", precision="fp64", tol=1e-8, maxit=500,
                  restart=30, flexible=False, mg_max_cycles=30, mg_tol=1e-10, stream=None,
-                 graphs=True, lowrank=False, disc="fd"):
+                 graphs=True, lowrank=False, disc="fd", bc="dirichlet", kappa=1.0):
         import torch
-        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
+        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc, bc,
+                            kappa)
         op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
                    lowrank)
         if stream is None:
@@ -217,7 +222,7 @@ class Plan:
         self.method, self.precision = method, precision
         self.restart, self.flexible, self.graphs = restart, flexible, graphs
         self.lowrank = lowrank
-        self.disc = disc
+        self.disc, self.bc = disc, bc
         self.footprint = int(_lib.wc_plan_footprint_bytes(ctypes.byref(pr), ctypes.byref(op)))
 
     def close(self):
@@ -236,10 +241,10 @@ class Plan:
             raise WcError(code, where)
 
     def retarget(self, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi, s2_remedy=1.0, a_face=None,
-                 tol=1e-8, maxit=500, mg_max_cycles=30, mg_tol=1e-10):
+                 tol=1e-8, maxit=500, mg_max_cycles=30, mg_tol=1e-10, kappa=1.0):
         """Same sizes and method/precision/restart: new problem data, no allocation."""
         pr, _keep = _problem(self.dims, self.M, self.n, T, theta, gamma, zeta, s2_remedy, a_face,
-                             self.disc)
+                             self.disc, self.bc, kappa)
         op = _opts(self.method, self.precision, tol, maxit, self.restart, self.flexible,
                    mg_max_cycles, mg_tol, self.graphs, self.lowrank)
         self._check(_lib.wc_plan_retarget(self._h, ctypes.byref(pr), ctypes.byref(op)),
@@ -304,10 +309,10 @@ class Plan:
 
 def pc_apply_noalloc(v, w, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4, zeta=np.pi,
                      s2_remedy=1.0, method="gmres_ps", precision="fp64", stream=None,
-                     disc="fd") -> None:
+                     disc="fd", bc="dirichlet", kappa=1.0) -> None:
     """w = P^{-1} v without a plan and without device allocation (wc_pc_apply_noalloc)."""
     import torch
-    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None, disc)
+    pr, _keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, None, disc, bc, kappa)
     if stream is None:
         stream = torch.cuda.current_stream()
     code = _lib.wc_pc_apply_noalloc(ctypes.byref(pr), METHODS[method], PRECISIONS[precision],
@@ -397,9 +402,11 @@ class Server:
     def submit(self, f, g, y0, y, p, u=None, *, dims, M, n, T=1.0, theta=1.0, gamma=1e-4,
                zeta=np.pi, s2_remedy=1.0, a_face=None, method="gmres_ps", precision="fp64",
                tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
-               mg_tol=1e-10, graphs=True, lowrank=False, disc="fd") -> int:
+               mg_tol=1e-10, graphs=True, lowrank=False, disc="fd", bc="dirichlet",
+               kappa=1.0) -> int:
         """Queue one solve; the tensors must stay alive and untouched until it is done."""
-        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc)
+        pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc, bc,
+                            kappa)
         op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
                    lowrank)
         t = _u64()

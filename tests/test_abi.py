@@ -89,6 +89,27 @@ def test_fem_options_and_footprint(wc):
     assert wc.footprint_bytes(1, 7, 8, method="minres_abs_ps", disc="fem") > 0
 
 
+def test_neumann_kappa_options_and_footprint(wc):
+    """Neumann data (wc_bc): GMRES-P_S, finite differences, constant a; the plan holds a
+    second spectral array and C, C^{-1} in FP64 and FP32.  kappa: 0 reads as 1, negative or
+    non-finite refused, only 0 or 1 beside a variable coefficient."""
+    fd = wc.footprint_bytes(2, 32, 32)
+    fn = wc.footprint_bytes(2, 32, 32, bc="neumann", kappa=1e-3)
+    assert fn - fd == 32 * 32 * 32 * 16 + 2 * 32 * 32 * 12
+    for kw in (dict(method="minres_abs_ps"), dict(method="minres_pms"), dict(lowrank=True),
+               dict(disc="fem")):
+        assert wc.footprint_bytes(2, 32, 32, bc="neumann", **kw) == 0, kw
+    assert wc.footprint_bytes(2, 1, 32, bc="neumann") == 0      # M >= 2 nodes
+    assert wc.footprint_bytes(2, 30, 32, bc="neumann") > 0      # any M
+    assert wc.footprint_bytes(2, 31, 32, bc=2) == 0
+    assert wc.footprint_bytes(2, 31, 32, kappa=0.0) == wc.footprint_bytes(2, 31, 32)
+    assert wc.footprint_bytes(2, 31, 32, kappa=-1.0) == 0
+    assert wc.footprint_bytes(2, 31, 32, kappa=float("nan")) == 0
+    a = np.ones(2 * 31 * 32)
+    assert wc.footprint_bytes(2, 31, 32, a_face=a, kappa=2.0) == 0
+    assert wc.footprint_bytes(2, 31, 32, a_face=a, kappa=1.0) > 0
+
+
 def test_multigrid_options_and_footprint(wc):
     a = np.ones(2 * 31 * 32)
     base = wc.footprint_bytes(2, 31, 32, method="gmres_ps")
