@@ -107,6 +107,16 @@ bool pc_path_ok(const wc_problem *pr) {
   return pow2_in(pr->n, 4, 1024) && pow2_in(pr->M + 1, 4, 1024);
 }
 
+// Sizes or zeta outside the FFT path, constant coefficient finite differences: the general
+// path (dense time transform over all n frequencies, dense spatial steps).  Its tables
+// grow with n^2 and M^2, so n and M stay at most 1024.
+bool general_ok(const wc_problem *pr) {
+  if (pr->a_face_host || pr->disc != WC_FD) return false;
+  if (pr->n < 2 || pr->n > 1024 || pr->M > 1024) return false;
+  return pr->bc == WC_NEUMANN ? pr->M >= 2 : pr->M >= 1;
+}
+bool uses_general(const wc_problem *pr) { return !pc_path_ok(pr) && general_ok(pr); }
+
 int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
   (void)pr;
   if (op->lowrank) return 2 + 2;  // r0, P^{-1} update; B, X
@@ -118,7 +128,8 @@ int krylov_vectors(const wc_problem *pr, const wc_opts *op) {
 }
 
 struct Sizes {
-  size_t nvec, spec_bytes, spec_t_bytes, fem_bytes, neu_bytes, partials, tables, vecs, mg, total;
+  size_t nvec, spec_bytes, spec_t_bytes, fem_bytes, neu_bytes, gen_bytes, partials, tables, vecs,
+      mg, total;
 };
 
 bool uses_spec_t(const wc_problem *pr, const wc_opts *op) {
@@ -156,15 +167,19 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   const size_t m = (size_t)std::llround(std::pow((double)pr->M, pr->dims));
   s.nvec = 2 * (size_t)pr->n * m;
   const size_t es = op->precision == WC_MIXED ? 8 : 16;
-  s.spec_bytes = (size_t)pr->n * m * es;  // n/2 frequencies x 2 halves x m complex
+  const bool gen = uses_general(pr);
+  // n/2 frequencies x 2 halves x m complex; the general path keeps all n frequencies
+  s.spec_bytes = (gen ? 2 : 1) * (size_t)pr->n * m * es;
   // 2D a == 1 (standard form), N1 >= 128: the transposed copy of the x2 pass, rows of N1
   s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es : 0;
   // finite elements: the FP64 complex sine transforms of the data and the solution
   s.fem_bytes = pr->disc == WC_FEM ? (size_t)pr->n * m * 16 : 0;
   // Neumann: the second spectral array of the out-of-place dense steps, C and C^{-1}
-  s.neu_bytes = pr->bc == WC_NEUMANN
+  s.neu_bytes = pr->bc == WC_NEUMANN || gen
                     ? s.spec_bytes + 2 * (size_t)pr->M * pr->M * (sizeof(double) + sizeof(float))
                     : 0;
+  // general path: Phi and its inverse, the full eigenvalue table (FP64 and FP32)
+  s.gen_bytes = gen ? (2 * (size_t)pr->n * pr->n + pr->n) * 3 * sizeof(double) : 0;
   // the Gram-Schmidt reduction of GMRES step j writes (j + 2) rows of kRedBlocks partials
   // (j + 1 projections and the norm), j < kMaxRestart
   size_t parts = std::max<size_t>(2 * ((m + kThreads - 1) / kThreads),
@@ -185,7 +200,7 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
            (g.faces + 2 * (size_t)(pr->M + 1) * pr->M) * sizeof(double) +
            (size_t)pr->n * 6 * sizeof(double);
   }
-  s.total = s.spec_bytes + s.spec_t_bytes + s.fem_bytes + s.neu_bytes +
+  s.total = s.spec_bytes + s.spec_t_bytes + s.fem_bytes + s.neu_bytes + s.gen_bytes +
             s.partials * sizeof(double) + s.tables + s.vecs + S_COUNT * sizeof(double) + s.mg;
   return s;
 }
@@ -273,6 +288,7 @@ void free_plan(wc_plan *p) {
   dfree(p->d_twt64); dfree(p->d_twt32); dfree(p->d_tws64); dfree(p->d_tws32);
   dfree(p->d_sin64); dfree(p->d_sin32); dfree(p->d_mu64); dfree(p->d_mu32);
   dfree(p->d_mass64); dfree(p->d_femW); dfree(p->d_cos64); dfree(p->d_cos32);
+  dfree(p->d_phi64); dfree(p->d_phi32); dfree(p->d_lamf64); dfree(p->d_lamf32);
   dfree(p->d_specA); dfree(p->d_specB); dfree(p->d_specT); dfree(p->d_partials); dfree(p->d_scal);
   dfree(p->d_mg_a); dfree(p->d_mg_work); dfree(p->d_mg_shift); dfree(p->d_mg_mix);
   dfree(p->d_mg_u2);
@@ -690,7 +706,7 @@ void set_scalars(wc_plan *p, const wc_problem *prob, const wc_opts *opts) {
   p->alpha = p->tau / std::sqrt(prob->gamma);
   p->kappa = prob->kappa == 0.0 ? 1.0 : prob->kappa;
   p->inv_h2 = p->kappa / (p->h * p->h);  // K_m scaled by the constant a
-  p->pc_ok = pc_path_ok(prob);
+  p->pc_ok = pc_path_ok(prob) || p->general;
   p->opts = *opts;
 }
 
@@ -749,7 +765,45 @@ wc_status set_tables(wc_plan *p, const wc_problem *prob) {
   WC_UP(d_lam32, lam32) WC_UP(d_twt32, twt32) WC_UP(d_tws32, tws32)
   WC_UP(d_sin32, sn32) WC_UP(d_mu32, mu32)
   if (p->fem) WC_UP(d_mass64, mass)
-  std::vector<float> cs32;
+  std::vector<float> cs32, phi32, lamf32;
+  std::vector<double> phi, lamf;
+  if (p->general) {
+    // Phi[l][k] = e^{i zeta k/n} e^{-2 pi i k l/n}; its inverse (1/n) e^{-i zeta k/n}
+    // e^{2 pi i k l/n}; lambda_l = lambda^(1)_l / lambda^(2)_l of every frequency (remedy)
+    phi.resize(4 * (size_t)n * n);
+    for (int l = 0; l < n; ++l)
+      for (int k = 0; k < n; ++k) {
+        const double a = p->zeta * k / n - 2.0 * M_PI * (double)(((long)k * l) % n) / n;
+        const size_t f = 2 * ((size_t)l * n + k), b = 2 * ((size_t)n * n + (size_t)k * n + l);
+        phi[f] = std::cos(a);
+        phi[f + 1] = std::sin(a);
+        phi[b] = std::cos(a) / n;
+        phi[b + 1] = -std::sin(a) / n;
+      }
+    lamf.resize(2 * (size_t)n);
+    for (int l = 0; l < n; ++l) {
+      const std::complex<double> e1 = std::polar(1.0, (p->zeta - 2.0 * M_PI * l) / n);
+      std::complex<double> l2 = p->theta + (1.0 - p->theta) * e1;
+      if (std::abs(l2) < 1e-13) l2 = p->s2_remedy;
+      const std::complex<double> lv = (1.0 - e1) / l2;
+      lamf[2 * l] = lv.real();
+      lamf[2 * l + 1] = lv.imag();
+    }
+    phi32 = to_f32(phi);
+    lamf32 = to_f32(lamf);
+    WC_UP(d_phi64, phi) WC_UP(d_phi32, phi32) WC_UP(d_lamf64, lamf) WC_UP(d_lamf32, lamf32)
+    if (!p->neumann) {  // Dirichlet: the orthonormal sine matrix U = U^{-1} both ways
+      cs.resize(2 * (size_t)M * M);
+      for (int j = 0; j < M; ++j)
+        for (int k = 0; k < M; ++k) {
+          const long r = ((long)(j + 1) * (k + 1)) % (2L * (M + 1));
+          const double u = std::sqrt(2.0 / (M + 1)) * std::sin(M_PI * (double)r / (M + 1));
+          cs[(size_t)j * M + k] = cs[(size_t)M * M + (size_t)j * M + k] = u;
+        }
+      cs32 = to_f32(cs);
+      WC_UP(d_cos64, cs) WC_UP(d_cos32, cs32)
+    }
+  }
   if (p->neumann) {  // C[j][k] = cos(j k pi/(M-1)), then C^{-1} = (2/(M-1)) W C W
     const int L = M - 1;
     cs.resize(2 * (size_t)M * M);
@@ -952,6 +1006,8 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   if (singular_s2_unremedied(prob)) return WC_E_SINGULAR_S2;
   // finite elements work in sine coordinates: the data transforms need the sine sizes
   if (prob->disc == WC_FEM && !pc_path_ok(prob)) return WC_E_UNSUPPORTED;
+  // the low-rank form runs on the FFT path only
+  if (opts->lowrank && uses_general(prob)) return WC_E_UNSUPPORTED;
   wc_plan *p = new (std::nothrow) wc_plan();
   if (!p) return WC_E_NOMEM;
   p->dims = prob->dims;
@@ -964,6 +1020,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   p->fem = prob->disc == WC_FEM;
   p->neumann = prob->bc == WC_NEUMANN;
   if (p->neumann) p->h = 1.0 / (prob->M - 1);  // M nodes including both boundary nodes
+  p->general = uses_general(prob);
   p->stream = (hipStream_t)stream;
   p->nvec = 2 * (size_t)p->n * p->m;
   set_scalars(p, prob, opts);
@@ -992,7 +1049,7 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
   if (sz.spec_t_bytes && p->pc_ok) alloc(&p->d_specT, sz.spec_t_bytes);
   if (p->var_coeff) alloc(&p->d_specB, sz.spec_bytes);
   if (sz.fem_bytes) alloc((void **)&p->d_femW, sz.fem_bytes);
-  if (p->neumann) alloc(&p->d_specB, sz.spec_bytes);
+  if (p->neumann || p->general) alloc(&p->d_specB, sz.spec_bytes);
   alloc((void **)&p->d_partials, sz.partials * sizeof(double));
   alloc((void **)&p->d_scal, S_COUNT * sizeof(double));
   p->nkvec = krylov_vectors(prob, opts);
@@ -1051,7 +1108,7 @@ wc_status wc_plan_retarget(wc_plan *p, const wc_problem *prob, const wc_opts *op
   const wc_opts &o = p->opts;
   if (prob->dims != p->dims || prob->M != p->M || prob->n != p->n ||
       (prob->a_face_host != nullptr) != p->var_coeff || (prob->disc == WC_FEM) != p->fem ||
-      (prob->bc == WC_NEUMANN) != p->neumann ||
+      (prob->bc == WC_NEUMANN) != p->neumann || uses_general(prob) != p->general ||
       opts->method != o.method ||
       opts->precision != o.precision || opts->restart != o.restart ||
       opts->flexible != o.flexible || opts->lowrank != o.lowrank)
@@ -1078,7 +1135,7 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   // x1 tiles of 4 or 8 rows (tx < 0, when the plan holds the transposed copy)
   // time passes: packed tiles of 4, 8, 16 columns, or per-block-row tiles of 8, 16 (< 0)
   const int tss[5] = {4, 8, 16, -8, -16}, txs[5] = {4, 8, 16, -4, -8};
-  const int nts = p->n >= 64 ? 5 : 3;
+  const int nts = p->general ? 1 : (p->n >= 64 ? 5 : 3);
   // (finite elements: no sine passes in the preconditioner, only the time tiles matter)
   const int ntx = (p->dims == 2 && !p->var_coeff && !p->fem && !p->neumann) ? (p->d_specT ? 5 : 3) : 1;
   float best = -1.f;

@@ -455,7 +455,7 @@ wc_status wc_batch_create(wc_plan *const *plans, int count, wc_batch **out) {
     for (int k = 0; k < i; ++k)
       if (plans[k] == plans[i]) return WC_E_ARG;  // each instance needs its own workspace
     const wc_plan &p = *plans[i];
-    if (p.dims != 2 || p.var_coeff || p.fem || p.neumann || !p.pc_ok ||
+    if (p.dims != 2 || p.var_coeff || p.fem || p.neumann || p.general || !p.pc_ok ||
         !batch_sizes_ok(p.n, p.N1))
       return WC_E_UNSUPPORTED;
   }

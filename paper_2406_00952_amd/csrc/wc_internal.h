@@ -111,6 +111,7 @@ struct wc_plan {
   bool var_coeff = false;
   bool fem = false;              // finite elements (a == 1): the system in sine coordinates
   bool neumann = false;          // Neumann data: M nodes incl. the boundary, dense cosine steps
+  bool general = false;          // sizes / zeta outside the FFT path: dense steps throughout
   double kappa = 1;              // constant a (folded into inv_h2 and the eigenvalue tables)
   bool pc_ok = false;            // the GPU preconditioner covers this problem
   int num_cu = 256;              // compute units of the plan's device
@@ -137,8 +138,12 @@ struct wc_plan {
   double *d_mass64 = nullptr;    // finite elements: M eigenvalues of the 1D mass matrix
   double *d_femW = nullptr;      // finite elements: n*m complex FP64, the sine transforms
                                  // of the data and of the solution
-  double *d_cos64 = nullptr;     // Neumann: 2 M*M reals, C then C^{-1} (row-major [j][k])
-  float *d_cos32 = nullptr;
+  double *d_cos64 = nullptr;     // dense spatial steps: 2 M*M reals, the basis matrix then its
+  float *d_cos32 = nullptr;      //   inverse (row-major [j][k]): C, C^{-1} or U, U
+  double *d_phi64 = nullptr;     // general path: 2 n*n complex, Phi = F diag(omega^{k/n}) then
+  float *d_phi32 = nullptr;      //   its inverse (row-major)
+  double *d_lamf64 = nullptr;    // general path: n complex, lambda_l of every frequency
+  float *d_lamf32 = nullptr;
   // workspaces
   void *d_specA = nullptr;       // n*m complex (P): spectral array, layout [q][half][x2][x1]
   void *d_specB = nullptr;       // n*m complex (P): multigrid fine solution (variable a)
@@ -277,6 +282,8 @@ int red_blocks(size_t n);
 hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,
                            const double *c, int slot, double h0, double h1, double h2);
 // partials of <a, b> (one per block) -> finalize into d_scal[slot]
+// sum_i a_i b_i over the system vector as partial sums in d_partials (count in *nparts)
+hipError_t launch_dot_partials(const wc_plan &p, const double *a, const double *b, int *nparts);
 hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot,
                       size_t len = 0);
 hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, int nsum,

@@ -763,6 +763,15 @@ hipError_t launch_finalize(const wc_plan &p, const double *partials, int count, 
   return hipGetLastError();
 }
 
+hipError_t launch_dot_partials(const wc_plan &p, const double *a, const double *b,
+                               int *nparts) {
+  const int nb = red_blocks(p.nvec);
+  ProfScope ps(p, K_DOT, 16.0 * p.nvec);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, p.stream, a, b, p.nvec, p.d_partials);
+  if (nparts) *nparts = nb;
+  return hipGetLastError();
+}
+
 hipError_t launch_dot(const wc_plan &p, const double *a, const double *b, int slot,
                       size_t len) {
   const size_t nv = len ? len : p.nvec;

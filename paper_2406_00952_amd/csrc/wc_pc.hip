@@ -1558,6 +1558,8 @@ template <> struct Tabs<double> {
   static const cx<double> *lam(const wc_plan &p) { return (const cx<double> *)p.d_lam64; }
   static const double *mu(const wc_plan &p) { return p.d_mu64; }
   static const double *cos(const wc_plan &p) { return p.d_cos64; }
+  static const cx<double> *phi(const wc_plan &p) { return (const cx<double> *)p.d_phi64; }
+  static const cx<double> *lamf(const wc_plan &p) { return (const cx<double> *)p.d_lamf64; }
 };
 template <> struct Tabs<float> {
   static const cx<float> *twt(const wc_plan &p) { return (const cx<float> *)p.d_twt32; }
@@ -1566,6 +1568,8 @@ template <> struct Tabs<float> {
   static const cx<float> *lam(const wc_plan &p) { return (const cx<float> *)p.d_lam32; }
   static const float *mu(const wc_plan &p) { return p.d_mu32; }
   static const float *cos(const wc_plan &p) { return p.d_cos32; }
+  static const cx<float> *phi(const wc_plan &p) { return (const cx<float> *)p.d_phi32; }
+  static const cx<float> *lamf(const wc_plan &p) { return (const cx<float> *)p.d_lamf32; }
 };
 
 int row_grid(int wave_groups, int wpb) {
@@ -1972,18 +1976,104 @@ __global__ __launch_bounds__(256) void k_dense_apply(const cx<P> *__restrict__ X
     }
 }
 
+// ---- general path: sizes or zeta outside the FFT path ------------------------------
+// Time step as a dense product over all n frequencies, both block rows (blockIdx.z = h):
+// FWD  G[h][l][s] = sum_k Phi[l][k] v[h][k][s]       (v real FP64, G complex P)
+// !FWD w[h][k][s] = Re sum_l Phiinv[k][l] G[h][l][s]  (real FP64 out)
+// with s = 0..m-1 contiguous: 64 x 64 output tiles of (l or k) x s, 16-deep chunks.
+template <typename P, bool FWD>
+__global__ __launch_bounds__(256) void k_dense_time(const void *__restrict__ Xv,
+                                                    void *__restrict__ Yv,
+                                                    const cx<P> *__restrict__ A, int n, int m) {
+  using XT = typename std::conditional<FWD, double, cx<P>>::type;
+  using YT = typename std::conditional<FWD, cx<P>, double>::type;
+  using AccT = typename std::conditional<FWD, cx<P>, P>::type;
+  __shared__ cx<P> As[kDenseK][kDenseT + 1];
+  __shared__ XT Xs[kDenseK][kDenseT + 1];
+  const int tid = threadIdx.x, tj = tid / 16, tc = tid % 16;
+  const int j0 = blockIdx.y * kDenseT, c0 = blockIdx.x * kDenseT;
+  const XT *X = (const XT *)Xv + (size_t)blockIdx.z * n * m;
+  YT *Y = (YT *)Yv + (size_t)blockIdx.z * n * m;
+  AccT acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = AccT{};
+  for (int k0 = 0; k0 < n; k0 += kDenseK) {
+    for (int e = tid; e < kDenseK * kDenseT; e += 256) {  // A rows contiguous in k
+      const int kk = e % kDenseK, jj = e / kDenseK, j = j0 + jj, k = k0 + kk;
+      As[kk][jj] = (j < n && k < n) ? A[(size_t)j * n + k] : cx<P>{(P)0, (P)0};
+    }
+    for (int e = tid; e < kDenseK * kDenseT; e += 256) {  // X rows contiguous in s
+      const int kk = e / kDenseT, cc = e % kDenseT, k = k0 + kk, c = c0 + cc;
+      Xs[kk][cc] = (k < n && c < m) ? X[(size_t)k * m + c] : XT{};
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kDenseK; ++kk) {
+      cx<P> a[4];
+      XT x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = As[kk][tj + 16 * i];
+        x[i] = Xs[kk][tc + 16 * i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (FWD) {  // complex times real data
+            acc[i][b].x += a[i].x * (P)x[b];
+            acc[i][b].y += a[i].y * (P)x[b];
+          } else {  // the real part of complex times complex
+            acc[i][b] += a[i].x * x[b].x - a[i].y * x[b].y;
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + tj + 16 * i, c = c0 + tc + 16 * b;
+      if (j < n && c < m) {
+        if constexpr (FWD) Y[(size_t)j * m + c] = acc[i][b];
+        else Y[(size_t)j * m + c] = (double)acc[i][b];
+      }
+    }
+}
+
+// step 2 of the general path: the per-mode operation of frequency l and mode s couples
+// G[0][l][s] and G[1][l][s] (lambda_l of the full table; the dense steps are normalised)
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_mode_full(cx<P> *__restrict__ G, int n, int m, int M,
+                                                       int dims, const cx<P> *__restrict__ lam,
+                                                       const P *__restrict__ mu, int kind, P tau,
+                                                       P alpha) {
+  const size_t idx = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t nm = (size_t)n * m;
+  if (idx >= nm) return;
+  const int l = (int)(idx / (size_t)m), s = (int)(idx - (size_t)l * m);
+  const P musum = dims == 1 ? mu[s] : mu[s % M] + mu[s / M];
+  cx<P> a = G[idx], b = G[nm + idx];
+  mode_op<P>(a, b, lam[l], musum, kind, tau, alpha, (P)1);
+  G[idx] = a;
+  G[nm + idx] = b;
+}
+
 namespace {
-// Neumann data, step 2 between the time transforms: into the cosine basis (C^{-1} along
-// x1, then x2), the per-mode solves, back (C along x2, then x1); d_specA -> d_specA via
-// d_specB
-template <typename P> hipError_t neumann_space(const wc_plan &p) {
+// the spatial step of the dense paths on nslab slabs of m complex (lines of M along x1):
+// into the basis (second table matrix along x1, then x2), op(W), back (first matrix along
+// x2, then x1); A -> A through B
+template <typename P, typename Op>
+hipError_t dense_space(const wc_plan &p, cx<P> *A, cx<P> *B, int nslab, Op op) {
   const int M = p.M;
-  cx<P> *A = (cx<P> *)p.d_specA, *B = (cx<P> *)p.d_specB;
   const P *Cf = Tabs<P>::cos(p), *Ci = Cf + (size_t)M * M;
-  const int lines = p.dims == 2 ? p.n * M : p.n;
+  const int lines = p.dims == 2 ? nslab * M : nslab;
   const int gj = (M + kDenseT - 1) / kDenseT;
-  const dim3 grows((lines + kDenseT - 1) / kDenseT, gj), gcols(gj, gj, p.n);
-  const double bytes = 2.0 * p.nvec * sizeof(P);
+  const dim3 grows((lines + kDenseT - 1) / kDenseT, gj), gcols(gj, gj, nslab);
+  const double bytes = 2.0 * nslab * (double)p.m * sizeof(cx<P>);
   hipError_t e;
   auto rows = [&](const cx<P> *in, cx<P> *out, const P *mat, int id) {
     ProfScope ps(p, id, bytes);
@@ -2003,16 +2093,60 @@ template <typename P> hipError_t neumann_space(const wc_plan &p) {
     if ((e = cols(B, A, Ci, K_DST_X1_FWD)) != hipSuccess) return e;
     W = A;
   }
-  {
-    const size_t cnt = (size_t)(p.n / 2) * p.m;
-    ProfScope ps(p, K_PAIR_MODE, bytes);
-    hipLaunchKernelGGL((k_mode_pointwise<P>), dim3((unsigned)((cnt + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, p.stream, W, p.n / 2, p.m, M, p.dims, Tabs<P>::lam(p),
-                       Tabs<P>::mu(p), 0, (P)p.tau, (P)p.alpha, (P)(1.0 / p.n));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if ((e = op(W)) != hipSuccess) return e;
   if (p.dims == 2 && (e = cols(A, B, Cf, K_DST_X1_INV)) != hipSuccess) return e;
   return rows(B, A, Cf, K_DST_X1_INV);
+}
+
+// P^{-1} v on the general path: dense time transform of both block rows over all n
+// frequencies (any n, any zeta), dense spatial steps, per-mode solves, the inverse
+// steps, the real part (the preconditioner of a real system)
+template <typename P>
+hipError_t pc_apply_general(const wc_plan &p, const double *v, double *w, const double *dotv,
+                            int *nparts) {
+  cx<P> *G = (cx<P> *)p.d_specA, *B = (cx<P> *)p.d_specB;
+  const int n = p.n, m = p.m;
+  const dim3 gt((m + kDenseT - 1) / kDenseT, (n + kDenseT - 1) / kDenseT, 2);
+  const double vbytes = 8.0 * p.nvec, gbytes = 2.0 * n * (double)m * sizeof(cx<P>);
+  hipError_t e;
+  {
+    ProfScope ps(p, K_TFFT_FWD, vbytes + gbytes);
+    hipLaunchKernelGGL((k_dense_time<P, true>), gt, dim3(256), 0, p.stream, (const void *)v,
+                       (void *)G, Tabs<P>::phi(p), n, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
+  e = dense_space<P>(p, G, B, 2 * n, [&](cx<P> *W) {
+    const size_t cnt = (size_t)n * m;
+    ProfScope ps(p, K_PAIR_MODE, 2.0 * gbytes);
+    hipLaunchKernelGGL((k_mode_full<P>), dim3((unsigned)((cnt + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, p.stream, W, n, m, p.M, p.dims, Tabs<P>::lamf(p),
+                       Tabs<P>::mu(p), kind, (P)p.tau, (P)p.alpha);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(p, K_TFFT_INV, vbytes + gbytes);
+    hipLaunchKernelGGL((k_dense_time<P, false>), gt, dim3(256), 0, p.stream, (const void *)G,
+                       (void *)w, Tabs<P>::phi(p) + (size_t)n * n, n, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  *nparts = 0;
+  if (dotv) return launch_dot_partials(p, w, dotv, nparts);
+  return hipSuccess;
+}
+
+// Neumann data on the FFT time path, step 2 between the time transforms: into the cosine
+// basis, the per-mode solves of the n/2 kept frequencies, back (d_specA via d_specB)
+template <typename P> hipError_t neumann_space(const wc_plan &p) {
+  return dense_space<P>(p, (cx<P> *)p.d_specA, (cx<P> *)p.d_specB, p.n, [&](cx<P> *W) {
+    const size_t cnt = (size_t)(p.n / 2) * p.m;
+    ProfScope ps(p, K_PAIR_MODE, 2.0 * p.nvec * sizeof(P));
+    hipLaunchKernelGGL((k_mode_pointwise<P>), dim3((unsigned)((cnt + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, p.stream, W, p.n / 2, p.m, p.M, p.dims, Tabs<P>::lam(p),
+                       Tabs<P>::mu(p), 0, (P)p.tau, (P)p.alpha, (P)(1.0 / p.n));
+    return hipGetLastError();
+  });
 }
 }  // namespace
 
@@ -2020,6 +2154,10 @@ template <typename P>
 hipError_t pc_apply_t(const wc_plan &p, const double *v, double *w, const double *dotv,
                       int *nparts, const GenIn *gen, const ContractOut *co) {
   hipError_t e = hipErrorInvalidValue;
+  if (p.general) {
+    if (gen || co) return hipErrorInvalidValue;  // the low-rank form runs on the FFT path
+    return pc_apply_general<P>(p, v, w, dotv, nparts);
+  }
   // 2D low-rank GMRES (Arnoldi steps and the cycle's update): the spectrum comes from the
   // cycle's transformed r0, in the first sine pass
   const bool hoist = gen && p.lr_2d;

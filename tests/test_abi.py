@@ -93,9 +93,15 @@ def test_neumann_kappa_options_and_footprint(wc):
     """Neumann data (wc_bc): GMRES-P_S, finite differences, constant a; the plan holds a
     second spectral array and C, C^{-1} in FP64 and FP32.  kappa: 0 reads as 1, negative or
     non-finite refused, only 0 or 1 beside a variable coefficient."""
-    fd = wc.footprint_bytes(2, 32, 32)
-    fn = wc.footprint_bytes(2, 32, 32, bc="neumann", kappa=1e-3)
-    assert fn - fd == 32 * 32 * 32 * 16 + 2 * 32 * 32 * 12
+    fd = wc.footprint_bytes(2, 31, 32)
+    fn = wc.footprint_bytes(2, 31, 32, bc="neumann", kappa=1e-3)
+    assert fn - fd == 32 * 31 * 31 * 16 + 2 * 31 * 31 * 12
+    # Dirichlet data with M + 1 = 33 takes the general path: both spectral arrays hold all
+    # n frequencies (twice the FFT path's), plus Phi and its inverse and the full
+    # eigenvalue table in FP64 and FP32; the dense sine matrices match the cosine ones
+    fg = wc.footprint_bytes(2, 32, 32)
+    fn = wc.footprint_bytes(2, 32, 32, bc="neumann")
+    assert fg - fn == 2 * 32 * 32 * 32 * 16 + (2 * 32 * 32 + 32) * 24
     for kw in (dict(method="minres_abs_ps"), dict(method="minres_pms"), dict(lowrank=True),
                dict(disc="fem")):
         assert wc.footprint_bytes(2, 32, 32, bc="neumann", **kw) == 0, kw

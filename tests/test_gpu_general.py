@@ -1,0 +1,165 @@
+"""GPU parity of the general path: sizes and zeta outside the FFT path (any n, including
+odd n with the remedied singular S_n^(2) of the remark in Section 1; any M; any zeta,
+omega = e^{i zeta}) for constant-coefficient finite differences, Dirichlet or Neumann data.
+The time step is a dense product over all n frequencies and the spatial steps dense
+products with the sine (or cosine) matrix; the preconditioner of the real system is the
+real part of P^{-1} v, as in the oracle.
+
+Tolerances: FP64 applies 1e-12 relative to the largest entry; FP32 applies 1e-4 (dense
+sums of up to n = 64 terms in single precision); solves to 1e-8 with iteration counts
+within 2 of the oracle, and agreement to 1e-10 at tolerance 1e-13.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle.discretization import Problem, AllAtOnce
+from oracle.precond import FastPreconditioner
+from oracle import solver as osolver
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"gmres_ps": "ps", "minres_abs_ps": "abs_ps", "minres_pms": "pms"}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2406_00952_amd import wc
+    return torch, wc
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def say(*args):
+    print(*args, flush=True)
+
+
+# dims, M, n, theta, zeta, bc
+PC_CASES = [
+    (2, 30, 16, 0.5, np.pi, "dirichlet"),    # M + 1 = 31: no sine FFT
+    (1, 100, 12, 1.0, np.pi, "dirichlet"),   # n = 12
+    (2, 20, 9, 0.5, np.pi, "dirichlet"),     # odd n, theta = 1/2: remedied S^(2)
+    (1, 63, 64, 0.5, 1.0, "dirichlet"),      # power-of-two sizes, complex omega
+    (2, 15, 10, 0.5, 0.0, "dirichlet"),      # omega = 1, n even: remedied S^(2)
+    (2, 70, 5, 0.7, 2.5, "dirichlet"),       # two 64-wide tiles with tails
+    (2, 20, 10, 0.5, 0.5, "neumann"),
+    (1, 33, 7, 1.0, np.pi, "neumann"),
+    (1, 1, 3, 0.5, np.pi, "dirichlet"),      # smallest sizes
+]
+
+
+def _problem(dims, M, n, theta, zeta, bc, gamma=1e-4):
+    kappa = 0.1 if bc == "neumann" else 1.0
+    return Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma, zeta=zeta, bc=bc,
+                   kappa=kappa)
+
+
+@pytest.mark.parametrize("dims,M,n,theta,zeta,bc", PC_CASES)
+@pytest.mark.parametrize("method", ["gmres_ps", "minres_abs_ps", "minres_pms"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_general_pc_apply(env, dims, M, n, theta, zeta, bc, method, precision):
+    torch, wc = env
+    if bc == "neumann" and method != "gmres_ps":
+        pytest.skip("the Neumann system is not symmetric: GMRES-P_S only")
+    say("general pc", dims, M, n, theta, zeta, bc, method, precision)
+    pr = _problem(dims, M, n, theta, zeta, bc)
+    plan = wc.Plan(dims, M, n, theta=theta, gamma=pr.gamma, zeta=zeta, method=method,
+                   precision=precision, bc=bc, kappa=pr.kappa)
+    v = datagen.random_vector(11, 2 * n * pr.m)
+    vd = dev(torch, v)
+    wd = torch.empty_like(vd)
+    plan.pc_apply(vd, wd)
+    ref = FastPreconditioner(pr, KIND[method]).apply(v)
+    torch.cuda.synchronize()
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert relerr(host(wd), ref) < tol
+    plan.pc_apply(vd, vd)  # in place
+    torch.cuda.synchronize()
+    assert relerr(host(vd), ref) < tol
+
+
+SOLVE_CASES = [
+    (2, 30, 24, 0.5, np.pi, "dirichlet", 1e-4, "gmres_ps"),
+    (1, 99, 33, 0.5, np.pi, "dirichlet", 1e-6, "minres_abs_ps"),
+    (1, 60, 21, 1.0, np.pi, "dirichlet", 1e-2, "minres_pms"),
+    (2, 15, 16, 0.5, 1.0, "dirichlet", 1e-4, "gmres_ps"),
+    (2, 24, 20, 0.5, np.pi, "neumann", 1e-4, "gmres_ps"),
+]
+
+
+@pytest.mark.parametrize("dims,M,n,theta,zeta,bc,gamma,method", SOLVE_CASES)
+def test_general_solve_matches_oracle(env, dims, M, n, theta, zeta, bc, gamma, method):
+    torch, wc = env
+    say("general solve", dims, M, n, theta, zeta, bc, gamma, method)
+    d = datagen.config_problem(dims, M, n, seed=12, noise_sigma=1e-3, y0_zero=False)
+    pr = _problem(dims, M, n, theta, zeta, bc, gamma)
+    ref = osolver.solve(pr, d["f"], d["g"], d["y0"], method, tol=1e-8)
+    plan = wc.Plan(dims, M, n, theta=theta, gamma=gamma, zeta=zeta, method=method, tol=1e-8,
+                   bc=bc, kappa=pr.kappa)
+    f, g, y0 = dev(torch, d["f"]), dev(torch, d["g"]), dev(torch, d["y0"])
+    y = torch.empty(n * pr.m, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(y)
+    info = plan.solve(f, g, y0, y, p)
+    say("  gpu iters", info.iters, "relres", info.relres, "oracle", ref["iters"])
+    assert info.relres <= 1e-8 and abs(info.iters - ref["iters"]) <= 2
+    ref_t = osolver.solve(pr, d["f"], d["g"], d["y0"], method, tol=1e-13, maxit=400)
+    plan_t = wc.Plan(dims, M, n, theta=theta, gamma=gamma, zeta=zeta, method=method, tol=1e-13,
+                     maxit=400, bc=bc, kappa=pr.kappa)
+    plan_t.solve(f, g, y0, y, p)
+    sc = max(np.abs(ref_t["y"]).max(), np.abs(ref_t["p"]).max())
+    assert np.abs(host(y).reshape(n, -1) - ref_t["y"]).max() <= 1e-10 * sc
+    assert np.abs(host(p).reshape(n, -1) - ref_t["p"]).max() <= 1e-10 * sc
+
+
+def test_general_mixed_solve(env):
+    torch, wc = env
+    dims, M, n, theta, gamma = 2, 40, 30, 0.5, 1e-4
+    d = datagen.config_problem(dims, M, n, seed=13, noise_sigma=1e-3)
+    pr = Problem(dims=dims, M=M, n=n, theta=theta, gamma=gamma)
+    ref = osolver.solve(pr, d["f"], d["g"], d["y0"], "gmres_ps", tol=1e-12, maxit=300)
+    plan = wc.Plan(dims, M, n, theta=theta, gamma=gamma, method="gmres_ps", precision="mixed",
+                   tol=1e-8, maxit=300)
+    y = torch.empty(n * pr.m, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(y)
+    info = plan.solve(dev(torch, d["f"]), dev(torch, d["g"]), dev(torch, d["y0"]), y, p)
+    assert info.relres <= 1e-8
+    sc = max(np.abs(ref["y"]).max(), np.abs(ref["p"]).max())
+    err = max(np.abs(host(y).reshape(n, -1) - ref["y"]).max(),
+              np.abs(host(p).reshape(n, -1) - ref["p"]).max()) / sc
+    assert err < 1e-5, err
+
+
+def test_general_refusals_and_retarget(env):
+    torch, wc = env
+    with pytest.raises(wc.WcError) as ei:  # the low-rank form needs the FFT path
+        wc.Plan(2, 30, 16, lowrank=True)
+    assert ei.value.code == wc.WC_E_UNSUPPORTED
+    with pytest.raises(wc.WcError):  # batches run the FFT path only
+        wc.Batch([wc.Plan(2, 63, 64, zeta=1.0)])
+    with pytest.raises(wc.WcError) as ei:  # odd n, theta = 1/2, zeta = pi, no remedy value
+        wc.Plan(2, 20, 9, theta=0.5, s2_remedy=0.0)
+    assert ei.value.code == wc.WC_E_SINGULAR_S2
+    plan = wc.Plan(2, 63, 64, zeta=np.pi)
+    with pytest.raises(wc.WcError):  # retargeting across the two paths is refused
+        plan.retarget(zeta=1.0)
+    plan.close()
+    plan = wc.Plan(2, 30, 16, theta=0.5, zeta=1.0)
+    plan.retarget(theta=1.0, zeta=2.0, gamma=1e-2)  # within the general path
+    pr = Problem(dims=2, M=30, n=16, theta=1.0, zeta=2.0, gamma=1e-2)
+    v = datagen.random_vector(14, 2 * 16 * 900)
+    vd = dev(torch, v)
+    plan.pc_apply(vd, vd)
+    torch.cuda.synchronize()
+    assert relerr(host(vd), FastPreconditioner(pr, "ps").apply(v)) < 1e-12
