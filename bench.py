@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--rates", default="5,20,60,150", help="arrival rates (requests/s), --serve")
     ap.add_argument("--requests", type=int, default=60, help="requests per rate, --serve")
     ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
+    ap.add_argument("--next-rows", type=int, default=1,
+                    help="also time the finite element, Neumann and general-size forms")
     ap.add_argument("--batch", type=int, default=8,
                     help="instances of the small serving shape (2D, M=63, n=64) solved one by "
                          "one and as one batch (0 = skip)")
@@ -343,6 +345,79 @@ def pc_apply_bench(torch, plan, nvec, reps):
     return e0.elapsed_time(e1) / reps, stats
 
 
+FP64_VALU_PEAK_TFS = 78.6  # MI355X FP64 vector peak (256 CUs x 4 SIMDs x 2.4 GHz x 32)
+
+
+def next_rows_bench(torch, wc, dev, steps=3):
+    """The forms beyond the headline, each timed on a full solve plus its preconditioner
+    apply: finite elements (2D M = 255, n = 256), homogeneous Neumann data on Table 4's
+    finest grid (256 nodes per dimension, n = 256, a = 1e-3), and the general path
+    (2D M = 300, n = 300: neither size fits the FFT path).  The dense steps of the last two
+    are FP64 ALU work; their rate is reported against the FP64 vector peak."""
+    import datagen
+    res = {}
+
+    def run(name, plan, data, nvec, dense_flops=None, extra=None):
+        if args_autotune[0]:
+            plan.autotune(reps=2)
+        ms, infos, _ = time_solve(torch, wc, plan, data, steps, 1)
+        pc_ms, st = pc_apply_bench(torch, plan, nvec, 5)
+        r = {"ms_per_solve": round(ms, 3), "iters": infos[-1].iters,
+             "relres": max(i.relres for i in infos), "pc_apply_ms": round(pc_ms, 4)}
+        if dense_flops:
+            dense_ms = sum(v[1] for k, v in st.items() if k in ("dst_x1_fwd", "dst_x1_inv")) / 5
+            r["dense_spatial_ms"] = round(dense_ms, 4)
+            r["dense_spatial_TFLOPs"] = round(dense_flops / (dense_ms * 1e-3) / 1e12, 2)
+            r["dense_frac_of_fp64_peak"] = round(dense_flops / (dense_ms * 1e-3) / 1e12 /
+                                                 FP64_VALU_PEAK_TFS, 4)
+        if extra:
+            r.update(extra())
+        res[name] = r
+        log(f"{name}: {r}")
+        plan.close()
+
+    def tens(dd, n, m):
+        t = [torch.from_numpy(np.ascontiguousarray(dd[k])).to(dev) for k in ("f", "g", "y0")]
+        y = torch.empty(n * m, dtype=torch.float64, device=dev)
+        return (*t, y, torch.empty_like(y))
+
+    import numpy as np
+    # finite elements, 2D M = 255, n = 256
+    M, n = 255, 256
+    dd = datagen.config_problem(2, M, n, seed=3, noise_sigma=1e-3)
+    data = tens(dd, n, M * M)
+    run("fem_heat2d_M255_n256", wc.Plan(2, M, n, theta=0.5, gamma=1e-4, method="gmres_ps",
+                                        tol=1e-8, disc="fem"), data, 2 * n * M * M)
+    # Neumann data, Example 3 at h = 2^-8: 256 nodes per dimension, n = 256
+    N = 256
+    dd = datagen.example3(N, N)
+    data = tens(dd, N, N * N)
+    lines = N * N  # lines of one dense x1 pass: n slabs x N rows
+    flops = 4 * (4.0 * lines * N * N)  # four dense passes, 4 flops per complex-real term
+
+    def eh():  # the error of Section 4: max over the 2n time slices of h ||slice error||_2
+        yy = data[3].cpu().numpy().reshape(N, -1)
+        pp = data[4].cpu().numpy().reshape(N, -1)
+        ey = np.linalg.norm(yy - dd["y_exact"][1:], axis=1).max()
+        ep = np.linalg.norm(pp - dd["p_exact"][:-1], axis=1).max()
+        return {"e_h": float(max(ey, ep) / (N - 1)), "e_h_printed": 5.10e-9}
+    run("neumann_example3_N256_n256", wc.Plan(2, N, N, theta=0.5, gamma=1e-4, method="gmres_ps",
+                                              tol=1e-8, bc="neumann", kappa=1e-3),
+        data, 2 * N * N * N, flops, eh)
+    # general path, 2D M = 300, n = 300
+    M, n = 300, 300
+    dd = datagen.config_problem(2, M, n, seed=4, noise_sigma=1e-3)
+    data = tens(dd, n, M * M)
+    flops = 4 * (4.0 * 2 * n * M * M * M)  # 2n slabs of M lines
+    run("general_heat2d_M300_n300", wc.Plan(2, M, n, theta=0.5, gamma=1e-4, method="gmres_ps",
+                                            tol=1e-8), data, 2 * n * M * M, flops)
+    torch.cuda.empty_cache()
+    return res
+
+
+args_autotune = [1]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -470,6 +545,8 @@ def main():
         torch.cuda.empty_cache()
 
     batch = batch_bench(args) if args.batch > 0 else None
+    args_autotune[0] = args.autotune
+    nxt = next_rows_bench(torch, wc, dev) if args.next_rows else None
     served = None
     if args.serve_inline:
         served = serve(args, rates=[10.0, 40.0], requests=30, quiet=True)
@@ -540,6 +617,7 @@ def main():
                   "rates": served["rates"], "population": served["population"],
                   "concurrency": served["concurrency"]} if served else None,
         "batch": batch,
+        "next_rows": nxt,
         "kernels": kernels,
         "copy": {"bytes": copy_bytes, "ms": round(copy_ms, 4),
                  "GBps": round(copy_bytes / (copy_ms * 1e-3) / 1e9, 1)},
