@@ -247,7 +247,10 @@ hipError_t run_captured(wc_plan *p, int slot, const void *key, F body) {
     p->gexec[slot] = nullptr;
   }
   if (!p->gexec[slot]) {
-    if (!p->cap_stream && hipStreamCreate(&p->cap_stream) != hipSuccess) {
+    // non-blocking: work that other threads put on the legacy stream must not take an
+    // implicit dependency on a stream while it captures (an error under capture)
+    if (!p->cap_stream &&
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
       p->graphs_failed = true;
       return body();
