@@ -24,6 +24,10 @@ Also measured in the same run (extra keys of the same line):
   * the low-rank form of the GMRES proposition (same iterates, compact basis);
   * the 2D M = 255, n = 256 workload in both forms;
   * a short serving pass (Poisson arrivals of mixed sizes, p50/p99 latency);
+  * batches: 8 instances solved in lockstep against one solve after another;
+  * next_rows: finite elements (M = 255, n = 256), Neumann data on Table 4's finest
+    grid (with its e_h beside the printed value) and a general-size problem
+    (M = 300, n = 300), each a timed solve plus its preconditioner apply;
   * cpu_baseline: the CPU oracle on a bounded sample of the same workload
     (setup, right-hand side, one Krylov iteration and recovery on the full-size
     problem, the iteration scaled to the GPU's iteration count).
