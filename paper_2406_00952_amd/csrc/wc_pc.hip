@@ -1976,6 +1976,103 @@ __global__ __launch_bounds__(256) void k_dense_apply(const cx<P> *__restrict__ X
     }
 }
 
+// FP64 form of k_dense_apply on the matrix cores: the real and imaginary parts of X are
+// two real products with the same matrix, each built from 16 x 16 x 4 FP64 MFMA steps.
+// Operand layout of that instruction (checked on the device): lane l supplies
+// A[l % 16][l / 16] of the 16 x 4 left operand and B[l / 16][l % 16] of the 4 x 16 right
+// one, and holds D[4 i + l / 16][l % 16], i < 4, of the 16 x 16 result.  Each of the 4
+// waves owns a 32 x 32 quarter of the 64 x 64 tile.  COLS: D = A X (rows j, columns c:
+// consecutive lanes store consecutive columns of a slab row); ROWS: D = X^T A^T (rows c,
+// columns j: consecutive lanes store consecutive entries of a line).
+typedef double dx4 __attribute__((ext_vector_type(4)));
+template <bool ROWS, int KC = 32>
+__global__ __launch_bounds__(256) void k_dense_mfma(const cx<double> *__restrict__ X,
+                                                    cx<double> *__restrict__ Y,
+                                                    const double *__restrict__ A, int N, int C) {
+  constexpr int PER = KC * kDenseT / 256;  // staged elements per thread and chunk
+  __shared__ double As[KC][kDenseT + 1];
+  __shared__ cx<double> Xs[KC][kDenseT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wj = (wv & 1) * 32, wc = (wv >> 1) * 32;  // the wave's quarter of the tile
+  const int lr = lane % 16, lk = lane / 16;
+  const int j0 = blockIdx.y * kDenseT, c0 = blockIdx.x * kDenseT;
+  const size_t slab = ROWS ? 0 : (size_t)blockIdx.z * N * N;
+  const cx<double> *Xb = X + slab;
+  cx<double> *Yb = Y + slab;
+  dx4 re[2][2], im[2][2];  // [j block][c block]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = dx4{0.0, 0.0, 0.0, 0.0};
+  // chunk k0 of both operands into registers (A rows are contiguous in k; X along its
+  // contiguous index); the next chunk's loads are issued before the current one's products
+  double ra[PER];
+  cx<double> rx[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e % KC, jj = e / KC, j = j0 + jj, k = k0 + kk;
+      ra[u] = (j < N && k < N) ? A[(size_t)j * N + k] : 0.0;
+      const int xk = ROWS ? e % KC : e / kDenseT, xc = ROWS ? e / KC : e % kDenseT;
+      const int k2 = k0 + xk, c = c0 + xc;
+      rx[u] = cx<double>{0.0, 0.0};
+      if (k2 < N && c < C) rx[u] = ROWS ? Xb[(size_t)c * N + k2] : Xb[(size_t)k2 * N + c];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < N; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      As[e % KC][e / KC] = ra[u];
+      const int xk = ROWS ? e % KC : e / kDenseT, xc = ROWS ? e / KC : e % kDenseT;
+      Xs[xk][xc] = rx[u];
+    }
+    __syncthreads();
+    if (k0 + KC < N) load(k0 + KC);
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int kr = ks + lk;
+      double am[2];
+      cx<double> xv[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        am[b] = As[kr][wj + 16 * b + lr];
+        xv[b] = Xs[kr][wc + 16 * b + lr];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (ROWS) {  // left operand X^T (row c, column k), right A^T (row k, column j)
+            re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[b].x, am[a], re[a][b], 0, 0, 0);
+            im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[b].y, am[a], im[a][b], 0, 0, 0);
+          } else {     // left operand A (row j, column k), right X (row k, column c)
+            re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a], xv[b].x, re[a][b], 0, 0, 0);
+            im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a], xv[b].y, im[a][b], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // result row 4 i + lk, column lr of the (a, b) block
+        const int j = ROWS ? j0 + wj + 16 * a + lr : j0 + wj + 16 * a + 4 * i + lk;
+        const int c = ROWS ? c0 + wc + 16 * b + 4 * i + lk : c0 + wc + 16 * b + lr;
+        if (j < N && c < C) {
+          const cx<double> v{re[a][b][i], im[a][b][i]};
+          if (ROWS) Yb[(size_t)c * N + j] = v;
+          else Yb[(size_t)j * N + c] = v;
+        }
+      }
+}
+
 // ---- general path: sizes or zeta outside the FFT path ------------------------------
 // Time step as a dense product over all n frequencies, both block rows (blockIdx.z = h):
 // FWD  G[h][l][s] = sum_k Phi[l][k] v[h][k][s]       (v real FP64, G complex P)
@@ -2044,6 +2141,93 @@ __global__ __launch_bounds__(256) void k_dense_time(const void *__restrict__ Xv,
     }
 }
 
+// FP64 form of k_dense_time on the matrix cores (operand layout as in k_dense_mfma):
+// FWD: Re G and Im G are Re Phi v and Im Phi v; !FWD: w = Re Phiinv Re G - Im Phiinv Im G.
+// Rows of the 64 x 64 tile are frequencies l (FWD) or time levels k (!FWD), columns are
+// spatial points s, so consecutive lanes store consecutive s.
+template <bool FWD, int KC = 32>
+__global__ __launch_bounds__(256) void k_dense_time_mfma(const void *__restrict__ Xv,
+                                                         void *__restrict__ Yv,
+                                                         const cx<double> *__restrict__ A, int n,
+                                                         int m) {
+  using XT = typename std::conditional<FWD, double, cx<double>>::type;
+  constexpr int PER = KC * kDenseT / 256;  // staged elements per thread and chunk
+  __shared__ cx<double> As[KC][kDenseT + 1];
+  __shared__ XT Xs[KC][kDenseT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wj = (wv & 1) * 32, wc = (wv >> 1) * 32;
+  const int lr = lane % 16, lk = lane / 16;
+  const int j0 = blockIdx.y * kDenseT, c0 = blockIdx.x * kDenseT;
+  const XT *X = (const XT *)Xv + (size_t)blockIdx.z * n * m;
+  dx4 re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = dx4{0.0, 0.0, 0.0, 0.0};
+  // chunk k0 into registers (A rows contiguous in k, X rows contiguous in s); the next
+  // chunk's loads are issued before the current one's products
+  cx<double> ra[PER];
+  XT rx[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e % KC, jj = e / KC, j = j0 + jj, k = k0 + kk;
+      ra[u] = (j < n && k < n) ? A[(size_t)j * n + k] : cx<double>{0.0, 0.0};
+      const int xk = e / kDenseT, xc = e % kDenseT, k2 = k0 + xk, c = c0 + xc;
+      rx[u] = (k2 < n && c < m) ? X[(size_t)k2 * m + c] : XT{};
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < n; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u;
+      As[e % KC][e / KC] = ra[u];
+      Xs[e / kDenseT][e % kDenseT] = rx[u];
+    }
+    __syncthreads();
+    if (k0 + KC < n) load(k0 + KC);
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int kr = ks + lk;
+      cx<double> am[2];
+      XT xv[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        am[b] = As[kr][wj + 16 * b + lr];
+        xv[b] = Xs[kr][wc + 16 * b + lr];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if constexpr (FWD) {
+            re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a].x, xv[b], re[a][b], 0, 0, 0);
+            im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a].y, xv[b], im[a][b], 0, 0, 0);
+          } else {
+            re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[a].x, xv[b].x, re[a][b], 0, 0, 0);
+            re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-am[a].y, xv[b].y, re[a][b], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = j0 + wj + 16 * a + 4 * i + lk, c = c0 + wc + 16 * b + lr;
+        if (j < n && c < m) {
+          const size_t o = (size_t)blockIdx.z * n * m + (size_t)j * m + c;
+          if constexpr (FWD) ((cx<double> *)Yv)[o] = cx<double>{re[a][b][i], im[a][b][i]};
+          else ((double *)Yv)[o] = re[a][b][i];
+        }
+      }
+}
+
 // step 2 of the general path: the per-mode operation of frequency l and mode s couples
 // G[0][l][s] and G[1][l][s] (lambda_l of the full table; the dense steps are normalised)
 template <typename P>
@@ -2075,16 +2259,25 @@ hipError_t dense_space(const wc_plan &p, cx<P> *A, cx<P> *B, int nslab, Op op) {
   const dim3 grows((lines + kDenseT - 1) / kDenseT, gj), gcols(gj, gj, nslab);
   const double bytes = 2.0 * nslab * (double)p.m * sizeof(cx<P>);
   hipError_t e;
+  // FP64 on the matrix cores, FP32 on the vector ALUs
   auto rows = [&](const cx<P> *in, cx<P> *out, const P *mat, int id) {
     ProfScope ps(p, id, bytes);
-    hipLaunchKernelGGL((k_dense_apply<P, true>), grows, dim3(256), 0, p.stream, in, out, mat, M,
-                       lines);
+    if constexpr (std::is_same<P, double>::value)
+      hipLaunchKernelGGL((k_dense_mfma<true>), grows, dim3(256), 0, p.stream, in, out, mat, M,
+                         lines);
+    else
+      hipLaunchKernelGGL((k_dense_apply<P, true>), grows, dim3(256), 0, p.stream, in, out, mat, M,
+                         lines);
     return hipGetLastError();
   };
   auto cols = [&](const cx<P> *in, cx<P> *out, const P *mat, int id) {
     ProfScope ps(p, id, bytes);
-    hipLaunchKernelGGL((k_dense_apply<P, false>), gcols, dim3(256), 0, p.stream, in, out, mat, M,
-                       M);
+    if constexpr (std::is_same<P, double>::value)
+      hipLaunchKernelGGL((k_dense_mfma<false>), gcols, dim3(256), 0, p.stream, in, out, mat, M,
+                         M);
+    else
+      hipLaunchKernelGGL((k_dense_apply<P, false>), gcols, dim3(256), 0, p.stream, in, out, mat,
+                         M, M);
     return hipGetLastError();
   };
   if ((e = rows(A, B, Ci, K_DST_X1_FWD)) != hipSuccess) return e;
@@ -2111,8 +2304,12 @@ hipError_t pc_apply_general(const wc_plan &p, const double *v, double *w, const 
   hipError_t e;
   {
     ProfScope ps(p, K_TFFT_FWD, vbytes + gbytes);
-    hipLaunchKernelGGL((k_dense_time<P, true>), gt, dim3(256), 0, p.stream, (const void *)v,
-                       (void *)G, Tabs<P>::phi(p), n, m);
+    if constexpr (std::is_same<P, double>::value)
+      hipLaunchKernelGGL((k_dense_time_mfma<true>), gt, dim3(256), 0, p.stream, (const void *)v,
+                         (void *)G, Tabs<P>::phi(p), n, m);
+    else
+      hipLaunchKernelGGL((k_dense_time<P, true>), gt, dim3(256), 0, p.stream, (const void *)v,
+                         (void *)G, Tabs<P>::phi(p), n, m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
@@ -2127,8 +2324,12 @@ hipError_t pc_apply_general(const wc_plan &p, const double *v, double *w, const 
   if (e != hipSuccess) return e;
   {
     ProfScope ps(p, K_TFFT_INV, vbytes + gbytes);
-    hipLaunchKernelGGL((k_dense_time<P, false>), gt, dim3(256), 0, p.stream, (const void *)G,
-                       (void *)w, Tabs<P>::phi(p) + (size_t)n * n, n, m);
+    if constexpr (std::is_same<P, double>::value)
+      hipLaunchKernelGGL((k_dense_time_mfma<false>), gt, dim3(256), 0, p.stream,
+                         (const void *)G, (void *)w, Tabs<P>::phi(p) + (size_t)n * n, n, m);
+    else
+      hipLaunchKernelGGL((k_dense_time<P, false>), gt, dim3(256), 0, p.stream, (const void *)G,
+                         (void *)w, Tabs<P>::phi(p) + (size_t)n * n, n, m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   *nparts = 0;
