@@ -168,12 +168,14 @@ wc_status wc_plan_create(const wc_problem *prob, const wc_opts *opts, void *stre
                          wc_plan **out);
 wc_status wc_plan_destroy(wc_plan *plan);
 /* Re-point a plan at another problem of the same shape without allocating: same
- * dims, M, n, method, precision, restart, flexible and lowrank, and a_face_host given iff
- * it was at creation (WC_E_ARG otherwise).  theta, gamma, T, zeta, s2_remedy,
- * the coefficient values and the remaining options may change; every table is
- * rebuilt.  Synchronises the plan's stream first.  On an error other than
- * WC_E_ARG the plan refuses solves until a retarget succeeds. */
+ * dims, M, n, method, precision, restart, flexible, lowrank, disc and bc, a_face_host
+ * given iff it was at creation, and the same preconditioner path (the FFT path or the
+ * general path) (WC_E_ARG otherwise).  theta, gamma, T, zeta, s2_remedy, kappa, the
+ * coefficient values and the remaining options may change; every table is rebuilt.
+ * Synchronises the plan's stream first.  On an error other than WC_E_ARG the plan
+ * refuses solves until a retarget succeeds. */
 wc_status wc_plan_retarget(wc_plan *plan, const wc_problem *prob, const wc_opts *opts);
+/* Later calls of the plan run on stream; the old stream is synchronised first. */
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
 /* Times the preconditioner apply (reps applies per candidate, after one warm-up)
  * for every time-pass choice and, in 2D with a = 1, every x2-pass choice (the values
@@ -206,7 +208,14 @@ wc_status wc_matvec(wc_plan *plan, const double *x, double *y);
 /* w = P^{-1} v for the plan's preconditioner (|P_S|, P_MS or P_S) by the
  * three-step procedure of Section 3.4: omega-scaled time FFT, independent
  * spatial problems per frequency, inverse transform.  v, w: 2*n*m doubles,
- * may alias.  Arithmetic in FP64 or FP32 per opts.precision. */
+ * may alias.  Arithmetic in FP64 or FP32 per opts.precision.
+ * Paths: zeta == pi with n and M+1 powers of two in [4, 1024] (Dirichlet; Neumann: n a
+ * power of two, any M) run the FFT path (half spectrum, sine transforms, multigrid for
+ * variable a).  Other n <= 1024, M <= 1024 or zeta with constant-coefficient finite
+ * differences run the general path: the time step as a dense product over all n
+ * frequencies, dense spatial steps, and the real part of P^{-1} v (for zeta not in
+ * {0, pi} P_S is complex; the real part is the preconditioner of the real system).
+ * Variable a and finite elements need the FFT path (WC_E_UNSUPPORTED otherwise). */
 wc_status wc_pc_apply(wc_plan *plan, const double *v, double *w);
 
 /* Recover y (levels 1..n), p (levels 0..n-1), each n*m doubles, from

@@ -1188,6 +1188,8 @@ wc_status wc_plan_set_tiles(wc_plan *p, int ts, int tx) {
 
 wc_status wc_plan_set_stream(wc_plan *plan, void *stream) {
   if (!plan) return WC_E_ARG;
+  // the plan's work so far is ordered on the old stream: finish it before switching
+  if (hipStreamSynchronize(plan->stream) != hipSuccess) return WC_E_HIP;
   plan->stream = (hipStream_t)stream;
   return WC_OK;
 }

@@ -404,7 +404,11 @@ class Server:
                tol=1e-8, maxit=500, restart=30, flexible=False, mg_max_cycles=30,
                mg_tol=1e-10, graphs=True, lowrank=False, disc="fd", bc="dirichlet",
                kappa=1.0) -> int:
-        """Queue one solve; the tensors must stay alive and untouched until it is done."""
+        """Queue one solve; the tensors must stay alive and untouched until it is done.
+        The server's workers run on their own streams, so the caller's current stream is
+        synchronised first: the inputs are complete when the request is queued."""
+        import torch
+        torch.cuda.current_stream().synchronize()
         pr, keep = _problem(dims, M, n, T, theta, gamma, zeta, s2_remedy, a_face, disc, bc,
                             kappa)
         op = _opts(method, precision, tol, maxit, restart, flexible, mg_max_cycles, mg_tol, graphs,
