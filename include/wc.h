@@ -185,8 +185,9 @@ wc_status wc_plan_set_stream(wc_plan *plan, void *stream);
 wc_status wc_plan_autotune(wc_plan *plan, int reps, int *ts, int *tx);
 /* Sets the preconditioner's kernel choices directly (e.g. to reuse a choice autotuned on
  * another plan): ts for the time passes (4, 8, 16: tiles of that many spatial columns
- * with both block rows packed in one complex sequence; -8, -16: tiles of 8 or 16 columns
- * of one block row, each transformed as an n/2-point sequence, n >= 64), tx for the
+ * with both block rows packed in one complex sequence; -8, -16, -32: tiles of 8, 16 or 32
+ * columns of one block row, each transformed as an n/2-point sequence, n >= 64; -32 runs
+ * as -16 where its tile exceeds the CU's LDS, FP64 at n = 1024), tx for the
  * 2D x2 pass (4, 8, 16: tiles of that many x1 columns; -4, -8: x1 passes that write a
  * transposed copy in tiles of 4 or 8 rows and an x2 pass on its contiguous rows, M+1 >=
  * 128); 0 = default.  WC_E_ARG for other values.  Synchronises the plan's stream. */

@@ -1136,9 +1136,9 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
   WC_TRY(launch_fill(*p, v, 1.0, p->nvec));
   // time-FFT tile widths; x2 pass: column tiles of 4, 8, 16, or the transposed rows in
   // x1 tiles of 4 or 8 rows (tx < 0, when the plan holds the transposed copy)
-  // time passes: packed tiles of 4, 8, 16 columns, or per-block-row tiles of 8, 16 (< 0)
-  const int tss[5] = {4, 8, 16, -8, -16}, txs[5] = {4, 8, 16, -4, -8};
-  const int nts = p->general ? 1 : (p->n >= 64 ? 5 : 3);
+  // time passes: packed tiles of 4, 8, 16 columns, or per-block-row tiles of 8, 16, 32 (< 0)
+  const int tss[6] = {4, 8, 16, -8, -16, -32}, txs[5] = {4, 8, 16, -4, -8};
+  const int nts = p->general ? 1 : (p->n >= 64 ? 6 : 3);
   // (finite elements: no sine passes in the preconditioner, only the time tiles matter)
   const int ntx = (p->dims == 2 && !p->var_coeff && !p->fem && !p->neumann) ? (p->d_specT ? 5 : 3) : 1;
   float best = -1.f;
@@ -1175,7 +1175,8 @@ wc_status wc_plan_autotune(wc_plan *p, int reps, int *ts_out, int *tx_out) {
 
 wc_status wc_plan_set_tiles(wc_plan *p, int ts, int tx) {
   if (!p) return WC_E_ARG;
-  const bool ts_ok = ts == 0 || ts == 4 || ts == 8 || ts == 16 || ts == -8 || ts == -16;
+  const bool ts_ok =
+      ts == 0 || ts == 4 || ts == 8 || ts == 16 || ts == -8 || ts == -16 || ts == -32;
   const bool tx_ok = tx == 0 || tx == 4 || tx == 8 || tx == 16 ||
                      ((tx == -4 || tx == -8) && p->d_specT);
   if (!ts_ok || !tx_ok) return WC_E_ARG;

@@ -1630,7 +1630,14 @@ hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *npa
 
 // time-pass choice: ts_time > 0 the packed one-sequence kernels with that tile width, < 0
 // the per-block-row kernels (n >= 64) with tile width -ts_time; 0 the default
+// per-block-row tiles: 16 columns where two workgroups fit per CU, else 8; FP32 32
+// columns where two still fit (measured at n = 512: 0.73 ms per pass against 0.9 ms at 16;
+// in FP64 a 32-column tile leaves one workgroup per CU and is slower, 1.17 against 0.96 ms)
+template <typename P, int N> constexpr bool fits_ts_h(int ts) {
+  return ts == 32 ? TimeCfgH<P, N, 32>::TILE <= kCuLds : true;
+}
 template <typename P, int N> constexpr int default_ts_h() {
+  if (std::is_same<P, float>::value && blocks_per_cu(TimeCfgH<P, N, 32>::TILE) >= 2) return 32;
   return blocks_per_cu(TimeCfgH<P, N, 16>::TILE) >= 2 ? 16 : 8;
 }
 template <typename P, int N> int time_choice(const wc_plan &p) {
@@ -1665,8 +1672,11 @@ hipError_t run_tfft_fwd(const wc_plan &p, const double *v, const GenIn *gen,
                         cx<P> *out = nullptr) {
   if constexpr (N >= 64) {
     const int tc = time_choice<P, N>(p);
-    if (tc < 0 && !gen && !out)
+    if (tc < 0 && !gen && !out) {
+      if constexpr (fits_ts_h<P, N>(32))
+        if (tc == -32) return tfft_fwd_h<P, N, 32>(p, v);
       return tc == -8 ? tfft_fwd_h<P, N, 8>(p, v) : tfft_fwd_h<P, N, 16>(p, v);
+    }
   }
   if (!out) out = (cx<P> *)p.d_specA;
   switch (p.ts_time > 0 ? p.ts_time : default_ts<P, N>()) {
@@ -1680,9 +1690,12 @@ template <typename P, int N>
 hipError_t run_tfft_inv(const wc_plan &p, double *w, const double *dotv, int *nparts) {
   if constexpr (N >= 64) {
     const int tc = time_choice<P, N>(p);
-    if (tc < 0)
+    if (tc < 0) {
+      if constexpr (fits_ts_h<P, N>(32))
+        if (tc == -32) return tfft_inv_h<P, N, 32>(p, w, dotv, nparts);
       return tc == -8 ? tfft_inv_h<P, N, 8>(p, w, dotv, nparts)
                       : tfft_inv_h<P, N, 16>(p, w, dotv, nparts);
+    }
   }
   switch (p.ts_time > 0 ? p.ts_time : default_ts<P, N>()) {
     case 4: return tfft_inv_ts<P, N, 4>(p, w, dotv, nparts);
