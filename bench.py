@@ -25,6 +25,8 @@ Also measured in the same run (extra keys of the same line):
   * the 2D M = 255, n = 256 workload in both forms;
   * a short serving pass (Poisson arrivals of mixed sizes, p50/p99 latency);
   * batches: 8 instances solved in lockstep against one solve after another;
+  * zeta_sweep: the workload with omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001} (the
+    dense general path), one FP64 solve each;
   * next_rows: finite elements (M = 255, n = 256), Neumann data on Table 4's finest
     grid (with its e_h beside the printed value) and a general-size problem
     (M = 300, n = 300), each a timed solve plus its preconditioner apply;
@@ -93,6 +95,8 @@ def parse():
     ap.add_argument("--rates", default="5,20,60,150", help="arrival rates (requests/s), --serve")
     ap.add_argument("--requests", type=int, default=60, help="requests per rate, --serve")
     ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
+    ap.add_argument("--zeta-sweep", type=int, default=1,
+                    help="also solve the workload with zeta in {0.1, 0.01, 0.001} (general path)")
     ap.add_argument("--next-rows", type=int, default=1,
                     help="also time the finite element, Neumann and general-size forms")
     ap.add_argument("--batch", type=int, default=8,
@@ -419,6 +423,24 @@ def next_rows_bench(torch, wc, dev, steps=3):
     return res
 
 
+def zeta_sweep_bench(torch, wc, data, common, M, n):
+    """The mixed-precision workload's omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001}, on the
+    same 2D M = 511, n = 512 problem: the general path (zeta != pi: dense time transform
+    over all n frequencies, dense sine steps on the FP64 matrix cores), one FP64 solve
+    each."""
+    res = {}
+    for zeta in (0.1, 0.01, 0.001):
+        plan = wc.Plan(2, M, n, precision="fp64", flexible=True, zeta=zeta,
+                       **dict(common, maxit=200))
+        ms, infos, _ = time_solve(torch, wc, plan, data, 1, 0)
+        res[str(zeta)] = {"ms_per_solve": round(ms, 1), "iters": infos[-1].iters,
+                          "relres": infos[-1].relres}
+        log(f"zeta {zeta}: {res[str(zeta)]}")
+        plan.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 args_autotune = [1]
 
 
@@ -551,6 +573,9 @@ def main():
     batch = batch_bench(args) if args.batch > 0 else None
     args_autotune[0] = args.autotune
     nxt = next_rows_bench(torch, wc, dev) if args.next_rows else None
+    zsweep = (zeta_sweep_bench(torch, wc, data, common, args.M, n)
+              if args.zeta_sweep and (args.dims, args.M, n, args.coeff) == (2, 511, 512, "const")
+              else None)
     served = None
     if args.serve_inline:
         served = serve(args, rates=[10.0, 40.0], requests=30, quiet=True)
@@ -622,6 +647,7 @@ def main():
                   "concurrency": served["concurrency"]} if served else None,
         "batch": batch,
         "next_rows": nxt,
+        "zeta_sweep": zsweep,
         "kernels": kernels,
         "copy": {"bytes": copy_bytes, "ms": round(copy_ms, 4),
                  "GBps": round(copy_bytes / (copy_ms * 1e-3) / 1e9, 1)},
