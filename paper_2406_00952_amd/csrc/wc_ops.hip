@@ -134,13 +134,7 @@ struct MvArgs {
 // DG (diagonal operator) and SUB (subtracted vector) are template arguments: a run-time
 // branch around the loads splits the batch, and every batch then waits for its loads one
 // branch at a time.
-#ifndef WC_MV_PTS
-#define WC_MV_PTS 2
-#endif
-#ifndef WC_MV_KB
-#define WC_MV_KB 4
-#endif
-constexpr int kMvPts = WC_MV_PTS, kMvKb = WC_MV_KB;
+constexpr int kMvPts = 2, kMvKb = 4;
 template <bool DG, bool SUB>
 __global__ __launch_bounds__(kThreads) void k_matvec(const double *__restrict__ x,
                                                      double *__restrict__ y,

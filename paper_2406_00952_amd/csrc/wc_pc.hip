@@ -491,27 +491,26 @@ __device__ __forceinline__ void mode_op(cx<P> &a, cx<P> &b, cx<P> l, P musum, in
   }
 }
 
-// The same operation, only the block row h of the result (the x2 row pass: each wave keeps
-// its own block row).
-template <typename P>
-__device__ __forceinline__ cx<P> mode_op_row(cx<P> a, cx<P> b, int h, cx<P> l, P musum, int kind,
-                                             P tau, P alpha, P cnorm) {
-  if (kind == 0) {
+// The same per-mode operation with the method and the block row fixed at compile time, as
+// the x2 row pass uses it: own is this row's mode, other the partner row's (read for P_S
+// only; the other two preconditioners scale each row by itself).
+template <typename P, int KIND, int H>
+__device__ __forceinline__ cx<P> mode_op_fixed(cx<P> own, cx<P> other, cx<P> l, P musum, P tau,
+                                               P alpha, P cnorm) {
+  if constexpr (KIND == 0) {
     const cx<P> Lm = {l.x + tau * musum, l.y};
     const P c = cnorm / (Lm.x * Lm.x + Lm.y * Lm.y + alpha * alpha);
-    if (h == 0)  // (conj(L) a + alpha b) c
-      return cscale(cx<P>{Lm.x * a.x + Lm.y * a.y + alpha * b.x, Lm.x * a.y - Lm.y * a.x + alpha * b.y}, c);
-    const cx<P> lb = cmul(Lm, b);  // (L b - alpha a) c
-    return cscale(cx<P>{lb.x - alpha * a.x, lb.y - alpha * a.y}, c);
-  }
-  P s;
-  if (kind == 1) {
+    if constexpr (H == 0)  // (conj(L) a + alpha b) c with a = own, b = other
+      return cscale(cx<P>{Lm.x * own.x + Lm.y * own.y + alpha * other.x,
+                          Lm.x * own.y - Lm.y * own.x + alpha * other.y}, c);
+    const cx<P> lb = cmul(Lm, own);  // (L b - alpha a) c with b = own, a = other
+    return cscale(cx<P>{lb.x - alpha * other.x, lb.y - alpha * other.y}, c);
+  } else if constexpr (KIND == 1) {
     const P re = l.x + tau * musum;
-    s = cnorm / sqrt(re * re + l.y * l.y + alpha * alpha);
+    return cscale(own, cnorm / sqrt(re * re + l.y * l.y + alpha * alpha));
   } else {
-    s = cnorm / (sqrt(l.x * l.x + l.y * l.y + alpha * alpha) + tau * musum);
+    return cscale(own, cnorm / (sqrt(l.x * l.x + l.y * l.y + alpha * alpha) + tau * musum));
   }
-  return cscale(h ? b : a, s);
 }
 
 // ---- step 1a: time transform of both block rows ------------------------------
@@ -698,7 +697,13 @@ __global__ __launch_bounds__((TimeCfg<P, N, TS, kTimeWavesInv>::NT)) void k_tfft
 // transformed on its own, so a tile of TS columns holds n/2 complex values per column: half
 // the LDS of the packed form at the same tile width, or twice the width (the real input
 // rows read TS * 8 bytes at a time) at the same LDS.
-template <typename P, int N, int TS, int WV = 4> struct TimeCfgH {
+// Waves per workgroup: 8 for the inverse transform and for FP32, 4 for the FP64 forward
+// transform (measured at M = 511, n = 512: the FP64 inverse 5% faster with 8, the FP64
+// forward 1% slower; FP32 with 32-column tiles 6% and 3% faster with 8).
+template <typename P, bool INV> constexpr int time_waves_h() {
+  return INV || sizeof(P) == 4 ? 8 : 4;
+}
+template <typename P, int N, int TS, int WV> struct TimeCfgH {
   static constexpr int N2 = N / 2;
   static constexpr int WAVES = TS < WV ? TS : WV;
   static constexpr int NT = 64 * WAVES;
@@ -710,10 +715,10 @@ template <typename P, int N, int TS, int WV = 4> struct TimeCfgH {
 };
 
 template <typename P, int N, int TS>
-__global__ __launch_bounds__((TimeCfgH<P, N, TS>::NT)) void k_tfft_fwd_h(
+__global__ __launch_bounds__((TimeCfgH<P, N, TS, time_waves_h<P, false>()>::NT)) void k_tfft_fwd_h(
     const double *__restrict__ v, cx<P> *__restrict__ W, const cx<double> *__restrict__ dtw,
     const cx<double> *__restrict__ twt, int m, int ntile) {
-  using C = TimeCfgH<P, N, TS>;
+  using C = TimeCfgH<P, N, TS, time_waves_h<P, false>()>;
   constexpr int N2 = C::N2, S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
   constexpr int LIT = (N2 * TS + NT - 1) / NT;
   __shared__ cx<P> buf[C::PN * S];
@@ -764,11 +769,11 @@ __global__ __launch_bounds__((TimeCfgH<P, N, TS>::NT)) void k_tfft_fwd_h(
 }
 
 template <typename P, int N, int TS>
-__global__ __launch_bounds__((TimeCfgH<P, N, TS>::NT)) void k_tfft_inv_h(
+__global__ __launch_bounds__((TimeCfgH<P, N, TS, time_waves_h<P, true>()>::NT)) void k_tfft_inv_h(
     const cx<P> *__restrict__ W, double *__restrict__ out, const cx<double> *__restrict__ dtw,
     const cx<double> *__restrict__ twt, int m, int ntile, const double *__restrict__ dotv,
     double *__restrict__ partials) {
-  using C = TimeCfgH<P, N, TS>;
+  using C = TimeCfgH<P, N, TS, time_waves_h<P, true>()>;
   constexpr int N2 = C::N2, S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
   constexpr int HT = (N2 / 2) * TS, LIT = (HT + NT - 1) / NT;
   __shared__ cx<P> buf[C::PN * S];
@@ -1011,9 +1016,12 @@ __global__ __launch_bounds__(kThreads) void k_pair_rows(cx<P> *__restrict__ W, i
 // (one LDS line per wave), and the inverse x1 pass reads T and writes [q][h][x2][x1] rows
 // again.  The x1 passes use tiles of R consecutive rows (one per wave), so the transposed
 // accesses move R consecutive elements at a time.
-template <typename P, int N1, int R> struct TrCfg {
+// Pad spacing of the LDS lines: every 8 elements in the forward pass, every 32 in the
+// inverse pass (measured at N1 = 512: the inverse pass 5% faster in FP64 and 13% in FP32
+// than with 8; the forward pass 8% slower in FP32 with 32).
+template <typename P, int N1, int R, bool INV = false> struct TrCfg {
   static constexpr int CXB = 2 * (int)sizeof(P);
-  static constexpr int PS = 3;
+  static constexpr int PS = INV ? 5 : 3;
   static constexpr int PN = padded<PS>(N1);
   static constexpr int NT = 64 * R;
   static constexpr int TAB = N1 * CXB + N1 * (int)sizeof(P);
@@ -1031,6 +1039,10 @@ template <typename P, int N1> struct PairCfg {
   // the pass holds about 160 VGPRs per lane in FP64 at N1 = 512 (three waves per SIMD,
   // three workgroups per CU), so the tables go to LDS whenever three workgroups still fit
   static constexpr bool TAB_LDS = 3 * (BUF + TAB) <= kCuLds;
+  // FP64 at N1 = 512: the P_S form is held to three waves per SIMD (168 VGPRs; left to the
+  // compiler it takes 184 and two waves, measured 1416 us against 1268 us at M = 511,
+  // n = 512); elsewhere the compiler's choice
+  static constexpr int WAVES_PER_SIMD = sizeof(P) == 8 && N1 == 512 ? 3 : 1;
 };
 
 template <typename P, int N1, bool TWL>
@@ -1084,7 +1096,7 @@ __global__ __launch_bounds__(64 * R) void k_rows_inv_t(const cx<P> *__restrict__
                                                        cx<P> *__restrict__ A,
                                                        const cx<P> *__restrict__ twg,
                                                        const P *__restrict__ sing) {
-  using C = TrCfg<P, N1, R>;
+  using C = TrCfg<P, N1, R, true>;
   constexpr int M = N1 - 1, PS = C::PS, PN = C::PN, NT = C::NT, NRB = (M + R - 1) / R;
   constexpr int LIT = (M * R + NT - 1) / NT;
   __shared__ cx<P> lds[R * PN];
@@ -1118,13 +1130,16 @@ __global__ __launch_bounds__(64 * R) void k_rows_inv_t(const cx<P> *__restrict__
 
 // x2 sine transform, step 2 and inverse x2 sine transform on T, in place.  A (q, j1) unit
 // is two waves, one per block row, each transforming its line with the result in
-// registers; the per-mode operation couples the two through their LDS lines (each wave
-// publishes its modes in natural order, reads its partner's, keeps its own block row of
-// the 2x2 result), then each wave runs the inverse transform on its own line.
-template <typename P, int N1>
-__global__ __launch_bounds__(64 * kPairWaves) void k_pair_cols_t(
+// registers; for P_S (KIND 0) the per-mode operation couples the two through their LDS
+// lines (each wave publishes its modes in natural order, reads its partner's, keeps its
+// own block row of the 2x2 result), |P_S| (1) and P_MS (2) scale each row by itself; then
+// each wave runs the inverse transform on its own line.  The method is a template
+// argument and the block row a scalar, so neither costs per-lane selects.
+template <typename P, int N1, int KIND>
+__global__ __launch_bounds__(64 * kPairWaves) __attribute__((
+    amdgpu_waves_per_eu(PairCfg<P, N1>::WAVES_PER_SIMD))) void k_pair_cols_t(
     cx<P> *__restrict__ T, int nunits, const cx<P> *__restrict__ twg, const P *__restrict__ sing,
-    const cx<P> *__restrict__ lam, const P *__restrict__ mu, int kind, P tau, P alpha, P cnorm) {
+    const cx<P> *__restrict__ lam, const P *__restrict__ mu, P tau, P alpha, P cnorm) {
   using C = PairCfg<P, N1>;
   using L = DstLanes<P, N1, 1>;
   constexpr int M = N1 - 1, PS = C::PS, PN = C::PN, CH = L::CH, UPB = kPairWaves / 2;
@@ -1132,7 +1147,10 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_cols_t(
   __shared__ cx<P> lds[kPairWaves * PN];
   __shared__ cx<P> stw[C::TAB_LDS ? N1 : 1];
   __shared__ P ssin[C::TAB_LDS ? N1 : 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, h = wv & 1;
+  // the wave index is uniform across the wave: read it into a scalar register, so the
+  // block row h selects code paths by scalar branches rather than per-lane selects
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), h = wv & 1;
   stage_tables<P, N1, C::TAB_LDS>(twg, sing, stw, ssin, 64 * kPairWaves);
   if constexpr (C::TAB_LDS) __syncthreads();
   const cx<P> *tw = C::TAB_LDS ? stw : twg;
@@ -1155,26 +1173,47 @@ __global__ __launch_bounds__(64 * kPairWaves) void k_pair_cols_t(
   wdst_regs<P, N1, 1, 1, PS>(buf, tw, lane, o, e, b, k0, valid);
   wave_sync();
   // modes j2 = 2k (odd outputs) and 2k - 1 (even outputs, k >= 1): k0 > 0 except on lane 0
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int k = k0 + c;
-    buf[pk<PS>(2 * k + 1)] = o[c];
-    if (k > 0) buf[pk<PS>(2 * k)] = e[c];
-  }
-  __syncthreads();
   const cx<P> l = lam[q];
   const P muj1 = mu[j1];
+  if constexpr (KIND == 0) {  // P_S couples the two block rows: exchange through LDS
 #pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int k = k0 + c;
-    const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
-    o[c] = mode_op_row<P>(h ? po : o[c], h ? o[c] : po, h, l, muj1 + mu[2 * k], kind, tau,
-                          alpha, cnorm);
-    const cx<P> pe = pbuf[pk<PS>(k > 0 ? 2 * k : 2 * k + 1)];
-    e[c] = mode_op_row<P>(h ? pe : e[c], h ? e[c] : pe, h, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0],
-                          kind, tau, alpha, cnorm);
+    for (int c = 0; c < CH; ++c) {
+      const int k = k0 + c;
+      buf[pk<PS>(2 * k + 1)] = o[c];
+      if (k > 0) buf[pk<PS>(2 * k)] = e[c];
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + c;
+        const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
+        const cx<P> pe = pbuf[pk<PS>(k > 0 ? 2 * k : 2 * k + 1)];
+        o[c] = mode_op_fixed<P, 0, 0>(o[c], po, l, muj1 + mu[2 * k], tau, alpha, cnorm);
+        e[c] = mode_op_fixed<P, 0, 0>(e[c], pe, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0], tau,
+                                      alpha, cnorm);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + c;
+        const cx<P> po = pbuf[pk<PS>(2 * k + 1)];
+        const cx<P> pe = pbuf[pk<PS>(k > 0 ? 2 * k : 2 * k + 1)];
+        o[c] = mode_op_fixed<P, 0, 1>(o[c], po, l, muj1 + mu[2 * k], tau, alpha, cnorm);
+        e[c] = mode_op_fixed<P, 0, 1>(e[c], pe, l, muj1 + mu[k > 0 ? 2 * k - 1 : 0], tau,
+                                      alpha, cnorm);
+      }
+    }
+    __syncthreads();
+  } else {  // |P_S| and P_MS scale each row by itself
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int k = k0 + c;
+      o[c] = mode_op_fixed<P, KIND, 0>(o[c], o[c], l, muj1 + mu[2 * k], tau, alpha, cnorm);
+      e[c] = mode_op_fixed<P, KIND, 0>(e[c], e[c], l, muj1 + mu[k > 0 ? 2 * k - 1 : 0], tau,
+                                       alpha, cnorm);
+    }
   }
-  __syncthreads();
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     const int k = k0 + c;
@@ -1634,11 +1673,11 @@ hipError_t tfft_inv_ts(const wc_plan &p, double *w, const double *dotv, int *npa
 // columns where two still fit (measured at n = 512: 0.73 ms per pass against 0.9 ms at 16;
 // in FP64 a 32-column tile leaves one workgroup per CU and is slower, 1.17 against 0.96 ms)
 template <typename P, int N> constexpr bool fits_ts_h(int ts) {
-  return ts == 32 ? TimeCfgH<P, N, 32>::TILE <= kCuLds : true;
+  return ts == 32 ? TimeCfgH<P, N, 32, 4>::TILE <= kCuLds : true;
 }
 template <typename P, int N> constexpr int default_ts_h() {
-  if (std::is_same<P, float>::value && blocks_per_cu(TimeCfgH<P, N, 32>::TILE) >= 2) return 32;
-  return blocks_per_cu(TimeCfgH<P, N, 16>::TILE) >= 2 ? 16 : 8;
+  if (std::is_same<P, float>::value && blocks_per_cu(TimeCfgH<P, N, 32, 4>::TILE) >= 2) return 32;
+  return blocks_per_cu(TimeCfgH<P, N, 16, 4>::TILE) >= 2 ? 16 : 8;
 }
 template <typename P, int N> int time_choice(const wc_plan &p) {
   if (p.ts_time) return (p.ts_time < 0 && N < 64) ? default_ts<P, N>() : p.ts_time;
@@ -1650,7 +1689,8 @@ template <typename P, int N, int TS>
 hipError_t tfft_fwd_h(const wc_plan &p, const double *v) {
   const int ntile = (p.m + TS - 1) / TS;
   ProfScope ps(p, K_TFFT_FWD, (double)p.nvec * (8.0 + sizeof(P)));
-  hipLaunchKernelGGL((k_tfft_fwd_h<P, N, TS>), dim3(2 * ntile), dim3(TimeCfgH<P, N, TS>::NT), 0,
+  hipLaunchKernelGGL((k_tfft_fwd_h<P, N, TS>), dim3(2 * ntile),
+                     dim3(TimeCfgH<P, N, TS, time_waves_h<P, false>()>::NT), 0,
                      p.stream, v, (cx<P> *)p.d_specA, (const cx<double> *)p.d_dtw,
                      (const cx<double> *)p.d_twt64, p.m, ntile);
   return hipGetLastError();
@@ -1661,7 +1701,8 @@ hipError_t tfft_inv_h(const wc_plan &p, double *w, const double *dotv, int *npar
   const int ntile = (p.m + TS - 1) / TS;
   *nparts = 2 * ntile;
   ProfScope ps(p, K_TFFT_INV, (double)p.nvec * (sizeof(P) + (dotv ? 16.0 : 8.0)));
-  hipLaunchKernelGGL((k_tfft_inv_h<P, N, TS>), dim3(2 * ntile), dim3(TimeCfgH<P, N, TS>::NT), 0,
+  hipLaunchKernelGGL((k_tfft_inv_h<P, N, TS>), dim3(2 * ntile),
+                     dim3(TimeCfgH<P, N, TS, time_waves_h<P, true>()>::NT), 0,
                      p.stream, (const cx<P> *)p.d_specA, w, (const cx<double> *)p.d_dtw,
                      (const cx<double> *)p.d_twt64, p.m, ntile, dotv, p.d_partials);
   return hipGetLastError();
@@ -1765,10 +1806,19 @@ hipError_t space_tr(const wc_plan &p, int kind, double c) {
   {
     const int nunits = (p.n / 2) * M, upb = kPairWaves / 2;
     ProfScope ps(p, K_PAIR_MODE, bytes);
-    hipLaunchKernelGGL((k_pair_cols_t<P, N1>), dim3((nunits + upb - 1) / upb),
-                       dim3(64 * kPairWaves), 0, p.stream, T, nunits, Tabs<P>::tws(p),
-                       Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p), kind, (P)p.tau,
-                       (P)p.alpha, (P)c);
+    const dim3 grid((nunits + upb - 1) / upb), block(64 * kPairWaves);
+    if (kind == 0)
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 0>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
+    else if (kind == 1)
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 1>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
+    else
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 2>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lam(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   ProfScope ps(p, K_DST_X1_INV, bytes);
