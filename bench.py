@@ -21,6 +21,8 @@ Also measured in the same run (extra keys of the same line):
   * mixed precision: the same solve with the FP32 preconditioner apply (FP64
     Krylov, matvec, inner products and residuals), its speedup over FP64 and
     the difference of its y, p from the FP64 solution;
+  * MINRES-|P_S| on the same problem and GMRES-P_S at the gamma draws of seeds 1-3, each
+    in FP64 and with the FP32 preconditioner apply (minres_and_gamma_draws);
   * the low-rank form of the GMRES proposition (same iterates, compact basis);
   * the 2D M = 255, n = 256 workload in both forms;
   * a short serving pass (Poisson arrivals of mixed sizes, p50/p99 latency);
@@ -97,6 +99,9 @@ def parse():
     ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
     ap.add_argument("--zeta-sweep", type=int, default=1,
                     help="also solve the workload with zeta in {0.1, 0.01, 0.001} (general path)")
+    ap.add_argument("--minres-gamma", type=int, default=1,
+                    help="also solve the workload by MINRES-|P_S| and over the gamma draws of "
+                         "seeds 1-3, each in FP64 and with the FP32 preconditioner (2D, a = 1)")
     ap.add_argument("--next-rows", type=int, default=1,
                     help="also time the finite element, Neumann and general-size forms")
     ap.add_argument("--batch", type=int, default=8,
@@ -441,6 +446,59 @@ def zeta_sweep_bench(torch, wc, data, common, M, n):
     return res
 
 
+def minres_gamma_bench(torch, wc, datagen, args, data, common, y64, p64):
+    """The mixed-precision workload's other method and gamma draws: MINRES-|P_S| (zeta = pi)
+    and GMRES(30)-P_S with gamma = 10^U(-8,-2) drawn for seeds 1, 2, 3 (the data of the
+    headline's seed), each in FP64 and with the FP32 preconditioner apply: iterations,
+    ms per solve (one solve after one untimed) and the largest difference of y, p from the
+    FP64 standard-form solution of the same problem (MINRES: the headline's)."""
+    M, n = args.M, args.n
+    y, p = data[3], data[4]
+    res = {}
+
+    def solve(plan):
+        ms, infos, _ = time_solve(torch, wc, plan, data, 1, 1)
+        return {"ms_per_solve": round(ms, 2), "iters": infos[-1].iters,
+                "relres": infos[-1].relres}
+
+    def diff(yr, pr):
+        sc = max(float(yr.abs().max()), float(pr.abs().max()))
+        return max(float((y - yr).abs().max()), float((p - pr).abs().max())) / sc
+
+    mres = {}
+    for prec in ("fp64", "mixed"):
+        plan = wc.Plan(2, M, n, precision=prec, **dict(common, method="minres_abs_ps"))
+        r = solve(plan)
+        r["max_rel_diff_vs_fp64_gmres_solution"] = diff(y64, p64)
+        mres[prec] = r
+        log(f"minres |P_S| {prec}: {r}")
+        plan.close()
+        torch.cuda.empty_cache()
+    mres["speedup_mixed_vs_fp64"] = round(mres["fp64"]["ms_per_solve"] /
+                                          mres["mixed"]["ms_per_solve"], 3)
+    res["minres_abs_ps"] = mres
+    sweep = {f"seed{seed}": {"gamma": datagen.log_uniform_gamma(seed)} for seed in (1, 2, 3)}
+    ref = {}
+    for prec in ("fp64", "mixed"):  # one plan at a time: an FGMRES(30) plan holds 131 GiB
+        plan = wc.Plan(2, M, n, precision=prec, flexible=True, **common)
+        for key, row in sweep.items():
+            plan.retarget(theta=common["theta"], gamma=row["gamma"], tol=common["tol"],
+                          maxit=common["maxit"])
+            row[prec] = solve(plan)
+            if prec == "fp64":
+                ref[key] = (y.clone(), p.clone())
+            else:
+                row[prec]["max_rel_diff_vs_fp64_solution"] = diff(*ref[key])
+                row["speedup_mixed_vs_fp64"] = round(row["fp64"]["ms_per_solve"] /
+                                                     row["mixed"]["ms_per_solve"], 3)
+                log(f"gamma {key}: {row}")
+        plan.close()
+        torch.cuda.empty_cache()
+    del ref
+    res["gamma_draws"] = sweep
+    return res
+
+
 args_autotune = [1]
 
 
@@ -525,6 +583,12 @@ def main():
         mp.close()
         del mp
         torch.cuda.empty_cache()
+
+    # ---- MINRES-|P_S| and the other gamma draws, FP64 and mixed -------------------------
+    mg = None
+    if (args.minres_gamma and args.dims == 2 and args.coeff == "const"
+            and args.method == "gmres_ps"):
+        mg = minres_gamma_bench(torch, wc, datagen, args, data, common, y64, p64)
 
     # ---- low-rank form (same iterates, compact Krylov basis) ---------------------------
     lowrank = None
@@ -639,6 +703,7 @@ def main():
                      "bytes_per_launch": tot_bytes / launches,
                      "overall_dominant_kernel": overall},
         "mixed": mixed,
+        "minres_and_gamma_draws": mg,
         "lowrank": lowrank,
         "heat2d_M255_n256": small,
         "serve": {"p50_ms": served["rates"][-1]["p50_ms"], "p99_ms": served["rates"][-1]["p99_ms"],
