@@ -125,36 +125,50 @@ def sync_ms(torch, fn, reps):
 
 
 def batch_bench(args):
-    """Many instances of a small problem: sequential wc_solve (captured iterations) against
-    one lockstep batch (one launch per preconditioner pass for all instances)."""
+    """Many instances of small problems: sequential wc_solve (captured iterations) against
+    one lockstep batch (one launch per preconditioner pass for all instances of a tile
+    shape): `args.batch` instances of 2D M = 63, n = 64, and as many of four uneven shapes
+    (M, n) in {63, 127} x {64, 128}."""
     import numpy as np
     import torch
     import datagen
     from paper_2406_00952_amd import wc
-    M, n, k = 63, 64, args.batch
-    plans = [wc.Plan(2, M, n, theta=0.5, gamma=1e-4, method="gmres_ps", tol=1e-8, maxit=500)
-             for _ in range(k)]
-    data = []
-    for i in range(k):
-        d = datagen.config_problem(2, M, n, seed=args.seed + 10 + i, noise_sigma=1e-3)
-        data.append([torch.from_numpy(np.ascontiguousarray(d[x])).cuda() for x in ("f", "g", "y0")])
-    ys = [torch.empty(n * M * M, dtype=torch.float64, device="cuda") for _ in range(k)]
-    ps = [torch.empty_like(y) for y in ys]
-    batch = wc.Batch(plans)
-    cols = [[dd[j] for dd in data] for j in range(3)]
-    out = {"instances": k, "shape": "2D M=63 n=64 fp64 GMRES(30)-P_S"}
-    fns = {"sequential": lambda: [pl.solve(*dd, y, p) for pl, dd, y, p in zip(plans, data, ys, ps)],
-           "batch": lambda: batch.solve(cols[0], cols[1], cols[2], ys, ps)}
-    for name, fn in fns.items():
-        fn()
-        ms, infos = sync_ms(torch, fn, 5)
-        out[name] = {"ms": round(ms, 3), "solves_per_s": round(1000.0 * k / ms, 1),
-                     "iters": [i.iters for i in infos],
-                     "max_relres": max(i.relres for i in infos)}
-    out["speedup"] = round(out["sequential"]["ms"] / out["batch"]["ms"], 3)
-    batch.close()
-    for pl in plans:
-        pl.close()
+    k = args.batch
+    shape_sets = {"same": [(63, 64)] * k,
+                  "uneven": [[(63, 64), (63, 128), (127, 64), (127, 128)][i % 4]
+                             for i in range(k)]}
+    out = {"instances": k, "shape": "2D M=63 n=64 fp64 GMRES(30)-P_S",
+           "uneven_shapes": shape_sets["uneven"]}
+    for label, shapes in shape_sets.items():
+        plans = [wc.Plan(2, M, n, theta=0.5, gamma=1e-4, method="gmres_ps", tol=1e-8,
+                         maxit=500) for (M, n) in shapes]
+        data = []
+        for i, (M, n) in enumerate(shapes):
+            d = datagen.config_problem(2, M, n, seed=args.seed + 10 + i, noise_sigma=1e-3)
+            data.append([torch.from_numpy(np.ascontiguousarray(d[x])).cuda()
+                         for x in ("f", "g", "y0")])
+        ys = [torch.empty(n * M * M, dtype=torch.float64, device="cuda") for (M, n) in shapes]
+        ps = [torch.empty_like(y) for y in ys]
+        batch = wc.Batch(plans)
+        cols = [[dd[j] for dd in data] for j in range(3)]
+        fns = {"sequential": lambda: [pl.solve(*dd, y, p)
+                                      for pl, dd, y, p in zip(plans, data, ys, ps)],
+               "batch": lambda: batch.solve(cols[0], cols[1], cols[2], ys, ps)}
+        res = {}
+        for name, fn in fns.items():
+            fn()
+            ms, infos = sync_ms(torch, fn, 5)
+            res[name] = {"ms": round(ms, 3), "solves_per_s": round(1000.0 * k / ms, 1),
+                         "iters": [i.iters for i in infos],
+                         "max_relres": max(i.relres for i in infos)}
+        res["speedup"] = round(res["sequential"]["ms"] / res["batch"]["ms"], 3)
+        if label == "same":
+            out.update(res)
+        else:
+            out["uneven"] = res
+        batch.close()
+        for pl in plans:
+            pl.close()
     log(f"batch: {out}")
     return out
 

@@ -302,6 +302,18 @@ __global__ __launch_bounds__(kThreads) void k_recover(const double *__restrict__
 
 // ---- streaming BLAS-1 with deterministic reductions ---------------------------
 
+// 16-byte accesses (pairs of elements) when every vector is 16-byte aligned and the length
+// even (system vectors have 2 n m elements); the streams present are template arguments, so
+// no run-time branch splits a thread's loads.
+__device__ __forceinline__ bool pairs_ok(size_t nv, const void *a, const void *b = nullptr,
+                                         const void *c = nullptr, const void *d = nullptr,
+                                         const void *e = nullptr, const void *f = nullptr) {
+  const uintptr_t m = (uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)d |
+                      (uintptr_t)e | (uintptr_t)f;
+  return (nv & 1) == 0 && (m & 15) == 0;
+}
+
+template <bool HB, bool HC>
 __global__ __launch_bounds__(kThreads) void k_lincomb3(double *__restrict__ dst,
                                                        const double *__restrict__ a,
                                                        const double *__restrict__ b,
@@ -312,11 +324,26 @@ __global__ __launch_bounds__(kThreads) void k_lincomb3(double *__restrict__ dst,
   const double c0 = slot >= 0 ? scal[slot] : h0;
   const double c1 = slot >= 0 ? scal[slot + 1] : h1;
   const double c2 = slot >= 0 ? scal[slot + 2] : h2;
+  if (pairs_ok(nv, dst, a, b, c)) {
+    const size_t np = nv >> 1;
+    const d2v *a2 = reinterpret_cast<const d2v *>(a);
+    const d2v *b2 = reinterpret_cast<const d2v *>(b);
+    const d2v *c2v = reinterpret_cast<const d2v *>(c);
+    d2v *o2 = reinterpret_cast<d2v *>(dst);
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < np;
+         i += (size_t)gridDim.x * kThreads) {
+      d2v v = c0 * a2[i];
+      if (HB) v += c1 * b2[i];
+      if (HC) v += c2 * c2v[i];
+      o2[i] = v;
+    }
+    return;
+  }
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
        i += (size_t)gridDim.x * kThreads) {
     double v = c0 * a[i];
-    if (b) v += c1 * b[i];
-    if (c) v += c2 * c[i];
+    if (HB) v += c1 * b[i];
+    if (HC) v += c2 * c[i];
     dst[i] = v;
   }
 }
@@ -326,9 +353,20 @@ __global__ __launch_bounds__(kThreads) void k_dot(const double *__restrict__ a,
                                                   double *__restrict__ partials) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads)
-    acc += a[i] * b[i];
+  if (pairs_ok(nv, a, b)) {
+    const size_t np = nv >> 1;
+    const d2v *a2 = reinterpret_cast<const d2v *>(a);
+    const d2v *b2 = reinterpret_cast<const d2v *>(b);
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < np;
+         i += (size_t)gridDim.x * kThreads) {
+      const d2v x = a2[i], y = b2[i];
+      acc += x.x * y.x + x.y * y.y;
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+         i += (size_t)gridDim.x * kThreads)
+      acc += a[i] * b[i];
+  }
   const double r = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
@@ -363,14 +401,34 @@ __global__ __launch_bounds__(kThreads) void k_minres_update(double *__restrict__
   const double cwz = scal[S_CWZ], cw0 = scal[S_CW0], cw1 = scal[S_CW1];
   const double cxx = scal[S_CX], crr = scal[S_CRR], crv = scal[S_CRV];
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (size_t)gridDim.x * kThreads) {
-    const double wn = cwz * z[i] + cw0 * w0[i] + cw1 * w1[i];
-    w0[i] = wn;
-    x[i] += cxx * wn;
-    const double rn = crr * r[i] + crv * vnew[i];
-    r[i] = rn;
-    acc += rn * rn;
+  if (pairs_ok(nv, w0, w1, z, x, r, vnew)) {
+    const size_t np = nv >> 1;
+    d2v *w02 = reinterpret_cast<d2v *>(w0);
+    const d2v *w12 = reinterpret_cast<const d2v *>(w1);
+    const d2v *z2 = reinterpret_cast<const d2v *>(z);
+    d2v *x2 = reinterpret_cast<d2v *>(x);
+    d2v *r2 = reinterpret_cast<d2v *>(r);
+    const d2v *v2 = reinterpret_cast<const d2v *>(vnew);
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < np;
+         i += (size_t)gridDim.x * kThreads) {
+      const d2v zi = z2[i], a0 = w02[i], a1 = w12[i], xi = x2[i], ri = r2[i], vi = v2[i];
+      const d2v wn = cwz * zi + cw0 * a0 + cw1 * a1;
+      w02[i] = wn;
+      x2[i] = xi + cxx * wn;
+      const d2v rn = crr * ri + crv * vi;
+      r2[i] = rn;
+      acc += rn.x * rn.x + rn.y * rn.y;
+    }
+  } else {
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+         i += (size_t)gridDim.x * kThreads) {
+      const double wn = cwz * z[i] + cw0 * w0[i] + cw1 * w1[i];
+      w0[i] = wn;
+      x[i] += cxx * wn;
+      const double rn = crr * r[i] + crv * vnew[i];
+      r[i] = rn;
+      acc += rn * rn;
+    }
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -774,8 +832,19 @@ hipError_t launch_recover(const wc_plan &p, const double *x, double *y, double *
 hipError_t launch_lincomb3(const wc_plan &p, double *dst, const double *a, const double *b,
                            const double *c, int slot, double h0, double h1, double h2) {
   ProfScope ps(p, K_LINCOMB, 8.0 * p.nvec * (2 + (b ? 1 : 0) + (c ? 1 : 0)));
-  hipLaunchKernelGGL(k_lincomb3, dim3(red_blocks(p.nvec)), dim3(kThreads), 0, p.stream, dst, a,
-                     b, c, p.nvec, p.d_scal, slot, h0, h1, h2);
+  const dim3 grid(red_blocks(p.nvec)), block(kThreads);
+  if (b && c)
+    hipLaunchKernelGGL((k_lincomb3<true, true>), grid, block, 0, p.stream, dst, a, b, c, p.nvec,
+                       p.d_scal, slot, h0, h1, h2);
+  else if (b)
+    hipLaunchKernelGGL((k_lincomb3<true, false>), grid, block, 0, p.stream, dst, a, b, c,
+                       p.nvec, p.d_scal, slot, h0, h1, h2);
+  else if (c)
+    hipLaunchKernelGGL((k_lincomb3<false, true>), grid, block, 0, p.stream, dst, a, b, c,
+                       p.nvec, p.d_scal, slot, h0, h1, h2);
+  else
+    hipLaunchKernelGGL((k_lincomb3<false, false>), grid, block, 0, p.stream, dst, a, b, c,
+                       p.nvec, p.d_scal, slot, h0, h1, h2);
   return hipGetLastError();
 }
 
