@@ -27,8 +27,8 @@ Also measured in the same run (extra keys of the same line):
   * the 2D M = 255, n = 256 workload in both forms;
   * a short serving pass (Poisson arrivals of mixed sizes, p50/p99 latency);
   * batches: 8 instances solved in lockstep against one solve after another;
-  * zeta_sweep: the workload with omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001} (the
-    dense general path), one FP64 solve each;
+  * zeta_sweep: the workload with omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001} (FFTs
+    over all n frequencies: no conjugate symmetry), one FP64 solve each;
   * next_rows: finite elements (M = 255, n = 256), Neumann data on Table 4's finest
     grid (with its e_h beside the printed value) and a general-size problem
     (M = 300, n = 300), each a timed solve plus its preconditioner apply;
@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=60, help="requests per rate, --serve")
     ap.add_argument("--concurrency", type=int, default=4, help="server workers, --serve")
     ap.add_argument("--zeta-sweep", type=int, default=1,
-                    help="also solve the workload with zeta in {0.1, 0.01, 0.001} (general path)")
+                    help="also solve the workload with zeta in {0.1, 0.01, 0.001} (full spectrum)")
     ap.add_argument("--minres-gamma", type=int, default=1,
                     help="also solve the workload by MINRES-|P_S| and over the gamma draws of "
                          "seeds 1-3, each in FP64 and with the FP32 preconditioner (2D, a = 1)")
@@ -444,9 +444,9 @@ def next_rows_bench(torch, wc, dev, steps=3):
 
 def zeta_sweep_bench(torch, wc, data, common, M, n):
     """The mixed-precision workload's omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001}, on the
-    same 2D M = 511, n = 512 problem: the general path (zeta != pi: dense time transform
-    over all n frequencies, dense sine steps on the FP64 matrix cores), one FP64 solve
-    each."""
+    same 2D M = 511, n = 512 problem: zeta != pi, so each block row's spectrum has no
+    conjugate symmetry and all n frequencies are transformed (n-point FFTs, the transposed
+    sine passes over 2n slabs), one FP64 solve each."""
     res = {}
     for zeta in (0.1, 0.01, 0.001):
         plan = wc.Plan(2, M, n, precision="fp64", flexible=True, zeta=zeta,

@@ -137,6 +137,14 @@ bool uses_spec_t(const wc_problem *pr, const wc_opts *op) {
          pr->bc == WC_DIRICHLET && pr->M + 1 >= 128 && pc_path_ok(pr);
 }
 
+// The general path at power-of-two sizes (2D Dirichlet, a constant, any zeta): FFTs over all
+// n frequencies and the transposed sine passes, whose copy holds 2n slabs of M rows of M + 1.
+bool uses_full_fft(const wc_problem *pr) {
+  auto p2 = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
+  return uses_general(pr) && pr->dims == 2 && pr->bc == WC_DIRICHLET && !pr->a_face_host &&
+         pr->disc == WC_FD && p2(pr->n, 4, 1024) && p2(pr->M + 1, 128, 1024);
+}
+
 // Multigrid levels M_0 = M, M_{l+1} = (M_l - 1)/2, ..., 1; the first level whose remaining
 // pyramid fits the LDS budget of one workgroup; bytes of u and f of levels 1..ltop.
 struct MgShape {
@@ -171,7 +179,9 @@ Sizes sizes_of(const wc_problem *pr, const wc_opts *op) {
   // n/2 frequencies x 2 halves x m complex; the general path keeps all n frequencies
   s.spec_bytes = (gen ? 2 : 1) * (size_t)pr->n * m * es;
   // 2D a == 1 (standard form), N1 >= 128: the transposed copy of the x2 pass, rows of N1
-  s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es : 0;
+  s.spec_t_bytes = uses_spec_t(pr, op) ? (size_t)pr->n * pr->M * (pr->M + 1) * es
+                  : uses_full_fft(pr)   ? 2 * (size_t)pr->n * pr->M * (pr->M + 1) * es
+                                        : 0;
   // finite elements: the FP64 complex sine transforms of the data and the solution
   s.fem_bytes = pr->disc == WC_FEM ? (size_t)pr->n * m * 16 : 0;
   // Neumann: the second spectral array of the out-of-place dense steps, C and C^{-1}

@@ -2354,12 +2354,214 @@ hipError_t dense_space(const wc_plan &p, cx<P> *A, cx<P> *B, int nslab, Op op) {
   return rows(B, A, Cf, K_DST_X1_INV);
 }
 
+// ---- any zeta at power-of-two sizes: the full time spectrum --------------------------
+// For omega = e^{i zeta} with zeta != pi each block row's twiddled sequence e^{i zeta k/n} v_k
+// is complex, so its spectrum has no conjugate symmetry: all n frequencies are kept, an
+// n-point FFT per block row and column (eqn:decompositiob_S12 as corrected).  G holds the
+// spectrum as [l][half][x2][x1] (slab 2l + h, twice the half-spectrum array), so the
+// transposed sine passes of the FFT path run on it unchanged over 2n slabs, with lambda_l of
+// every frequency; the inverse takes the real part (the preconditioner of the real system).
+template <typename P, int N, int TS> struct FullCfg {
+  static constexpr int WAVES = TS < 4 ? TS : 4;
+  static constexpr int NT = 64 * WAVES;
+  static constexpr int CXB = 2 * (int)sizeof(P);
+  static constexpr int PS = 4;
+  static constexpr int PN = padded<PS>(N);
+  static constexpr int S = TS + 1;
+  static constexpr int TILE = PN * S * CXB;  // twiddles are read from global memory
+};
+// the widest tile (at most 16 columns) that keeps two workgroups resident per CU
+template <typename P, int N> constexpr int full_ts() {
+  if constexpr (blocks_per_cu(FullCfg<P, N, 16>::TILE) >= 2) return 16;
+  else if constexpr (blocks_per_cu(FullCfg<P, N, 8>::TILE) >= 2) return 8;
+  else if constexpr (blocks_per_cu(FullCfg<P, N, 4>::TILE) >= 2) return 4;
+  else return 2;
+}
+
+// forward: tile (h, TS columns) of block row h of v -> G[l][h][s], l = 0..N-1
+template <typename P, int N, int TS>
+__global__ __launch_bounds__((FullCfg<P, N, TS>::NT)) void k_tfft_full_fwd(
+    const double *__restrict__ v, cx<P> *__restrict__ G, const cx<double> *__restrict__ dtw,
+    const cx<P> *__restrict__ twt, int m, int ntile) {
+  using C = FullCfg<P, N, TS>;
+  constexpr int S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
+  constexpr int LIT = (N * TS + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * S];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int h = t / ntile, s0 = (t % ntile) * TS;
+  const double *src = v + (size_t)h * N * m;
+  double ra[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {  // every load issued before any is consumed
+    const int idx = tid + it * NT, k = idx / TS, gs = s0 + idx % TS;
+    ra[it] = 0.0;
+    if ((N * TS % NT == 0 || idx < N * TS) && gs < m) ra[it] = src[(size_t)k * m + gs];
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (N * TS % NT == 0 || idx < N * TS) {
+      const int k = idx / TS, s = idx % TS;
+      const cx<double> d = dtw[k];  // e^{i zeta k/n}
+      buf[pk<PS>(k) * S + s] = cx<P>{(P)(ra[it] * d.x), (P)(ra[it] * d.y)};
+    }
+  }
+  __syncthreads();
+  wfft<P, N, 1, CPW, S, PS, false, true>(buf + wv * CPW, twt, lane);
+  __syncthreads();
+  for (int idx = tid; idx < N * TS; idx += NT) {
+    const int l = idx / TS, s = idx % TS, gs = s0 + s;
+    if (gs < m) G[((size_t)l * 2 + h) * m + gs] = buf[pk<PS>(l) * S + s];
+  }
+}
+
+// inverse: G[l][h][s] -> Re(e^{-i zeta k/n} sum_l e^{2 pi i k l/n} G_l), block row h of w (the
+// 1/n sits in the per-mode scale)
+template <typename P, int N, int TS>
+__global__ __launch_bounds__((FullCfg<P, N, TS>::NT)) void k_tfft_full_inv(
+    const cx<P> *__restrict__ G, double *__restrict__ w, const cx<double> *__restrict__ dtw,
+    const cx<P> *__restrict__ twt, int m, int ntile) {
+  using C = FullCfg<P, N, TS>;
+  constexpr int S = C::S, PS = C::PS, NT = C::NT, CPW = TS / C::WAVES;
+  constexpr int LIT = (N * TS + NT - 1) / NT;
+  __shared__ cx<P> buf[C::PN * S];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int h = t / ntile, s0 = (t % ntile) * TS;
+  cx<P> ya[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT, l = idx / TS, gs = s0 + idx % TS;
+    ya[it] = cx<P>{(P)0, (P)0};
+    if ((N * TS % NT == 0 || idx < N * TS) && gs < m) ya[it] = G[((size_t)l * 2 + h) * m + gs];
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (N * TS % NT == 0 || idx < N * TS) buf[pk<PS>(idx / TS) * S + idx % TS] = ya[it];
+  }
+  __syncthreads();
+  wfft<P, N, 1, CPW, S, PS, true, true>(buf + wv * CPW, twt, lane);
+  __syncthreads();
+  double *o = w + (size_t)h * N * m;
+  for (int idx = tid; idx < N * TS; idx += NT) {
+    const int k = idx / TS, s = idx % TS, gs = s0 + s;
+    if (gs >= m) continue;
+    const cx<P> z = buf[pk<PS>(k) * S + s];
+    const cx<double> d = dtw[k];  // Re(z conj(d))
+    o[(size_t)k * m + gs] = (double)z.x * d.x + (double)z.y * d.y;
+  }
+}
+
+template <typename P, int N, bool INV>
+hipError_t full_time(const wc_plan &p, const double *v, double *w) {
+  constexpr int TS = full_ts<P, N>();
+  using C = FullCfg<P, N, TS>;
+  const int ntile = (p.m + TS - 1) / TS;
+  const double bytes = 8.0 * p.nvec + 2.0 * p.n * (double)p.m * sizeof(cx<P>);
+  cx<P> *G = (cx<P> *)p.d_specA;
+  if constexpr (INV) {
+    ProfScope ps(p, K_TFFT_INV, bytes);
+    hipLaunchKernelGGL((k_tfft_full_inv<P, N, TS>), dim3(2 * ntile), dim3(C::NT), 0, p.stream, G,
+                       w, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m, ntile);
+  } else {
+    ProfScope ps(p, K_TFFT_FWD, bytes);
+    hipLaunchKernelGGL((k_tfft_full_fwd<P, N, TS>), dim3(2 * ntile), dim3(C::NT), 0, p.stream,
+                       v, G, (const cx<double> *)p.d_dtw, Tabs<P>::twt(p), p.m, ntile);
+  }
+  return hipGetLastError();
+}
+
+// the transposed sine passes and the per-mode solves over the 2n slabs of G (through the
+// transposed copy d_specT, 2n slabs of M rows of N1)
+template <typename P, int N1>
+hipError_t full_space(const wc_plan &p, int kind, double c) {
+  constexpr int M = N1 - 1, R = default_tr<P, N1>(), NRB = (M + R - 1) / R;
+  cx<P> *A = (cx<P> *)p.d_specA;
+  cx<P> *T = (cx<P> *)p.d_specT;
+  const int nslab = 2 * p.n;
+  const double bytes = 2.0 * nslab * (double)p.m * sizeof(cx<P>);
+  hipError_t e;
+  {
+    ProfScope ps(p, K_DST_X1_FWD, bytes);
+    hipLaunchKernelGGL((k_rows_fwd_t<P, N1, R>), dim3(nslab * NRB), dim3(64 * R), 0, p.stream, A,
+                       T, Tabs<P>::tws(p), Tabs<P>::sin(p));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    const int nunits = p.n * M, upb = kPairWaves / 2;
+    const dim3 grid((nunits + upb - 1) / upb), block(64 * kPairWaves);
+    ProfScope ps(p, K_PAIR_MODE, bytes);
+    if (kind == 0)
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 0>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lamf(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
+    else if (kind == 1)
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 1>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lamf(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
+    else
+      hipLaunchKernelGGL((k_pair_cols_t<P, N1, 2>), grid, block, 0, p.stream, T, nunits,
+                         Tabs<P>::tws(p), Tabs<P>::sin(p), Tabs<P>::lamf(p), Tabs<P>::mu(p),
+                         (P)p.tau, (P)p.alpha, (P)c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ProfScope ps(p, K_DST_X1_INV, bytes);
+  hipLaunchKernelGGL((k_rows_inv_t<P, N1, R>), dim3(nslab * NRB), dim3(64 * R), 0, p.stream, T, A,
+                     Tabs<P>::tws(p), Tabs<P>::sin(p));
+  return hipGetLastError();
+}
+
+bool pow2_between(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+// the full-spectrum FFT form applies: 2D Dirichlet finite differences, n a power of two in
+// [4, 1024], M + 1 a power of two in [128, 1024] (the transposed sine passes)
+bool full_fft_ok(const wc_plan &p) {
+  return p.dims == 2 && !p.neumann && !p.fem && !p.var_coeff && p.d_specT &&
+         pow2_between(p.n, 4, 1024) && pow2_between(p.M + 1, 128, 1024);
+}
+
+template <typename P>
+hipError_t pc_apply_full(const wc_plan &p, const double *v, double *w, const double *dotv,
+                         int *nparts) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (p.n) {
+#define CASE_N(NN) case NN: e = full_time<P, NN, false>(p, v, nullptr); break;
+    WC_POW2_CASES(CASE_N)
+#undef CASE_N
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int kind = p.opts.method == WC_GMRES_PS ? 0 : (p.opts.method == WC_MINRES_ABS_PS ? 1 : 2);
+  const double c = (1.0 / p.n) * (2.0 / (p.M + 1)) * (2.0 / (p.M + 1));
+  switch (p.M + 1) {
+    case 128: e = full_space<P, 128>(p, kind, c); break;
+    case 256: e = full_space<P, 256>(p, kind, c); break;
+    case 512: e = full_space<P, 512>(p, kind, c); break;
+    case 1024: e = full_space<P, 1024>(p, kind, c); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (p.n) {
+#define CASE_N(NN) case NN: e = full_time<P, NN, true>(p, nullptr, w); break;
+    WC_POW2_CASES(CASE_N)
+#undef CASE_N
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  *nparts = 0;
+  if (dotv) return launch_dot_partials(p, w, dotv, nparts);
+  return hipSuccess;
+}
+
 // P^{-1} v on the general path: dense time transform of both block rows over all n
 // frequencies (any n, any zeta), dense spatial steps, per-mode solves, the inverse
 // steps, the real part (the preconditioner of a real system)
 template <typename P>
 hipError_t pc_apply_general(const wc_plan &p, const double *v, double *w, const double *dotv,
                             int *nparts) {
+  if (full_fft_ok(p)) return pc_apply_full<P>(p, v, w, dotv, nparts);
   cx<P> *G = (cx<P> *)p.d_specA, *B = (cx<P> *)p.d_specB;
   const int n = p.n, m = p.m;
   const dim3 gt((m + kDenseT - 1) / kDenseT, (n + kDenseT - 1) / kDenseT, 2);

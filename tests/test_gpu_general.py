@@ -2,8 +2,9 @@
 odd n with the remedied singular S_n^(2) of the remark in Section 1; any M; any zeta,
 omega = e^{i zeta}) for constant-coefficient finite differences, Dirichlet or Neumann data.
 The time step is a dense product over all n frequencies and the spatial steps dense
-products with the sine (or cosine) matrix; the preconditioner of the real system is the
-real part of P^{-1} v, as in the oracle.
+products with the sine (or cosine) matrix; at 2D Dirichlet power-of-two sizes (n, and M + 1
+from 128) an n-point FFT over all frequencies and the transposed sine passes instead. The
+preconditioner of the real system is the real part of P^{-1} v, as in the oracle.
 
 Tolerances: FP64 applies 1e-12 relative to the largest entry; FP32 applies 1e-4 (dense
 sums of up to n = 64 terms in single precision); solves to 1e-8 with iteration counts
@@ -57,6 +58,12 @@ PC_CASES = [
     (2, 20, 10, 0.5, 0.5, "neumann"),
     (1, 33, 7, 1.0, np.pi, "neumann"),
     (1, 1, 3, 0.5, np.pi, "dirichlet"),      # smallest sizes
+    # 2D power-of-two sizes with zeta != pi: FFTs over all n frequencies and the transposed
+    # sine passes (N1 = 128, 256, 512)
+    (2, 127, 16, 0.5, 1.0, "dirichlet"),
+    (2, 255, 8, 1.0, 2.5, "dirichlet"),
+    (2, 511, 4, 0.5, 0.1, "dirichlet"),
+    (2, 127, 32, 0.5, 0.0, "dirichlet"),     # omega = 1, n even: remedied S^(2)
 ]
 
 
@@ -96,6 +103,7 @@ SOLVE_CASES = [
     (1, 60, 21, 1.0, np.pi, "dirichlet", 1e-2, "minres_pms"),
     (2, 15, 16, 0.5, 1.0, "dirichlet", 1e-4, "gmres_ps"),
     (2, 24, 20, 0.5, np.pi, "neumann", 1e-4, "gmres_ps"),
+    (2, 127, 16, 0.5, 2.5, "dirichlet", 1e-4, "gmres_ps"),  # full-spectrum FFT path
 ]
 
 
