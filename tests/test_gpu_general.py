@@ -64,6 +64,8 @@ PC_CASES = [
     (2, 255, 8, 1.0, 2.5, "dirichlet"),
     (2, 511, 4, 0.5, 0.1, "dirichlet"),
     (2, 127, 32, 0.5, 0.0, "dirichlet"),     # omega = 1, n even: remedied S^(2)
+    (2, 127, 512, 0.5, 1.0, "dirichlet"),    # the 512-point full-spectrum time FFT
+    (2, 127, 1024, 1.0, 0.3, "dirichlet"),   # the 1024-point one (two-column tiles in FP64)
 ]
 
 
