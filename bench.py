@@ -28,7 +28,8 @@ Also measured in the same run (extra keys of the same line):
   * a short serving pass (Poisson arrivals of mixed sizes, p50/p99 latency);
   * batches: 8 instances solved in lockstep against one solve after another;
   * zeta_sweep: the workload with omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001} (FFTs
-    over all n frequencies: no conjugate symmetry), one FP64 solve each;
+    over all n frequencies: no conjugate symmetry), one FP64 solve and one with the FP32
+    preconditioner apply each;
   * next_rows: finite elements (M = 255, n = 256), Neumann data on Table 4's finest
     grid (with its e_h beside the printed value) and a general-size problem
     (M = 300, n = 300), each a timed solve plus its preconditioner apply;
@@ -446,17 +447,37 @@ def zeta_sweep_bench(torch, wc, data, common, M, n):
     """The mixed-precision workload's omega = e^{i zeta}, zeta in {0.1, 0.01, 0.001}, on the
     same 2D M = 511, n = 512 problem: zeta != pi, so each block row's spectrum has no
     conjugate symmetry and all n frequencies are transformed (n-point FFTs, the transposed
-    sine passes over 2n slabs), one FP64 solve each."""
+    sine passes over 2n slabs).  One FP64 solve each (at most 200 iterations), then one with
+    the FP32 preconditioner apply (at most 100 iterations; near omega = 1 it may stop there,
+    reported with its residual) and the largest difference of its y, p from the FP64
+    solution."""
+    y, p = data[3], data[4]
     res = {}
     for zeta in (0.1, 0.01, 0.001):
         plan = wc.Plan(2, M, n, precision="fp64", flexible=True, zeta=zeta,
                        **dict(common, maxit=200))
         ms, infos, _ = time_solve(torch, wc, plan, data, 1, 0)
-        res[str(zeta)] = {"ms_per_solve": round(ms, 1), "iters": infos[-1].iters,
-                          "relres": infos[-1].relres}
-        log(f"zeta {zeta}: {res[str(zeta)]}")
+        r = {"ms_per_solve": round(ms, 1), "iters": infos[-1].iters, "relres": infos[-1].relres}
         plan.close()
         torch.cuda.empty_cache()
+        yr, pr = y.clone(), p.clone()
+        mp = wc.Plan(2, M, n, precision="mixed", flexible=True, zeta=zeta,
+                     **dict(common, maxit=100))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = mp.solve(*data, allow_maxit=True)
+        torch.cuda.synchronize()
+        sc = max(float(yr.abs().max()), float(pr.abs().max()))
+        r["mixed"] = {"ms_per_solve": round((time.perf_counter() - t0) * 1000.0, 1),
+                      "iters": inf.iters, "relres": inf.relres,
+                      "converged": bool(inf.status == wc.WC_OK),
+                      "max_rel_diff_vs_fp64_solution":
+                          max(float((y - yr).abs().max()), float((p - pr).abs().max())) / sc}
+        mp.close()
+        del yr, pr
+        torch.cuda.empty_cache()
+        res[str(zeta)] = r
+        log(f"zeta {zeta}: {r}")
     return res
 
 
