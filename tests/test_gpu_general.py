@@ -106,6 +106,7 @@ SOLVE_CASES = [
     (2, 15, 16, 0.5, 1.0, "dirichlet", 1e-4, "gmres_ps"),
     (2, 24, 20, 0.5, np.pi, "neumann", 1e-4, "gmres_ps"),
     (2, 127, 16, 0.5, 2.5, "dirichlet", 1e-4, "gmres_ps"),  # full-spectrum FFT path
+    (2, 127, 16, 1.0, 1.0, "dirichlet", 1e-2, "minres_abs_ps"),  # full spectrum, Re P^{-1} v
 ]
 
 
