@@ -215,7 +215,10 @@ wc_status wc_matvec(wc_plan *plan, const double *x, double *y);
  * variable a).  Other n <= 1024, M <= 1024 or zeta with constant-coefficient finite
  * differences run the general path: the time step as a dense product over all n
  * frequencies, dense spatial steps, and the real part of P^{-1} v (for zeta not in
- * {0, pi} P_S is complex; the real part is the preconditioner of the real system).
+ * {0, pi} P_S is complex; the real part is the preconditioner of the real system).  In
+ * 2D with Dirichlet data, n a power of two in [4, 1024] and M+1 one in [128, 1024], the
+ * general path takes n-point FFTs over all n frequencies and the FFT path's sine passes
+ * instead of the dense products (same result to rounding).
  * Variable a and finite elements need the FFT path (WC_E_UNSUPPORTED otherwise). */
 wc_status wc_pc_apply(wc_plan *plan, const double *v, double *w);
 
