@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -61,10 +62,13 @@ struct Key {
     return pe && oe && aface == o.aface;
   }
 
-  // same device footprint and buffers: a plan for one can be retargeted to the other
+  // same device footprint and buffers: a plan for one can be retargeted to the other (the
+  // preconditioner's path, which zeta == pi or not decides at equal sizes, must match too)
   bool same_shape(const Key &o) const {
+    const bool pi_a = std::fabs(prob.zeta - M_PI) <= 1e-12;
+    const bool pi_b = std::fabs(o.prob.zeta - M_PI) <= 1e-12;
     return prob.dims == o.prob.dims && prob.M == o.prob.M && prob.n == o.prob.n &&
-           prob.disc == o.prob.disc && prob.bc == o.prob.bc &&
+           prob.disc == o.prob.disc && prob.bc == o.prob.bc && pi_a == pi_b &&
            opts.method == o.opts.method && opts.precision == o.opts.precision &&
            opts.restart == o.opts.restart && opts.flexible == o.opts.flexible &&
            opts.lowrank == o.opts.lowrank && aface.empty() == o.aface.empty();

@@ -206,3 +206,29 @@ def test_retarget_matches_fresh_plan(env, coeff):
     with pytest.raises(wc.WcError):
         plan.retarget(theta=0.5, gamma=1e-4, a_face=None if coeff == "sin" else
                       datagen.sinusoidal_a(dims, M))
+
+
+def test_plan_reuse_across_zeta(env):
+    """Requests of one shape at zeta = pi and zeta = 1 take different preconditioner paths
+    (the half-spectrum FFT path and the general path), so the idle plan of the first is not
+    retargeted to the second: both succeed, and the second equals its standalone solve."""
+    torch, wc = env
+    dims, M, n = 2, 31, 32
+    kw, f, g, y0, m = make_request(torch, 7, (dims, M, n, 0.5, 1e-4, "gmres_ps", "fp64", "const"))
+    print("server zeta pi then zeta 1", dims, M, n, flush=True)
+    srv = wc.Server(hbm_budget=0, max_concurrency=1)
+    outs = [(torch.empty(n * m, dtype=torch.float64, device="cuda"),
+             torch.empty(n * m, dtype=torch.float64, device="cuda")) for _ in range(2)]
+    r0 = srv.wait(srv.submit(f, g, y0, *outs[0], **kw))
+    r1 = srv.wait(srv.submit(f, g, y0, *outs[1], **dict(kw, zeta=1.0)))
+    srv.close()
+    assert r0[0].status == wc.WC_OK and r1[0].status == wc.WC_OK
+    assert r1[0].relres <= 1e-8
+    plan = wc.Plan(**dict(kw, zeta=1.0))
+    y = torch.empty(n * m, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(y)
+    info = plan.solve(f, g, y0, y, p)
+    torch.cuda.synchronize()
+    assert info.iters == r1[0].iters
+    assert np.array_equal(y.cpu().numpy(), outs[1][0].cpu().numpy())
+    assert np.array_equal(p.cpu().numpy(), outs[1][1].cpu().numpy())
